@@ -1,0 +1,395 @@
+/*
+ * agn_oracle.c -- plain FP64 CPU oracle for the light-curve generator of
+ * Sartori et al. (2019), arXiv:1909.06374 (Sec. 2.1, Sec. 3.1, Sec. 3.2.2,
+ * Eqs. 3, 4, A1, A2), which runs the Emmanoulopoulos et al. (2013) iteration
+ * (a Timmer & Koenig (1995) random spectrum, then repeated amplitude
+ * replacement in Fourier space and rank-order substitution of the PDF draw).
+ *
+ * TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark are the only users.  It shares nothing
+ * with the GPU library.
+ *
+ * Style: each step is the textbook definition, written out with no blocking,
+ * fusion or reordering; speed is not a goal.
+ *
+ * Readings taken where the paper is silent (they are listed in the design
+ * notes as well):
+ *  - TK95 moduli: only the Fourier moduli of the TK95 spectrum are kept by
+ *    the iteration (Sec. 2.1), so each interior bin's modulus is drawn as
+ *    sqrt(P_j * E), E ~ Exp(1) = -ln U, which equals |sqrt(P/2)(g1 + i g2)| in
+ *    distribution.  The Nyquist bin is real: sqrt(P/2)|g|, g by Box-Muller.
+ *    The DC bin is 0.
+ *  - Forward DFT uses exp(-2 pi i jk/N) and the inverse exp(+...); Eq. A1
+ *    prints the opposite sign, which only conjugates both spectra and leaves
+ *    the real output unchanged.
+ *  - The inverse DFT is unnormalised (a positive scale does not change ranks).
+ *  - A zero-modulus bin takes phase 0; the Nyquist bin keeps the sign of its
+ *    real part (sign(0) = +1).
+ *  - Eq. 4's log is log10 and rms is over all N samples.
+ *  - Ties in the sort break by time index; -0 and +0 are equal.
+ */
+#include "agn_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define E_OK 0
+#define E_INVAL (-1)
+#define E_SIZE (-2)
+#define E_NOMEM (-3)
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as  */
+/* easy as 1, 2, 3", SC'11): 10 rounds of two 64x64->128 multiplications,   */
+/* with a Weyl-sequence key schedule.                                        */
+/* ------------------------------------------------------------------------ */
+static const uint64_t PHILOX_M0 = 0xD2E7470EE14C6C93ULL;
+static const uint64_t PHILOX_M1 = 0xCA5A826395121157ULL;
+static const uint64_t PHILOX_W0 = 0x9E3779B97F4A7C15ULL; /* golden ratio */
+static const uint64_t PHILOX_W1 = 0xBB67AE8584CAA73BULL; /* sqrt(3) - 1 */
+
+void agn_oracle_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        unsigned __int128 p0 = (unsigned __int128)PHILOX_M0 * c0;
+        unsigned __int128 p1 = (unsigned __int128)PHILOX_M1 * c2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        uint64_t n0 = hi1 ^ c1 ^ k0;
+        uint64_t n1 = lo1;
+        uint64_t n2 = hi0 ^ c3 ^ k1;
+        uint64_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Stream layout: key = (seed, stream << 32 | curve_id), counter = (k / 4, 0, 0, 0),
+ * uniform #k is word k % 4.  A 64-bit word w maps to ((w >> 12) + 1/2) 2^-52, which
+ * is exact in FP64 and lies in [2^-53, 1 - 2^-53]. */
+double agn_oracle_uniform(uint64_t seed, uint32_t stream, uint32_t curve_id, uint64_t k)
+{
+    uint64_t key[2] = {seed, ((uint64_t)stream << 32) | (uint64_t)curve_id};
+    uint64_t ctr[4] = {k / 4, 0, 0, 0};
+    uint64_t out[4];
+    agn_oracle_philox4x64(ctr, key, out);
+    uint64_t w = out[k % 4];
+    return ((double)(w >> 12) + 0.5) * 0x1.0p-52;
+}
+
+/* ------------------------------------------------------------------------ */
+/* PSD, Eq. 3, on the Fourier grid f_j = j / (N dt) of Appendix A.           */
+/* ------------------------------------------------------------------------ */
+double agn_oracle_psd_eq3(double f, double A, double f_br, double a_low, double a_high)
+{
+    double r = f / f_br;
+    return A / (pow(r, a_low) + pow(r, a_high));
+}
+
+static int valid_n(int64_t n)
+{
+    if (n < 1) return 0;
+    int64_t m = n;
+    while (m % 2 == 0) m /= 2;
+    while (m % 3 == 0) m /= 3;
+    return m == 1;
+}
+
+double agn_oracle_psd_norm(const agn_oracle_psd_params* p, int64_t n, double dt)
+{
+    if (p->norm > 0.0) return p->norm;
+    /* Unit expected variance of the (1/N-normalised) TK95 series:
+     * Var = (1/N^2) [ 2 sum_{j=1}^{N/2-1} P_j + P_{N/2} / 2 ]. */
+    double s = 0.0;
+    for (int64_t j = 1; j < n / 2; ++j)
+        s += 2.0 * agn_oracle_psd_eq3((double)j / ((double)n * dt), 1.0, p->f_br, p->a_low, p->a_high);
+    s += 0.5 * agn_oracle_psd_eq3(0.5 / dt, 1.0, p->f_br, p->a_low, p->a_high);
+    return (double)n * (double)n / s;
+}
+
+static int valid_params(const agn_oracle_psd_params* p, double dt)
+{
+    if (!(dt > 0.0) || !isfinite(dt)) return 0;
+    if (!(p->f_br > 0.0) || !isfinite(p->f_br)) return 0;
+    if (!isfinite(p->a_low) || !isfinite(p->a_high) || !isfinite(p->norm)) return 0;
+    return 1;
+}
+
+int agn_oracle_psd_spectrum(const agn_oracle_psd_params* p, int64_t n, double dt,
+                            uint64_t seed, uint32_t curve_id, double* amp)
+{
+    if (!p || !amp) return E_INVAL;
+    if (n < 2 || n % 2 != 0 || !valid_n(n)) return E_SIZE;
+    if (!valid_params(p, dt)) return E_INVAL;
+    double A = agn_oracle_psd_norm(p, n, dt);
+    int64_t h = n / 2;
+    amp[0] = 0.0;
+    for (int64_t j = 1; j < h; ++j) {
+        double P = agn_oracle_psd_eq3((double)j / ((double)n * dt), A, p->f_br, p->a_low, p->a_high);
+        double U = agn_oracle_uniform(seed, 0, curve_id, (uint64_t)j);
+        amp[j] = sqrt(P * (-log(U)));
+    }
+    {
+        double P = agn_oracle_psd_eq3(0.5 / dt, A, p->f_br, p->a_low, p->a_high);
+        double Ua = agn_oracle_uniform(seed, 0, curve_id, (uint64_t)h);
+        double Ub = agn_oracle_uniform(seed, 0, curve_id, (uint64_t)h + 1);
+        double g = sqrt(-2.0 * log(Ua)) * cos(2.0 * M_PI * Ub);
+        amp[h] = sqrt(0.5 * P) * fabs(g);
+    }
+    return E_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* DFT: recursive mixed-radix (2, 3) Cooley-Tukey, decimation in time.       */
+/* X[k] = sum_r W_n^{rk} F_r[k mod m], F_r = DFT_m of x[p t + r].            */
+/* Each twiddle is cos/sin of 2 pi ((r k) mod n) / n, computed directly.     */
+/* ------------------------------------------------------------------------ */
+static int dft_rec(const double* x, int64_t stride, int64_t n, int sign, double* X)
+{
+    if (n == 1) {
+        X[0] = x[0];
+        X[1] = x[1];
+        return E_OK;
+    }
+    int64_t p = (n % 2 == 0) ? 2 : 3;
+    int64_t m = n / p;
+    double* F = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    if (!F) return E_NOMEM;
+    for (int64_t r = 0; r < p; ++r) {
+        int rc = dft_rec(x + 2 * stride * r, stride * p, m, sign, F + 2 * m * r);
+        if (rc) { free(F); return rc; }
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        double re = 0.0, im = 0.0;
+        for (int64_t r = 0; r < p; ++r) {
+            double ang = (double)sign * 2.0 * M_PI * (double)((r * k) % n) / (double)n;
+            double wr = cos(ang), wi = sin(ang);
+            double fr = F[2 * (m * r + k % m)], fi = F[2 * (m * r + k % m) + 1];
+            re += wr * fr - wi * fi;
+            im += wr * fi + wi * fr;
+        }
+        X[2 * k] = re;
+        X[2 * k + 1] = im;
+    }
+    free(F);
+    return E_OK;
+}
+
+int agn_oracle_dft(double* data, int64_t n, int sign)
+{
+    if (!data) return E_INVAL;
+    if (!valid_n(n)) return E_SIZE;
+    if (sign != 1 && sign != -1) return E_INVAL;
+    double* out = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    if (!out) return E_NOMEM;
+    int rc = dft_rec(data, 1, n, sign, out);
+    if (!rc) memcpy(data, out, sizeof(double) * 2 * (size_t)n);
+    free(out);
+    return rc;
+}
+
+int agn_oracle_rfft(const double* x, int64_t n, double* X)
+{
+    if (!x || !X) return E_INVAL;
+    if (n < 2 || n % 2 != 0 || !valid_n(n)) return E_SIZE;
+    double* z = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    if (!z) return E_NOMEM;
+    for (int64_t i = 0; i < n; ++i) {
+        z[2 * i] = x[i];
+        z[2 * i + 1] = 0.0;
+    }
+    int rc = agn_oracle_dft(z, n, -1);
+    if (!rc) memcpy(X, z, sizeof(double) * 2 * (size_t)(n / 2 + 1));
+    free(z);
+    return rc;
+}
+
+/* Real part of the unnormalised inverse DFT of the Hermitian extension
+ * Z[k] = Y[k] (k <= n/2), Z[n-k] = conj(Y[k]) (0 < k < n/2). */
+int agn_oracle_irfft(const double* Y, int64_t n, double* y)
+{
+    if (!Y || !y) return E_INVAL;
+    if (n < 2 || n % 2 != 0 || !valid_n(n)) return E_SIZE;
+    double* z = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    if (!z) return E_NOMEM;
+    int64_t h = n / 2;
+    for (int64_t k = 0; k <= h; ++k) {
+        z[2 * k] = Y[2 * k];
+        z[2 * k + 1] = Y[2 * k + 1];
+    }
+    for (int64_t k = 1; k < h; ++k) {
+        z[2 * (n - k)] = Y[2 * k];
+        z[2 * (n - k) + 1] = -Y[2 * k + 1];
+    }
+    int rc = agn_oracle_dft(z, n, +1);
+    if (!rc)
+        for (int64_t i = 0; i < n; ++i) y[i] = z[2 * i];
+    free(z);
+    return rc;
+}
+
+/* Amplitude replacement (Sec. 2.1, Sec. 3.2.2): keep the phase of X, take the
+ * modulus from amp.  DC -> 0; Nyquist -> amp * sign(Re X) with sign(0) = +1;
+ * a zero-modulus bin takes phase 0. */
+int agn_oracle_replace(const double* X, const double* amp, int64_t n, double* Y)
+{
+    if (!X || !amp || !Y) return E_INVAL;
+    if (n < 2 || n % 2 != 0) return E_SIZE;
+    int64_t h = n / 2;
+    for (int64_t j = 1; j < h; ++j) {
+        double re = X[2 * j], im = X[2 * j + 1];
+        double mod = sqrt(re * re + im * im);
+        if (mod == 0.0) {
+            Y[2 * j] = amp[j];
+            Y[2 * j + 1] = 0.0;
+        } else {
+            Y[2 * j] = amp[j] * (re / mod);
+            Y[2 * j + 1] = amp[j] * (im / mod);
+        }
+    }
+    {
+        double re = X[2 * h];
+        Y[2 * h] = (re >= 0.0) ? amp[h] : -amp[h];
+        Y[2 * h + 1] = 0.0;
+    }
+    Y[0] = 0.0;
+    Y[1] = 0.0;
+    return E_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stable ascending argsort.  The comparator orders (value, index) pairs, a  */
+/* total order, so the unstable library sort returns the stable result.      */
+/* ------------------------------------------------------------------------ */
+static _Thread_local const double* g_sort_keys;
+
+static int cmp_idx(const void* a, const void* b)
+{
+    uint32_t ia = *(const uint32_t*)a, ib = *(const uint32_t*)b;
+    double ya = g_sort_keys[ia], yb = g_sort_keys[ib];
+    if (ya < yb) return -1;
+    if (ya > yb) return 1;
+    return (ia < ib) ? -1 : (ia > ib) ? 1 : 0;
+}
+
+int agn_oracle_argsort(const double* y, int64_t n, uint32_t* perm)
+{
+    if (!y || !perm) return E_INVAL;
+    if (n < 0 || n > (int64_t)0xFFFFFFFFLL) return E_SIZE;
+    for (int64_t i = 0; i < n; ++i)
+        if (isnan(y[i])) return E_INVAL;
+    for (int64_t i = 0; i < n; ++i) perm[i] = (uint32_t)i;
+    g_sort_keys = y;
+    qsort(perm, (size_t)n, sizeof(uint32_t), cmp_idx);
+    g_sort_keys = NULL;
+    return E_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The iteration (Sec. 2.1, Sec. 3.2.2):                                     */
+/*   s      = PDF draw sorted ascending (values fixed for the whole run)     */
+/*   x_0    = PDF draw in draw order                                         */
+/*   y      = IDFT(replace(DFT(x_{i-1}), amp))                               */
+/*   x_i    = s placed in the rank order of y                                */
+/*   delta_i = rms_n log10(x_i[n] / x_{i-1}[n])            (Eq. 4)            */
+/* Stopping: tol < 0 runs all iterations; tol >= 0 stops after the first     */
+/* iteration that reaches an exact fixed point, or (tol > 0) delta_i <= tol. */
+/* ------------------------------------------------------------------------ */
+int agn_oracle_iterate(const double* amp, const double* x0, int64_t n, int32_t iters,
+                       double tol, double* x_out, double* delta_out, int32_t* iters_done,
+                       uint32_t* rank_out)
+{
+    if (!amp || !x0 || !x_out) return E_INVAL;
+    if (n < 2 || n % 2 != 0 || !valid_n(n) || n > ((int64_t)1 << 31)) return E_SIZE;
+    if (iters < 0) return E_INVAL;
+    for (int64_t i = 0; i < n; ++i)
+        if (!(x0[i] > 0.0) || !isfinite(x0[i])) return E_INVAL;
+
+    int64_t h = n / 2;
+    double* s = (double*)malloc(sizeof(double) * (size_t)n);
+    double* xp = (double*)malloc(sizeof(double) * (size_t)n);
+    double* xn = (double*)malloc(sizeof(double) * (size_t)n);
+    double* y = (double*)malloc(sizeof(double) * (size_t)n);
+    double* X = (double*)malloc(sizeof(double) * 2 * (size_t)(h + 1));
+    uint32_t* perm = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
+    int rc = E_OK;
+    if (!s || !xp || !xn || !y || !X || !perm) { rc = E_NOMEM; goto done; }
+
+    rc = agn_oracle_argsort(x0, n, perm);
+    if (rc) goto done;
+    for (int64_t k = 0; k < n; ++k) s[k] = x0[perm[k]];
+    if (rank_out)
+        for (int64_t k = 0; k < n; ++k) rank_out[perm[k]] = (uint32_t)k;
+    memcpy(xp, x0, sizeof(double) * (size_t)n);
+    if (delta_out)
+        for (int32_t i = 0; i < iters; ++i) delta_out[i] = 0.0;
+
+    int32_t done_count = 0;
+    for (int32_t it = 0; it < iters; ++it) {
+        if ((rc = agn_oracle_rfft(xp, n, X))) goto done;
+        if ((rc = agn_oracle_replace(X, amp, n, X))) goto done;
+        if ((rc = agn_oracle_irfft(X, n, y))) goto done;
+        if ((rc = agn_oracle_argsort(y, n, perm))) goto done;
+        for (int64_t k = 0; k < n; ++k) xn[perm[k]] = s[k];
+        if (rank_out)
+            for (int64_t k = 0; k < n; ++k) rank_out[perm[k]] = (uint32_t)k;
+
+        double acc = 0.0;
+        int same = 1;
+        for (int64_t i = 0; i < n; ++i) {
+            double l = log10(xn[i] / xp[i]);
+            acc += l * l;
+            if (xn[i] != xp[i]) same = 0;
+        }
+        double delta = sqrt(acc / (double)n);
+        if (delta_out) delta_out[it] = delta;
+        memcpy(xp, xn, sizeof(double) * (size_t)n);
+        done_count = it + 1;
+        if (tol >= 0.0 && (same || (tol > 0.0 && delta <= tol))) break;
+    }
+    memcpy(x_out, xp, sizeof(double) * (size_t)n);
+    if (iters_done) *iters_done = done_count;
+
+done:
+    free(s); free(xp); free(xn); free(y); free(X); free(perm);
+    return rc;
+}
+
+int agn_oracle_generate(const agn_oracle_psd_params* p, const double* erdf, int64_t n,
+                        double dt, int32_t iters, double tol, uint64_t seed,
+                        uint32_t curve_id, double* x_out, double* delta_out,
+                        int32_t* iters_done, uint32_t* rank_out)
+{
+    if (!p || !erdf || !x_out) return E_INVAL;
+    if (n < 2 || n % 2 != 0 || !valid_n(n)) return E_SIZE;
+    double* amp = (double*)malloc(sizeof(double) * (size_t)(n / 2 + 1));
+    if (!amp) return E_NOMEM;
+    int rc = agn_oracle_psd_spectrum(p, n, dt, seed, curve_id, amp);
+    if (!rc)
+        rc = agn_oracle_iterate(amp, erdf, n, iters, tol, x_out, delta_out, iters_done, rank_out);
+    free(amp);
+    return rc;
+}
+
+/* Periodogram, Eq. A2 (Appendix A): P(f_j) = 2 / N^2 |DFT(f_j)|^2, j = 0..N/2. */
+int agn_oracle_periodogram(const double* x, int64_t n, double* P)
+{
+    if (!x || !P) return E_INVAL;
+    if (n < 2 || n % 2 != 0 || !valid_n(n)) return E_SIZE;
+    int64_t h = n / 2;
+    double* X = (double*)malloc(sizeof(double) * 2 * (size_t)(h + 1));
+    if (!X) return E_NOMEM;
+    int rc = agn_oracle_rfft(x, n, X);
+    if (!rc)
+        for (int64_t j = 0; j <= h; ++j)
+            P[j] = 2.0 / ((double)n * (double)n) * (X[2 * j] * X[2 * j] + X[2 * j + 1] * X[2 * j + 1]);
+    free(X);
+    return rc;
+}

@@ -1,0 +1,82 @@
+/*
+ * agn_oracle.h -- plain FP64 CPU oracle for the Emmanoulopoulos-style
+ * light-curve iteration of Sartori et al. (2019), arXiv:1909.06374.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously correct
+ * statement of what the GPU path computes.  It shares no code, header,
+ * table or constant generator with the HIP library.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.
+ *
+ * Everything is host memory, double precision, single threaded.
+ * Every function returns 0 on success and a negative code on bad input.
+ */
+#ifndef AGN_ORACLE_H
+#define AGN_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Eq. 3 parameters.  norm <= 0 selects the unit-variance normalisation. */
+typedef struct {
+    double norm;
+    double f_br;
+    double a_low;
+    double a_high;
+} agn_oracle_psd_params;
+
+/* Philox4x64-10 block function (Salmon et al., SC'11). */
+void agn_oracle_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* Uniform number #k of stream `stream` for (seed, curve_id); value in (0, 1). */
+double agn_oracle_uniform(uint64_t seed, uint32_t stream, uint32_t curve_id, uint64_t k);
+
+/* Eq. 3 at frequency f with the given amplitude A. */
+double agn_oracle_psd_eq3(double f, double A, double f_br, double a_low, double a_high);
+
+/* Amplitude A actually used for a length-n grid (norm, or the unit-variance value). */
+double agn_oracle_psd_norm(const agn_oracle_psd_params* p, int64_t n, double dt);
+
+/* Timmer-Koenig Fourier moduli, amp[0..n/2]. */
+int agn_oracle_psd_spectrum(const agn_oracle_psd_params* p, int64_t n, double dt,
+                            uint64_t seed, uint32_t curve_id, double* amp);
+
+/* Complex DFT of length n (n = 2^a 3^b), unnormalised.  sign = -1 forward, +1 inverse.
+ * data is interleaved (re, im), in place. */
+int agn_oracle_dft(double* data, int64_t n, int sign);
+
+/* Real forward DFT: x[n] -> X[n/2+1] interleaved complex. */
+int agn_oracle_rfft(const double* x, int64_t n, double* X);
+
+/* Unnormalised inverse real DFT of a Hermitian half spectrum: Y[n/2+1] -> y[n]. */
+int agn_oracle_irfft(const double* Y, int64_t n, double* y);
+
+/* Fourier amplitude replacement keeping phases (in: X, amp; out: Y; may alias X). */
+int agn_oracle_replace(const double* X, const double* amp, int64_t n, double* Y);
+
+/* Stable ascending argsort of y (ties by index; -0 equals +0).  perm[k] = index of
+ * the k-th smallest. */
+int agn_oracle_argsort(const double* y, int64_t n, uint32_t* perm);
+
+/* Iterate from x0 (the PDF draw, in draw order) with target moduli amp.
+ * x_out[n]: final series; delta_out[iters] (nullable); iters_done (nullable);
+ * rank_out[n] (nullable): rank of each time sample in the sorted draw. */
+int agn_oracle_iterate(const double* amp, const double* x0, int64_t n, int32_t iters,
+                       double tol, double* x_out, double* delta_out, int32_t* iters_done,
+                       uint32_t* rank_out);
+
+/* Spectrum + iterate. */
+int agn_oracle_generate(const agn_oracle_psd_params* p, const double* erdf, int64_t n,
+                        double dt, int32_t iters, double tol, uint64_t seed,
+                        uint32_t curve_id, double* x_out, double* delta_out,
+                        int32_t* iters_done, uint32_t* rank_out);
+
+/* Periodogram, Eq. A2: P[j] = 2/n^2 |DFT_j|^2 for j = 0..n/2. */
+int agn_oracle_periodogram(const double* x, int64_t n, double* P);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,122 @@
+"""Pins of the oracle's random numbers, Eq. 3 and the Timmer-Koenig moduli.
+
+Each check compares the oracle with something other than itself: numpy's
+independent Philox4x64-10, closed forms of Eq. 3, the variance of series
+built with numpy's inverse FFT, and the Exp(1) / chi^2_1 laws of the moduli.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+
+
+def numpy_philox_block(key, block):
+    """Block `block` of Philox4x64-10 under `key` from numpy's implementation.
+    numpy increments the counter before each block, so start one below."""
+    ctr = (block - 1) % (2**256)
+    words = [(ctr >> (64 * i)) & (2**64 - 1) for i in range(4)]
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(words, dtype=np.uint64))
+    return [int(v) for v in bg.random_raw(4)]
+
+
+@pytest.mark.parametrize("key", [(0, 0), (12345, 678), (2**64 - 1, 2**63 + 5), (0xDEADBEEF, 3 << 32 | 17)])
+def test_philox_matches_numpy(key):
+    for block in [0, 1, 2, 7, 1000, 2**40 + 3]:
+        assert oracle.philox4x64([block, 0, 0, 0], key) == numpy_philox_block(key, block)
+
+
+def test_uniform_stream_layout_and_mapping():
+    for seed, stream, curve in [(0, 0, 0), (7, 1, 3), (2**63 + 11, 0, 1023)]:
+        key = (seed, (stream << 32) | curve)
+        for k in [0, 1, 2, 3, 4, 5, 1023, 4097]:
+            w = numpy_philox_block(key, k // 4)[k % 4]
+            expect = ((w >> 12) + 0.5) * 2.0**-52
+            assert oracle.uniform(seed, stream, curve, k) == expect
+            assert 0.0 < expect < 1.0
+
+
+def test_uniforms_are_uniform():
+    u = np.array([oracle.uniform(3, 0, 5, k) for k in range(20000)])
+    assert stats.kstest(u, "uniform").pvalue > 1e-3
+
+
+def test_eq3_closed_forms():
+    A, fb = 3.7, 0.01
+    # At the break both terms are 1.
+    assert oracle.psd_eq3(fb, A, fb, 1.0, 2.5) == pytest.approx(A / 2, rel=1e-15)
+    # Equal slopes: a single power law of half the amplitude.
+    for f in [1e-4, 3e-3, 0.2]:
+        assert oracle.psd_eq3(f, A, fb, 1.7, 1.7) == pytest.approx(0.5 * A * (f / fb) ** -1.7, rel=1e-14)
+    # Asymptotes.
+    assert oracle.psd_eq3(fb * 1e-6, A, fb, 1.0, 2.0) / (A * 1e6) == pytest.approx(1.0, rel=2e-6)
+    assert oracle.psd_eq3(fb * 1e6, A, fb, 1.0, 2.0) / (A * 1e-12) == pytest.approx(1.0, rel=2e-6)
+    # The bending form A f^-1 / (1 + (f/f_b)^1.5) is Eq. 3 with slopes (1, 2.5).
+    for f in [1e-4, 5e-3, 0.1, 0.5]:
+        bend = A * (fb / f) / (1.0 + (f / fb) ** 1.5)
+        assert oracle.psd_eq3(f, A, fb, 1.0, 2.5) == pytest.approx(bend, rel=1e-13)
+
+
+def test_norm_gives_unit_variance_series():
+    """TK95 series built with numpy (complex Gaussians of variance P/2 per
+    component, real Nyquist, zero DC, numpy's inverse FFT) have unit mean
+    variance under the oracle's normalisation."""
+    n, dt = 512, 1.0
+    p = oracle.psd_params(0.0, 1 / 50.0, 1.0, 2.0)
+    A = oracle.psd_norm(p, n, dt)
+    j = np.arange(1, n // 2 + 1)
+    P = np.array([oracle.psd_eq3(jj / (n * dt), A, p.f_br, p.a_low, p.a_high) for jj in j])
+    rng = np.random.default_rng(0)
+    R = 4000
+    X = np.zeros((R, n // 2 + 1), dtype=complex)
+    X[:, 1:] = np.sqrt(P / 2) * (rng.standard_normal((R, n // 2)) + 1j * rng.standard_normal((R, n // 2)))
+    X[:, -1] = np.sqrt(P[-1] / 2) * rng.standard_normal(R)
+    x = np.fft.irfft(X, n, axis=1)
+    v = (x ** 2).mean(axis=1)
+    assert abs(v.mean() - 1.0) < 4 * v.std() / math.sqrt(R)
+
+
+def test_tk95_moduli_laws():
+    n, dt = 2**16, 1.0
+    p = oracle.psd_params(0.0, 1 / 300.0, 1.2, 2.7)
+    A = oracle.psd_norm(p, n, dt)
+    amp = oracle.psd_spectrum(p, n, dt, seed=11, curve_id=2)
+    assert amp[0] == 0.0
+    j = np.arange(1, n // 2)
+    P = np.array([oracle.psd_eq3(jj / (n * dt), A, p.f_br, p.a_low, p.a_high) for jj in j])
+    e = amp[1:n // 2] ** 2 / P
+    assert stats.kstest(e, "expon").pvalue > 1e-3
+    assert abs(e.mean() - 1.0) < 4 / math.sqrt(len(e))
+    # Nyquist bin: amp^2 / (P/2) ~ chi^2 with one degree of freedom.
+    m = 6
+    Pn = oracle.psd_eq3(0.5 / dt, oracle.psd_norm(p, m, dt), p.f_br, p.a_low, p.a_high)
+    ny = np.array([oracle.psd_spectrum(p, m, dt, seed=s, curve_id=0)[m // 2] for s in range(3000)])
+    assert stats.kstest(ny ** 2 / (Pn / 2), "chi2", args=(1,)).pvalue > 1e-3
+    # Expected sum of squared moduli gives unit variance (normalisation).
+    tot = []
+    for s in range(200):
+        a = oracle.psd_spectrum(p, 256, dt, seed=s, curve_id=0)
+        tot.append((2 * (a[1:128] ** 2).sum() + a[128] ** 2) / 256**2)
+    tot = np.array(tot)
+    assert abs(tot.mean() - 1.0) < 4 * tot.std() / math.sqrt(len(tot))
+
+
+def test_tk95_seed_and_curve_streams_differ():
+    p = oracle.psd_params(0.0, 0.01, 1.0, 2.0)
+    a = oracle.psd_spectrum(p, 64, 1.0, seed=1, curve_id=0)
+    b = oracle.psd_spectrum(p, 64, 1.0, seed=1, curve_id=1)
+    c = oracle.psd_spectrum(p, 64, 1.0, seed=2, curve_id=0)
+    d = oracle.psd_spectrum(p, 64, 1.0, seed=1, curve_id=0)
+    assert np.array_equal(a, d)
+    assert not np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+def test_spectrum_rejects_bad_input():
+    p = oracle.psd_params(0.0, 0.01, 1.0, 2.0)
+    for n in [0, 3, 10, 14]:
+        with pytest.raises(oracle.OracleError):
+            oracle.psd_spectrum(p, n, 1.0, 0)
+    with pytest.raises(oracle.OracleError):
+        oracle.psd_spectrum(oracle.psd_params(0.0, -1.0, 1.0, 2.0), 8, 1.0, 0)
