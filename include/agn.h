@@ -1,0 +1,205 @@
+/*
+ * agn.h -- C ABI of the MI355X (gfx950) light-curve generator.
+ *
+ * The library generates light curves with a prescribed power spectral density
+ * (Eq. 3 of Sartori et al. 2019, arXiv:1909.06374) and a prescribed
+ * distribution of values (a sample of the Eddington-ratio distribution, the
+ * PDF draw of Sec. 2.1), using the Emmanoulopoulos et al. (2013) iteration
+ * that the paper adopts (Sec. 2.1, Sec. 3.1, Sec. 3.2.2):
+ *
+ *   1. draw a Timmer & Koenig (1995) random spectrum for the PSD; only its
+ *      Fourier moduli are kept (agn_psd_spectrum);
+ *   2. start from the PDF draw in draw order;
+ *   3. repeat: forward real FFT, replace the Fourier moduli by the target
+ *      moduli keeping the phases, inverse real FFT, rank the result, and put
+ *      the sorted PDF draw into that rank order (agn_lc_iterate);
+ *   4. record the convergence distance of Eq. 4 after every iteration.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Device pointers are HIP device memory owned by the caller (for example
+ *    torch tensors' data_ptr()).  The library never frees or retains them
+ *    after the enqueued work completes.  Host pointers are read before the
+ *    call returns.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Every
+ *    call is stream ordered and returns without synchronising the host;
+ *    outputs are valid once the stream has completed the work.
+ *  - `ws` is a caller-owned device workspace of at least the size reported
+ *    by the matching *_workspace_size call; its contents on entry do not
+ *    matter.  Calls that overlap in time must not share a workspace.
+ *  - Return value: AGN_OK or a negative agn_status.  All argument checks
+ *    happen on the host before anything is enqueued; on error nothing is
+ *    enqueued and agn_last_error() describes the problem.
+ *  - Supported lengths: n even, n = 2^a or 3 * 2^a, 2 <= n <= 2^27.
+ *  - PDF draw values must be finite and > 0 (Eq. 4 takes logarithms).  This
+ *    is checked on the device: an invalid draw sets *iters_done = -1 and the
+ *    outputs of that curve are unspecified.
+ *  - Determinism: identical inputs give bit-identical outputs; the kernels
+ *    chosen depend only on (n, precision), never on batch composition.
+ *
+ * Precision
+ * ---------
+ *  AGN_FP64: every step in double precision (the plain method).
+ *  AGN_FP32: FFTs, moduli and sort keys in single precision, twiddle tables
+ *            generated in double and rounded once, convergence sums in
+ *            double.  The output values are always the caller's double
+ *            precision PDF draw, only reordered.
+ */
+#ifndef AGN_H
+#define AGN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct agn_ctx agn_ctx;
+
+/* PSD parameters of Eq. 3: PSD(f) = norm / ((f/f_br)^a_low + (f/f_br)^a_high).
+ * f and f_br are in cycles per unit of dt.  norm <= 0 selects the value of
+ * norm that gives the Timmer-Koenig series unit expected variance:
+ * norm = N^2 / (2 sum_{j=1}^{N/2-1} P~_j + P~_{N/2} / 2), P~ = Eq. 3 with norm 1.
+ * The normalisation does not change the output ordering, only the moduli. */
+typedef struct {
+    double norm;
+    double f_br;
+    double a_low;
+    double a_high;
+} agn_psd_params;
+
+typedef enum { AGN_FP64 = 0, AGN_FP32 = 1 } agn_precision;
+
+typedef enum {
+    AGN_OK = 0,
+    AGN_EINVAL = -1,          /* bad pointer, parameter or workspace size */
+    AGN_EUNSUPPORTED_N = -2,  /* n not of the supported form */
+    AGN_ENOMEM = -3,          /* library-owned table allocation failed */
+    AGN_EDEVICE = -4          /* HIP runtime error */
+} agn_status;
+
+/* Context: holds per-(n, precision) twiddle tables on one device.
+ * Created once; the tables are allocated on the first call that needs them. */
+int agn_ctx_create(int device, agn_ctx** out);
+int agn_ctx_destroy(agn_ctx* ctx);
+
+/* Thread-local description of the last error (never NULL). */
+const char* agn_last_error(void);
+
+/* 1 if n is a supported length, else 0. */
+int agn_supported_n(int64_t n);
+
+/* Bytes of workspace for agn_psd_spectrum on one curve of length n. */
+int agn_spectrum_workspace_size(int64_t n, size_t* bytes);
+
+/* Bytes of workspace for agn_lc_iterate / agn_lc_generate on one curve. */
+int agn_workspace_size(int64_t n, agn_precision prec, size_t* bytes);
+
+/* Bytes of workspace for agn_lc_generate_batch; n is a host array. */
+int agn_batch_workspace_size(int32_t n_curves, const int64_t* n, agn_precision prec,
+                             size_t* bytes);
+
+/*
+ * agn_psd_spectrum -- Timmer-Koenig Fourier moduli (Sec. 2.1 step i; Eq. 3 on
+ * the Fourier grid f_j = j / (n dt) of Appendix A).
+ *   amp_out[0]       = 0 (the DC bin; the series has zero mean)
+ *   amp_out[j]       = sqrt(PSD(f_j) * E_j),  E_j = -ln U_j,   0 < j < n/2
+ *   amp_out[n/2]     = sqrt(PSD(f_{n/2}) / 2) * |g|,  g = sqrt(-2 ln U_a) cos(2 pi U_b)
+ * E_j is the squared modulus of a complex Gaussian with variance PSD/2 per
+ * component, divided by PSD; only the moduli matter to the iteration.
+ * Random numbers: Philox4x64-10 with key (seed, 0 << 32 | curve_id),
+ * counter (k / 4, 0, 0, 0); uniform #k = word k % 4 mapped to
+ * ((w >> 12) + 1/2) 2^-52.  Bin j uses uniform #j; the Nyquist bin uses
+ * #(n/2) and #(n/2 + 1).
+ *   p        host, PSD parameters.
+ *   amp_out  device, n/2 + 1 values of float (AGN_FP32) or double (AGN_FP64).
+ *   ws       device workspace of agn_spectrum_workspace_size(n) bytes.
+ */
+int agn_psd_spectrum(agn_ctx* ctx, const agn_psd_params* p, int64_t n, double dt,
+                     uint64_t seed, uint32_t curve_id, agn_precision prec,
+                     void* amp_out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * agn_lc_iterate -- the iteration of Sec. 2.1 / Sec. 3.2.2 from a given start.
+ *   amp        device, n/2 + 1 target moduli (float for AGN_FP32, double for
+ *              AGN_FP64), as produced by agn_psd_spectrum.
+ *   x0         device, n doubles: the PDF draw in draw order (it is also the
+ *              starting series x_0).  s = x0 sorted ascending is the fixed set
+ *              of values; every output is a permutation of it.
+ *   iters      number of iterations (>= 0).
+ *   tol        < 0: run exactly `iters` iterations.  >= 0: stop after the first
+ *              iteration i with x_i == x_{i-1} (an exact fixed point), or, if
+ *              tol > 0, with delta_i <= tol.
+ *   x_out      device, n doubles: x_iters_done.
+ *   delta_out  device, `iters` doubles or NULL: delta_i of Eq. 4,
+ *              sqrt(mean_n (log10 x_i[n] - log10 x_{i-1}[n])^2); entries past
+ *              iters_done are 0.
+ *   iters_done device, one int32 or NULL: iterations performed, -1 if x0 holds
+ *              a value that is not finite and > 0.
+ *   rank_out   device, n uint32 or NULL: rank_out[t] = index into s of x_out[t].
+ * Each iteration: X = rFFT(x_{i-1}); Y_j = amp_j X_j / |X_j| (Y_0 = 0,
+ * Y_{n/2} = amp_{n/2} sign(Re X_{n/2}) with sign(0) = +1, phase 0 where
+ * |X_j| = 0); y = unnormalised inverse rFFT(Y); perm = stable ascending
+ * argsort of y (ties by index, -0 == +0); x_i[perm[k]] = s[k].
+ */
+int agn_lc_iterate(agn_ctx* ctx, const void* amp, const double* x0, int64_t n, int32_t iters,
+                   double tol, agn_precision prec, double* x_out, double* delta_out,
+                   int32_t* iters_done, uint32_t* rank_out, void* ws, size_t ws_bytes,
+                   void* stream);
+
+/*
+ * agn_lc_generate -- agn_psd_spectrum followed by agn_lc_iterate for one curve
+ * (the whole method of Sec. 2.1 for a given PDF draw).  Arguments as above;
+ * erdf is the PDF draw (device, n doubles, draw order).
+ */
+int agn_lc_generate(agn_ctx* ctx, const agn_psd_params* p, const double* erdf, int64_t n,
+                    double dt, int32_t iters, double tol, uint64_t seed, uint32_t curve_id,
+                    agn_precision prec, double* x_out, double* delta_out, int32_t* iters_done,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * agn_lc_generate_batch -- agn_lc_generate for n_curves independent curves of
+ * possibly different lengths in one call.  Per-curve arrays are HOST arrays
+ * of n_curves entries: n, offset (element offset of the curve in erdf and
+ * x_out), p, dt, iters, seed, curve_id.  erdf and x_out are device arrays
+ * holding all curves at their offsets (curves must not overlap).  delta_out
+ * (device, nullable) holds max(iters) doubles per curve, curve c at
+ * c * max(iters); iters_done (device, nullable) one int32 per curve.
+ * Results are bit-identical to n_curves separate agn_lc_generate calls.
+ */
+int agn_lc_generate_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n,
+                          const int64_t* offset, const agn_psd_params* p, const double* dt,
+                          const int32_t* iters, const uint64_t* seed, const uint32_t* curve_id,
+                          const double* erdf, double tol, agn_precision prec, double* x_out,
+                          double* delta_out, int32_t* iters_done, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* ---- instrumentation ----------------------------------------------------- */
+
+/* Turns per-kernel timing on (1) or off (0) for calls made with this context.
+ * While on, every kernel launch is bracketed by two HIP events recorded on
+ * the launch stream. */
+int agn_ctx_set_profiling(agn_ctx* ctx, int on);
+
+/* Synchronises the recorded events and returns, for kernel `name` (one of the
+ * names listed by agn_ctx_kernel_names), the summed duration in milliseconds
+ * and the number of launches since the last reset; reset = 1 clears all
+ * records afterwards.  Unknown name: *total_ms = 0, *launches = 0. */
+int agn_ctx_kernel_time(agn_ctx* ctx, const char* name, double* total_ms, int64_t* launches,
+                        int reset);
+
+/* Comma-separated kernel names the library times. */
+const char* agn_ctx_kernel_names(void);
+
+/* ---- test-only exports (same conventions) ------------------------------- */
+
+/* Philox4x64-10 blocks: out[4 b + w] = word w of block (ctr0 + b) under key
+ * (key0, key1), counter (ctr0 + b, 0, 0, 0), for b < n_blocks.  out: device. */
+int agn_test_philox(uint64_t key0, uint64_t key1, uint64_t ctr0, int64_t n_blocks,
+                    uint64_t* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AGN_H */

@@ -1,0 +1,219 @@
+"""MI355X (gfx950) light-curve generator: Python binding of ``libagn.so``.
+
+The functions below carry the names of the C ABI in ``include/agn.h`` and
+only marshal arguments: every step of the method runs in the HIP kernels of
+the library.  Tensors are torch tensors on the GPU (PyTorch supplies device
+memory and streams); ``stream=None`` means the current torch stream.
+
+Importing this package never falls back to another implementation: if the
+library is not built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libagn.so")
+
+AGN_FP64 = 0
+AGN_FP32 = 1
+AGN_OK = 0
+AGN_EINVAL = -1
+AGN_EUNSUPPORTED_N = -2
+AGN_ENOMEM = -3
+AGN_EDEVICE = -4
+
+_lib = None
+
+
+class AgnError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"agn error {code}: {msg}")
+        self.code = code
+
+
+class agn_psd_params(C.Structure):
+    """Eq. 3 parameters: norm (<= 0: unit variance), f_br, a_low, a_high."""
+    _fields_ = [("norm", C.c_double), ("f_br", C.c_double),
+                ("a_low", C.c_double), ("a_high", C.c_double)]
+
+
+def psd_params(norm=0.0, f_br=1.0, a_low=1.0, a_high=2.0):
+    return agn_psd_params(float(norm), float(f_br), float(a_low), float(a_high))
+
+
+def _declare(lib):
+    i32, i64, u32, u64, d = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
+    vp, sz = C.c_void_p, C.c_size_t
+    pp = C.POINTER(agn_psd_params)
+    lib.agn_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
+    lib.agn_ctx_destroy.argtypes = [vp]
+    lib.agn_last_error.argtypes = []
+    lib.agn_last_error.restype = C.c_char_p
+    lib.agn_supported_n.argtypes = [i64]
+    lib.agn_spectrum_workspace_size.argtypes = [i64, C.POINTER(sz)]
+    lib.agn_workspace_size.argtypes = [i64, C.c_int, C.POINTER(sz)]
+    lib.agn_batch_workspace_size.argtypes = [i32, vp, C.c_int, C.POINTER(sz)]
+    lib.agn_psd_spectrum.argtypes = [vp, pp, i64, d, u64, u32, C.c_int, vp, vp, sz, vp]
+    lib.agn_lc_iterate.argtypes = [vp, vp, vp, i64, i32, d, C.c_int, vp, vp, vp, vp, vp, sz, vp]
+    lib.agn_lc_generate.argtypes = [vp, pp, vp, i64, d, i32, d, u64, u32, C.c_int, vp, vp, vp,
+                                    vp, sz, vp]
+    lib.agn_lc_generate_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_int,
+                                          vp, vp, vp, vp, sz, vp]
+    lib.agn_test_philox.argtypes = [u64, u64, u64, i64, vp, vp]
+    lib.agn_ctx_set_profiling.argtypes = [vp, C.c_int]
+    lib.agn_ctx_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(d), C.POINTER(i64), C.c_int]
+    lib.agn_ctx_kernel_names.argtypes = []
+    lib.agn_ctx_kernel_names.restype = C.c_char_p
+    for f in ("agn_ctx_create", "agn_ctx_destroy", "agn_supported_n", "agn_spectrum_workspace_size",
+              "agn_workspace_size", "agn_batch_workspace_size", "agn_psd_spectrum",
+              "agn_lc_iterate", "agn_lc_generate", "agn_lc_generate_batch", "agn_test_philox",
+              "agn_ctx_set_profiling", "agn_ctx_kernel_time"):
+        getattr(lib, f).restype = C.c_int
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        _lib = C.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+def _check(rc):
+    if rc != AGN_OK:
+        raise AgnError(rc, lib().agn_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """agn_ctx on one device (twiddle tables per length and precision)."""
+
+    def __init__(self, device: int = 0):
+        self.device = int(device)
+        h = C.c_void_p()
+        _check(lib().agn_ctx_create(self.device, C.byref(h)))
+        self.handle = h
+
+    def set_profiling(self, on: bool):
+        _check(lib().agn_ctx_set_profiling(self.handle, 1 if on else 0))
+
+    def kernel_times(self, reset: bool = True):
+        """{kernel name: (total ms, launches)} of the launches timed so far."""
+        out = {}
+        for name in lib().agn_ctx_kernel_names().decode().split(","):
+            ms, cnt = C.c_double(), C.c_int64()
+            _check(lib().agn_ctx_kernel_time(self.handle, name.encode(), C.byref(ms), C.byref(cnt), 0))
+            out[name] = (ms.value, cnt.value)
+        if reset:
+            ms, cnt = C.c_double(), C.c_int64()
+            _check(lib().agn_ctx_kernel_time(self.handle, b"", C.byref(ms), C.byref(cnt), 1))
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().agn_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def agn_supported_n(n: int) -> bool:
+    return bool(lib().agn_supported_n(int(n)))
+
+
+def agn_spectrum_workspace_size(n: int) -> int:
+    b = C.c_size_t()
+    _check(lib().agn_spectrum_workspace_size(int(n), C.byref(b)))
+    return b.value
+
+
+def agn_workspace_size(n: int, prec: int) -> int:
+    b = C.c_size_t()
+    _check(lib().agn_workspace_size(int(n), int(prec), C.byref(b)))
+    return b.value
+
+
+def agn_batch_workspace_size(n, prec: int) -> int:
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    b = C.c_size_t()
+    _check(lib().agn_batch_workspace_size(len(n), n.ctypes.data_as(C.c_void_p), int(prec),
+                                          C.byref(b)))
+    return b.value
+
+
+def agn_psd_spectrum(ctx: Context, params, n, dt, seed, curve_id, prec, amp_out, ws, stream=None):
+    _check(lib().agn_psd_spectrum(ctx.handle, C.byref(params), int(n), float(dt), int(seed),
+                                  int(curve_id), int(prec), _ptr(amp_out), _ptr(ws),
+                                  ws.numel() * ws.element_size(), _stream(stream, ctx.device)))
+
+
+def agn_lc_iterate(ctx: Context, amp, x0, n, iters, tol, prec, x_out, delta_out=None,
+                   iters_done=None, rank_out=None, ws=None, stream=None):
+    _check(lib().agn_lc_iterate(ctx.handle, _ptr(amp), _ptr(x0), int(n), int(iters), float(tol),
+                                int(prec), _ptr(x_out), _ptr(delta_out), _ptr(iters_done),
+                                _ptr(rank_out), _ptr(ws),
+                                0 if ws is None else ws.numel() * ws.element_size(),
+                                _stream(stream, ctx.device)))
+
+
+def agn_lc_generate(ctx: Context, params, erdf, n, dt, iters, tol, seed, curve_id, prec, x_out,
+                    delta_out=None, iters_done=None, ws=None, stream=None):
+    _check(lib().agn_lc_generate(ctx.handle, C.byref(params), _ptr(erdf), int(n), float(dt),
+                                 int(iters), float(tol), int(seed), int(curve_id), int(prec),
+                                 _ptr(x_out), _ptr(delta_out), _ptr(iters_done), _ptr(ws),
+                                 0 if ws is None else ws.numel() * ws.element_size(),
+                                 _stream(stream, ctx.device)))
+
+
+def agn_lc_generate_batch(ctx: Context, n, offset, params, dt, iters, seed, curve_id, erdf, tol,
+                          prec, x_out, delta_out=None, iters_done=None, ws=None, stream=None):
+    """n, offset, dt, iters, seed, curve_id: host sequences; params: sequence of
+    agn_psd_params; erdf, x_out, delta_out, iters_done, ws: GPU tensors."""
+    nc = len(n)
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    offset = np.ascontiguousarray(offset, dtype=np.int64)
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    iters = np.ascontiguousarray(iters, dtype=np.int32)
+    seed = np.ascontiguousarray(seed, dtype=np.uint64)
+    curve_id = np.ascontiguousarray(curve_id, dtype=np.uint32)
+    parr = (agn_psd_params * nc)(*params)
+    vp = C.c_void_p
+    _check(lib().agn_lc_generate_batch(
+        ctx.handle, nc, n.ctypes.data_as(vp), offset.ctypes.data_as(vp), C.cast(parr, vp),
+        dt.ctypes.data_as(vp), iters.ctypes.data_as(vp), seed.ctypes.data_as(vp),
+        curve_id.ctypes.data_as(vp), _ptr(erdf), float(tol), int(prec), _ptr(x_out),
+        _ptr(delta_out), _ptr(iters_done), _ptr(ws),
+        0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, ctx.device)))
+
+
+def agn_test_philox(key0, key1, ctr0, n_blocks, out, stream=None, device=0):
+    _check(lib().agn_test_philox(int(key0) & (2**64 - 1), int(key1) & (2**64 - 1),
+                                 int(ctr0) & (2**64 - 1), int(n_blocks), _ptr(out),
+                                 _stream(stream, device)))

@@ -1,0 +1,211 @@
+// lds_fft.hpp -- complex FFT of length M = 2^a 3^b held in LDS by one
+// workgroup, and the real-to-complex / complex-to-real fold around the
+// Fourier-modulus replacement of the light-curve iteration.
+//
+// Transform: self-sorting (Stockham) passes.  Pass with radix R over the
+// current block size Ns: butterfly j (0 <= j < M/R) reads the R inputs
+// buf[j + r M/R], multiplies input r by W_{Ns R}^{(j mod Ns) r}, takes a
+// length-R DFT and writes output q to buf[(j - j mod Ns) R + j mod Ns + q Ns].
+// After the last pass the data are in natural order.  Every thread owns E
+// complex values (E/R butterflies per pass), so a pass reads all of them into
+// registers, meets the workgroup barrier and then writes in place: one LDS
+// buffer of M values suffices.
+//
+// Twiddles come from a table of W_N^t = exp(-2 pi i t / N), t = 0..N/2, for the
+// real length N = 2M (computed in double on the host, rounded once to T);
+// W_M^u = W_N^{2u}.
+#pragma once
+#include "common.hpp"
+
+namespace agn {
+
+struct FftPlan {
+    int32_t npass;
+    uint8_t radix[20];
+};
+
+// W_N^t for 0 <= t < N from the half table (t <= N/2); inverse = conjugate.
+template <typename T, bool INV>
+AGN_DEV cplx<T> twiddle(const cplx<T>* __restrict__ tw, int t, int halfN) {
+    cplx<T> w;
+    if (t <= halfN) {
+        w = tw[t];
+    } else {
+        cplx<T> u = tw[t - halfN];
+        w = cmk(-u.re, -u.im);
+    }
+    return INV ? cconj(w) : w;
+}
+
+// ---- small DFTs in registers; forward uses exp(-2 pi i / R) ----------------
+template <typename T, bool INV>
+AGN_DEV void dft2(cplx<T>* v) {
+    cplx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <typename T, bool INV>
+AGN_DEV void dft3(cplx<T>* v) {
+    const T c = (T)0.86602540378443864676;  // sqrt(3)/2
+    cplx<T> t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
+    cplx<T> m = cmk(v[0].re - (T)0.5 * t1.re, v[0].im - (T)0.5 * t1.im);
+    // forward: X1 = m - i c t2, X2 = m + i c t2
+    cplx<T> u = cmk(c * t2.im, -c * t2.re);  // -i c t2
+    v[0] = cadd(v[0], t1);
+    if (INV) {
+        v[1] = csub(m, u);
+        v[2] = cadd(m, u);
+    } else {
+        v[1] = cadd(m, u);
+        v[2] = csub(m, u);
+    }
+}
+
+template <typename T, bool INV>
+AGN_DEV void dft4(cplx<T>* v) {
+    cplx<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    cplx<T> s13 = cadd(v[1], v[3]);
+    cplx<T> d13 = cmul_mi<T, INV>(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+}
+
+template <typename T, bool INV>
+AGN_DEV void dft8(cplx<T>* v) {
+    const T h = (T)0.70710678118654752440;
+    cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<T, INV>(e);
+    dft4<T, INV>(o);
+    cplx<T> o1, o3;
+    if (INV) {
+        o1 = cmk(h * (o[1].re - o[1].im), h * (o[1].re + o[1].im));
+        o3 = cmk(-h * (o[3].re + o[3].im), h * (o[3].re - o[3].im));
+    } else {
+        o1 = cmk(h * (o[1].re + o[1].im), h * (o[1].im - o[1].re));
+        o3 = cmk(h * (o[3].im - o[3].re), -h * (o[3].re + o[3].im));
+    }
+    cplx<T> o2 = cmul_mi<T, INV>(o[2]);
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+}
+
+template <typename T, int R, bool INV>
+AGN_DEV void dftR(cplx<T>* v) {
+    if constexpr (R == 2) dft2<T, INV>(v);
+    else if constexpr (R == 3) dft3<T, INV>(v);
+    else if constexpr (R == 4) dft4<T, INV>(v);
+    else if constexpr (R == 8) dft8<T, INV>(v);
+}
+
+// One Stockham pass.  The M/R butterflies are dealt round-robin to the nt
+// threads (at most BMAX per thread); all threads meet both barriers.
+template <typename T, int R, int BMAX, bool INV>
+AGN_DEV void lds_pass(cplx<T>* buf, int M, int Ns, int tid, int nt,
+                      const cplx<T>* __restrict__ tw, int halfN) {
+    cplx<T> v[BMAX][R];
+    const int MR = M / R;
+#pragma unroll
+    for (int b = 0; b < BMAX; ++b) {
+        const int j = tid + b * nt;
+        if (j < MR) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b][r] = buf[j + r * MR];
+        }
+    }
+    __syncthreads();
+    const int tstep = 2 * (M / (Ns * R));
+#pragma unroll
+    for (int b = 0; b < BMAX; ++b) {
+        const int j = tid + b * nt;
+        if (j < MR) {
+            const int jm = j % Ns;
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r)
+                    v[b][r] = cmul(v[b][r], twiddle<T, INV>(tw, jm * r * tstep, halfN));
+            }
+            dftR<T, R, INV>(v[b]);
+            const int d = (j - jm) * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[d + r * Ns] = v[b][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Full transform; E = M / nt complex values per thread (compile-time bound).
+template <typename T, int E, bool INV>
+AGN_DEV void lds_fft(cplx<T>* buf, int M, const FftPlan& plan, int tid, int nt,
+                     const cplx<T>* __restrict__ tw, int halfN) {
+    int Ns = 1;
+    for (int p = 0; p < plan.npass; ++p) {
+        const int R = plan.radix[p];
+        if (R == 8) lds_pass<T, 8, (E + 7) / 8, INV>(buf, M, Ns, tid, nt, tw, halfN);
+        else if (R == 4) lds_pass<T, 4, (E + 3) / 4, INV>(buf, M, Ns, tid, nt, tw, halfN);
+        else if (R == 3) lds_pass<T, 3, (E + 2) / 3, INV>(buf, M, Ns, tid, nt, tw, halfN);
+        else lds_pass<T, 2, (E + 1) / 2, INV>(buf, M, Ns, tid, nt, tw, halfN);
+        Ns *= R;
+    }
+}
+
+// Modulus replacement keeping the phase; zero modulus takes phase 0.
+template <typename T>
+AGN_DEV cplx<T> replace_modulus(cplx<T> X, T a) {
+    T mod = sqrt(X.re * X.re + X.im * X.im);
+    if (mod == (T)0) return cmk(a, (T)0);
+    return cmk(a * (X.re / mod), a * (X.im / mod));
+}
+
+// Z holds FFT_M(z), z[m] = x[2m] + i x[2m+1].  For every Hermitian pair
+// (k, M-k) this forms the real-input spectrum X_k, X_{M-k}, replaces the
+// moduli with amp (DC -> 0, Nyquist -> amp sign(Re X)), and writes back the
+// length-M spectrum whose inverse FFT is y[2m] + i y[2m+1] with
+// y = unnormalised inverse real DFT of Y.
+//   X_k     = E_k + W_N^k O_k,          X_{M-k} = conj(E_k - W_N^k O_k)
+//   E_k     = (Z_k + conj Z_{M-k}) / 2,  O_k = (Z_k - conj Z_{M-k}) / 2i
+//   Z'_k    = A + i conj(W_N^k) B,       Z'_{M-k} = conj(A) + i W_N^k conj(B)
+//   A       = Y_k + conj Y_{M-k},        B = Y_k - conj Y_{M-k}
+template <typename T>
+AGN_DEV void lds_fold_replace(cplx<T>* Z, int M, const T* __restrict__ amp,
+                              const cplx<T>* __restrict__ tw, int tid, int nthreads) {
+    const int half = M / 2;
+    for (int k = tid; k <= half; k += nthreads) {
+        const int mk = (k == 0) ? 0 : M - k;
+        const cplx<T> zk = Z[k], zm = Z[mk];
+        const cplx<T> Ev = cmk((zk.re + zm.re) * (T)0.5, (zk.im - zm.im) * (T)0.5);
+        const cplx<T> Ov = cmk((zk.im + zm.im) * (T)0.5, (zm.re - zk.re) * (T)0.5);
+        const cplx<T> w = tw[k];
+        const cplx<T> wO = cmul(w, Ov);
+        if (k == 0) {
+            const T xn = Ev.re - wO.re;  // X_M, real for real input
+            const T yn = (xn >= (T)0) ? amp[M] : -amp[M];
+            Z[0] = cmk(yn, -yn);
+        } else {
+            const cplx<T> Xk = cadd(Ev, wO);
+            const cplx<T> Xm = cconj(csub(Ev, wO));
+            const cplx<T> Yk = replace_modulus(Xk, amp[k]);
+            const cplx<T> Ym = replace_modulus(Xm, amp[M - k]);
+            const cplx<T> A = cadd(Yk, cconj(Ym));
+            const cplx<T> B = csub(Yk, cconj(Ym));
+            const cplx<T> cwB = cmul(cconj(w), B);
+            Z[k] = cmk(A.re - cwB.im, A.im + cwB.re);  // A + i conj(w) B
+            if (mk != k) {
+                const cplx<T> wcB = cmul(w, cconj(B));
+                Z[mk] = cmk(A.re - wcB.im, -A.im + wcB.re);  // conj(A) + i w conj(B)
+            }
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace agn

@@ -1,0 +1,234 @@
+// lds_iterate.hpp -- the light-curve iteration (Sec. 2.1, Sec. 3.2.2) for a
+// curve that fits in one workgroup's LDS: the whole loop runs inside one
+// kernel, one workgroup per curve, and HBM is touched only to read the fixed
+// per-curve tables (sorted draw, its log10, target moduli, twiddles) and to
+// write the result.
+//
+// Per iteration, inside LDS:
+//   forward FFT of z[m] = x[2m] + i x[2m+1]  ->  fold to the real spectrum,
+//   replace moduli, unfold  ->  inverse FFT gives y  ->  block radix sort of
+//   (key(y[n]), n)  ->  for sorted position k holding sample n:
+//   rank[n] = k, x[n] = s[k]  ->  delta of Eq. 4 from the log10 table.
+//
+// LDS layout (bytes): [work: FFT buffer / sort keys / sort counters]
+//                     [ibuf: N uint16 sorted indices] [rank: N uint16]
+//                     [scratch: 64 words + 40 doubles]
+#pragma once
+#include "common.hpp"
+#include "lds_fft.hpp"
+#include "lds_sort.hpp"
+
+namespace agn {
+
+// One curve handled by the LDS-resident kernels.
+struct LcDesc {
+    int32_t n;             // real length N
+    int32_t iters;         // iterations to run
+    double tol;            // stopping rule (see agn_lc_iterate)
+    const void* amp;       // T[N/2 + 1] target moduli
+    const double* x0;      // [N] PDF draw, draw order
+    double* s64;           // [N] sorted draw (written by the prep kernel)
+    void* sT;              // T[N] sorted draw in working precision
+    double* L;             // [N] log10 of the sorted draw
+    uint32_t* rank0;       // [N] rank of x0[n] in the sorted draw
+    int32_t* valid;        // 1 if every draw value is finite and > 0
+    double* x_out;         // [N]
+    double* delta_out;     // [iters] or null
+    int32_t* iters_done;   // [1] or null
+    uint32_t* rank_out;    // [N] or null
+    const void* tw;        // cplx<T>[N/2 + 1], W_N^t
+    FftPlan plan;          // radices of the length-N/2 complex FFT
+};
+
+// LDS bytes of the iteration kernel (host and device agree on this layout).
+template <typename T>
+__host__ __device__ inline size_t lds_iter_layout(int N, int nt, size_t* ibuf_off, size_t* rank_off,
+                                                   size_t* scratch_off) {
+    typedef typename key_of<T>::type K;
+    size_t work = (size_t)N * sizeof(K);
+    if ((size_t)(N / 2) * sizeof(cplx<T>) > work) work = (size_t)(N / 2) * sizeof(cplx<T>);
+    const size_t cnt = (size_t)SORT_LANES * 4 * (size_t)nt;
+    if (cnt > work) work = cnt;
+    work = (work + 15) & ~(size_t)15;
+    const size_t ib = work;
+    const size_t rk = ib + (((size_t)N * 2 + 15) & ~(size_t)15);
+    const size_t sc = rk + (((size_t)N * 2 + 15) & ~(size_t)15);
+    if (ibuf_off) *ibuf_off = ib;
+    if (rank_off) *rank_off = rk;
+    if (scratch_off) *scratch_off = sc;
+    return sc + 128 * 4 + 64 * 8;
+}
+
+__host__ __device__ inline size_t lds_prep_layout(int N, int nt, size_t* scratch_off) {
+    size_t work = (size_t)N * 8;
+    const size_t cnt = (size_t)SORT_LANES * 4 * (size_t)nt;
+    if (cnt > work) work = cnt;
+    work = (work + 15) & ~(size_t)15;
+    if (scratch_off) *scratch_off = work;
+    return work + 128 * 4;
+}
+
+// Deterministic block sum (fixed butterfly + fixed wave order).
+template <typename V>
+AGN_DEV V block_sum(V v, V* scratch /* >= 64 */) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nw = (nt + 63) >> 6;
+    __syncthreads();
+    if (nt < 64) {
+        // Partial single wave: serial sum in thread order.
+        scratch[tid] = v;
+        __syncthreads();
+        V t = scratch[0];
+        for (int i = 1; i < nt; ++i) t += scratch[i];
+        __syncthreads();
+        return t;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (lane == 0) scratch[wave] = v;
+    __syncthreads();
+    V t = scratch[0];
+    for (int w = 1; w < nw; ++w) t += scratch[w];
+    __syncthreads();
+    return t;
+}
+
+// One-time preparation: stable argsort of the draw (64-bit keys), sorted
+// tables and starting ranks.  Same block shape as the iteration kernel.
+template <typename T, int E>
+__global__ __launch_bounds__(1024) void k_lds_prep(const LcDesc* __restrict__ descs) {
+    constexpr int IPT = 2 * E;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const LcDesc& d = descs[blockIdx.x];
+    const int N = d.n;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    size_t sc_off;
+    lds_prep_layout(N, nt, &sc_off);
+    uint32_t* scratch = (uint32_t*)(smem + sc_off);
+    uint16_t* ibuf = (uint16_t*)smem;  // aliases the sort work region
+
+    uint64_t key[IPT];
+    uint32_t idx2[IPT / 2];
+    int bad = 0;
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const int p = tid * IPT + i;
+        const double x = d.x0[p];
+        bad |= !(x > 0.0 && x <= 1.7976931348623157e308);
+        key[i] = ord_key(x);
+    }
+#pragma unroll
+    for (int j = 0; j < IPT / 2; ++j)
+        idx2[j] = (uint32_t)(tid * IPT + 2 * j) | ((uint32_t)(tid * IPT + 2 * j + 1) << 16);
+    bad = __syncthreads_or(bad);
+    block_radix_sort<uint64_t, IPT, false>(key, idx2, smem, ibuf, scratch);
+    T* sT = (T*)d.sT;
+#pragma unroll 4
+    for (int u = 0; u < IPT; ++u) {
+        const int k = u * nt + tid;
+        const uint32_t src = ibuf[k];
+        const double v = d.x0[src];
+        d.s64[k] = v;
+        sT[k] = (T)v;
+        d.L[k] = log10(v);
+        d.rank0[src] = (uint32_t)k;
+    }
+    if (tid == 0) *d.valid = bad ? 0 : 1;
+}
+
+template <typename T, int E>
+__global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__ descs) {
+    typedef typename key_of<T>::type K;
+    constexpr int IPT = 2 * E;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const LcDesc& d = descs[blockIdx.x];
+    const int N = d.n, M = N / 2;
+    const int tid = threadIdx.x, nt = blockDim.x;
+
+    if (*d.valid == 0) {
+        if (tid == 0 && d.iters_done) *d.iters_done = -1;
+        return;
+    }
+
+    size_t ib_off, rk_off, sc_off;
+    lds_iter_layout<T>(N, nt, &ib_off, &rk_off, &sc_off);
+    cplx<T>* Zc = (cplx<T>*)smem;
+    T* Zf = (T*)smem;
+    uint16_t* ibuf = (uint16_t*)(smem + ib_off);
+    uint16_t* rank16 = (uint16_t*)(smem + rk_off);
+    uint32_t* scratch = (uint32_t*)(smem + sc_off);
+    double* dscratch = (double*)(smem + sc_off + 128 * 4);
+
+    const T* __restrict__ amp = (const T*)d.amp;
+    const T* __restrict__ sT = (const T*)d.sT;
+    const double* __restrict__ s64 = d.s64;
+    const double* __restrict__ L = d.L;
+    const cplx<T>* __restrict__ tw = (const cplx<T>*)d.tw;
+    const FftPlan plan = d.plan;
+
+#pragma unroll 4
+    for (int u = 0; u < IPT; ++u) {
+        const int p = u * nt + tid;
+        const uint32_t r = d.rank0[p];
+        rank16[p] = (uint16_t)r;
+        Zf[p] = sT[r];
+    }
+    __syncthreads();
+
+    int done = 0;
+#pragma unroll 1
+    for (int it = 0; it < d.iters; ++it) {
+        lds_fft<T, E, false>(Zc, M, plan, tid, nt, tw, M);
+        lds_fold_replace<T>(Zc, M, amp, tw, tid, nt);
+        lds_fft<T, E, true>(Zc, M, plan, tid, nt, tw, M);
+
+        {
+            K key[IPT];
+            uint32_t idx2[IPT / 2];
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) key[i] = ord_key(Zf[tid * IPT + i]);
+#pragma unroll
+            for (int j = 0; j < IPT / 2; ++j)
+                idx2[j] = (uint32_t)(tid * IPT + 2 * j) | ((uint32_t)(tid * IPT + 2 * j + 1) << 16);
+            __syncthreads();
+            block_radix_sort<K, IPT, true>(key, idx2, smem, ibuf, scratch);
+        }
+
+        double acc = 0.0;
+        uint32_t chg = 0;
+#pragma unroll 4
+        for (int u = 0; u < IPT; ++u) {
+            const uint32_t k = (uint32_t)(u * nt + tid);
+            const uint32_t t = ibuf[k];
+            const uint32_t ro = rank16[t];
+            rank16[t] = (uint16_t)k;
+            if (ro != k) {
+                const double dl = L[k] - L[ro];
+                acc += dl * dl;
+                chg += (s64[k] != s64[ro]) ? 1u : 0u;
+            }
+            Zf[t] = sT[k];
+        }
+        acc = block_sum<double>(acc, dscratch);
+        chg = block_sum<uint32_t>(chg, scratch + 64);
+        const double delta = sqrt(acc / (double)N);
+        if (tid == 0 && d.delta_out) d.delta_out[it] = delta;
+        done = it + 1;
+        if (d.tol >= 0.0 && (chg == 0u || (d.tol > 0.0 && delta <= d.tol))) break;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int u = 0; u < IPT; ++u) {
+        const int p = u * nt + tid;
+        const uint32_t r = rank16[p];
+        d.x_out[p] = s64[r];
+        if (d.rank_out) d.rank_out[p] = r;
+    }
+    if (tid == 0) {
+        if (d.iters_done) *d.iters_done = done;
+        if (d.delta_out)
+            for (int j = done; j < d.iters; ++j) d.delta_out[j] = 0.0;
+    }
+}
+
+}  // namespace agn

@@ -1,0 +1,160 @@
+// lds_sort.hpp -- stable least-significant-digit radix sort of one block of
+// keys held in registers, used for the per-iteration ranking (32-bit keys of
+// float values, 64-bit keys of double values) and for the one-time sort of
+// the PDF draw.
+//
+// Layout: "blocked" -- thread t holds the IPT consecutive positions
+// t * IPT + i.  Digits are RB = 5 bits wide.  Ranking uses thread-private
+// counters, two 16-bit counters per 32-bit LDS word: digit d lives in word
+// (d mod 16) * T + t, half d / 16.  A thread walks its items in position
+// order, so the old value of the counter is the number of earlier equal
+// digits in the same thread.  One exclusive scan of the words in memory order
+// (word lane, then thread) then yields, for each half separately, offsets in
+// (digit, thread) order; adding the low-half total to every high half puts
+// digits 16..31 after digits 0..15.  Every pass is therefore stable, and so is
+// the whole sort.
+#pragma once
+#include "common.hpp"
+
+namespace agn {
+
+// Exclusive scan of one uint32 per thread over the block (fixed order).
+AGN_DEV uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= nw + 1 words */,
+                                      uint32_t* total) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nw = (nt + 63) >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += o;
+    }
+    const int last = (nt - (wave << 6) < 64) ? (nt - (wave << 6) - 1) : 63;
+    if (lane == last) scratch[wave] = inc;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < nw; ++w) {
+            uint32_t t = scratch[w];
+            scratch[w] = run;
+            run += t;
+        }
+        scratch[nw] = run;
+    }
+    __syncthreads();
+    uint32_t r = scratch[wave] + inc - v;
+    if (total) *total = scratch[nw];
+    __syncthreads();
+    return r;
+}
+
+constexpr int SORT_RB = 5;
+constexpr int SORT_LANES = 1 << (SORT_RB - 1);  // counter words per thread
+
+// Bytes of the aliased work region the sort needs for n_block keys of K.
+template <typename K>
+constexpr size_t sort_region_bytes(size_t n_block, size_t nthreads) {
+    return (n_block * sizeof(K) > (size_t)SORT_LANES * 4 * nthreads) ? n_block * sizeof(K)
+                                                                     : (size_t)SORT_LANES * 4 * nthreads;
+}
+
+// Sorts (key, idx) ascending by key, stable in position order.
+//   key[IPT]           this thread's keys at positions t*IPT + i
+//   idx2[IPT/2]        their 16-bit indices, two per word (low half = even i)
+//   work               LDS region of sort_region_bytes<K>(N, T) (counters, keys)
+//   ibuf               LDS, N uint16, 4-byte aligned; may alias `work` only if
+//                      SEP == false
+//   scratch            LDS, >= 20 words, not aliased
+// On return ibuf[k] holds the index carried by the k-th smallest key (after a
+// barrier).  key[] and idx2[] are left in an unspecified state.
+template <typename K, int IPT, bool SEP>
+AGN_DEV void block_radix_sort(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned char* work,
+                              uint16_t* ibuf, uint32_t* scratch) {
+    static_assert(IPT % 2 == 0, "IPT must be even");
+    const int t = threadIdx.x, T = blockDim.x;
+    constexpr int NPASS = (int)((8 * sizeof(K) + SORT_RB - 1) / SORT_RB);
+    uint32_t* cnt = (uint32_t*)work;
+    K* kb = (K*)work;
+    const uint32_t* ibuf32 = (const uint32_t*)ibuf;
+
+#pragma unroll 1
+    for (int pass = 0; pass < NPASS; ++pass) {
+        const int shift = pass * SORT_RB;
+#pragma unroll
+        for (int l = 0; l < SORT_LANES; ++l) cnt[l * T + t] = 0u;
+        // pos[i]: bits 0..15 running position, bits 16..20 the digit.
+        uint32_t pos[IPT];
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const uint32_t d = (uint32_t)(key[i] >> shift) & (2 * SORT_LANES - 1);
+            const int a = (int)(d & (SORT_LANES - 1)) * T + t;
+            const uint32_t sh = (d & SORT_LANES) ? 16u : 0u;
+            const uint32_t c = cnt[a];
+            pos[i] = ((c >> sh) & 0xFFFFu) | (d << 16);
+            cnt[a] = c + (1u << sh);
+        }
+        __syncthreads();
+        {
+            uint32_t w[SORT_LANES];
+            uint32_t s = 0;
+#pragma unroll
+            for (int q = 0; q < SORT_LANES; ++q) {
+                w[q] = cnt[t * SORT_LANES + q];
+                s += w[q];
+            }
+            uint32_t total;
+            uint32_t run = block_exclusive_scan(s, scratch, &total);
+            run += (total & 0xFFFFu) << 16;
+#pragma unroll
+            for (int q = 0; q < SORT_LANES; ++q) {
+                cnt[t * SORT_LANES + q] = run;
+                run += w[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const uint32_t d = pos[i] >> 16;
+            const int a = (int)(d & (SORT_LANES - 1)) * T + t;
+            const uint32_t sh = (d & SORT_LANES) ? 16u : 0u;
+            pos[i] = (pos[i] & 0xFFFFu) + ((cnt[a] >> sh) & 0xFFFFu);
+        }
+        __syncthreads();
+        const bool last = (pass == NPASS - 1);
+        if (SEP) {
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                if (!last) kb[pos[i]] = key[i];
+                ibuf[pos[i]] = (uint16_t)((i & 1) ? (idx2[i / 2] >> 16) : (idx2[i / 2] & 0xFFFFu));
+            }
+            __syncthreads();
+            if (!last) {
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) key[i] = kb[t * IPT + i];
+#pragma unroll
+                for (int j = 0; j < IPT / 2; ++j) idx2[j] = ibuf32[(t * IPT) / 2 + j];
+                __syncthreads();
+            }
+        } else {
+            if (!last) {
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) kb[pos[i]] = key[i];
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) key[i] = kb[t * IPT + i];
+                __syncthreads();
+            }
+#pragma unroll
+            for (int i = 0; i < IPT; ++i)
+                ibuf[pos[i]] = (uint16_t)((i & 1) ? (idx2[i / 2] >> 16) : (idx2[i / 2] & 0xFFFFu));
+            __syncthreads();
+            if (!last) {
+#pragma unroll
+                for (int j = 0; j < IPT / 2; ++j) idx2[j] = ibuf32[(t * IPT) / 2 + j];
+                __syncthreads();
+            }
+        }
+    }
+}
+
+}  // namespace agn
