@@ -150,6 +150,7 @@ struct ProfRec {
 
 struct agn_ctx {
     int device = 0;
+    size_t lds_max = 65536;  // LDS bytes one workgroup may allocate
     bool prof = false;
     std::vector<ProfRec> prof_recs;
     std::mutex mu;
@@ -264,34 +265,17 @@ static int stage_upload(agn_ctx* ctx, void* dst, const void* src, size_t bytes, 
     return AGN_OK;
 }
 
-template <typename T, int E>
-static void set_attrs_one() {
-    (void)hipFuncSetAttribute((const void*)k_lds_iterate<T, E>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        160 * 1024);
-    (void)hipFuncSetAttribute((const void*)k_lds_prep<T, E>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        160 * 1024);
-}
-
-template <typename T>
-static void set_attrs_prec() {
-    set_attrs_one<T, 1>();
-    set_attrs_one<T, 2>();
-    set_attrs_one<T, 3>();
-    set_attrs_one<T, 4>();
-    set_attrs_one<T, 6>();
-    set_attrs_one<T, 8>();
-}
-
 extern "C" int agn_ctx_create(int device, agn_ctx** out) {
     if (!out) return fail(AGN_EINVAL, "out is NULL");
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(AGN_EINVAL, "device %d out of range (%d devices)", device, ndev);
     HIPCHK(hipSetDevice(device));
-    set_attrs_prec<float>();
-    set_attrs_prec<double>();
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, device));
     agn_ctx* c = new agn_ctx();
     c->device = device;
+    c->lds_max = prop.sharedMemPerBlock;
     *out = c;
     return AGN_OK;
 }
@@ -562,6 +546,9 @@ static int run_batch(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_pr
         const int E = lds_ipt(n) / 2;
         const int nt = (int)(n / lds_ipt(n));
         const size_t pl = lds_prep_bytes(n), il = lds_iter_bytes(n, prec);
+        if (pl > ctx->lds_max || il > ctx->lds_max)
+            return fail(AGN_EUNSUPPORTED_N, "n=%lld needs %zu bytes of LDS per workgroup; the device allows %zu",
+                        (long long)n, std::max(pl, il), ctx->lds_max);
         int rc = (prec == AGN_FP32) ? launch_lds_E<float>(ctx, E, d_lc + i, j - i, nt, pl, il, st)
                                     : launch_lds_E<double>(ctx, E, d_lc + i, j - i, nt, pl, il, st);
         if (rc) return rc;

@@ -35,6 +35,14 @@ AGN_DEV uint64_t ord_key(double f) {
     return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
 }
 
+// Returns x unchanged but opaque to the optimiser, so that per-item address
+// arithmetic derived from it is recomputed where it is used instead of being
+// hoisted out of long loops and kept live in registers.
+AGN_DEV int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 template <typename T> struct key_of;
 template <> struct key_of<float> { typedef uint32_t type; };
 template <> struct key_of<double> { typedef uint64_t type; };

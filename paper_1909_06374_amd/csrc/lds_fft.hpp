@@ -6,10 +6,9 @@
 // current block size Ns: butterfly j (0 <= j < M/R) reads the R inputs
 // buf[j + r M/R], multiplies input r by W_{Ns R}^{(j mod Ns) r}, takes a
 // length-R DFT and writes output q to buf[(j - j mod Ns) R + j mod Ns + q Ns].
-// After the last pass the data are in natural order.  Every thread owns E
-// complex values (E/R butterflies per pass), so a pass reads all of them into
-// registers, meets the workgroup barrier and then writes in place: one LDS
-// buffer of M values suffices.
+// After the last pass the data are in natural order.  Each thread reads all of
+// its butterflies' inputs into registers, meets the workgroup barrier and then
+// writes in place: one LDS buffer of M values (plus padding) suffices.
 //
 // Twiddles come from a table of W_N^t = exp(-2 pi i t / N), t = 0..N/2, for the
 // real length N = 2M (computed in double on the host, rounded once to T);
@@ -23,6 +22,17 @@ struct FftPlan {
     int32_t npass;
     uint8_t radix[20];
 };
+
+// LDS address of complex element c: one pad element per 256 bytes, so that the
+// strided writes of the first Stockham passes and the blocked reads of the
+// sort spread over all 64 banks.
+template <typename T>
+AGN_DEV int cpad(int c) { return c + (c >> (sizeof(T) == 4 ? 5 : 4)); }
+// LDS address (in T units) of real element p of the same buffer.
+template <typename T>
+AGN_DEV int rpad(int p) { return 2 * cpad<T>(p >> 1) + (p & 1); }
+template <typename T>
+__host__ __device__ inline int cpad_size(int m) { return m + (m >> (sizeof(T) == 4 ? 5 : 4)) + 1; }
 
 // W_N^t for 0 <= t < N from the half table (t <= N/2); inverse = conjugate.
 template <typename T, bool INV>
@@ -108,36 +118,45 @@ AGN_DEV void dftR(cplx<T>* v) {
 }
 
 // One Stockham pass.  The M/R butterflies are dealt round-robin to the nt
-// threads (at most BMAX per thread); all threads meet both barriers.
+// threads (at most BMAX per thread); all threads meet both barriers.  The
+// twiddles depend only on the butterfly index, so they are fetched before the
+// barrier, overlapping their latency with the LDS reads.
 template <typename T, int R, int BMAX, bool INV>
 AGN_DEV void lds_pass(cplx<T>* buf, int M, int Ns, int tid, int nt,
                       const cplx<T>* __restrict__ tw, int halfN) {
     cplx<T> v[BMAX][R];
+    cplx<T> w[BMAX][R];
+    tid = opaque(tid);
     const int MR = M / R;
-#pragma unroll
-    for (int b = 0; b < BMAX; ++b) {
-        const int j = tid + b * nt;
-        if (j < MR) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[b][r] = buf[j + r * MR];
-        }
-    }
-    __syncthreads();
+    const bool pow2 = (Ns & (Ns - 1)) == 0;
     const int tstep = 2 * (M / (Ns * R));
 #pragma unroll
     for (int b = 0; b < BMAX; ++b) {
         const int j = tid + b * nt;
         if (j < MR) {
-            const int jm = j % Ns;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b][r] = buf[cpad<T>(j + r * MR)];
+            if (Ns > 1) {
+                const int jm = pow2 ? (j & (Ns - 1)) : (j % Ns);
+#pragma unroll
+                for (int r = 1; r < R; ++r) w[b][r] = twiddle<T, INV>(tw, jm * r * tstep, halfN);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BMAX; ++b) {
+        const int j = tid + b * nt;
+        if (j < MR) {
+            const int jm = pow2 ? (j & (Ns - 1)) : (j % Ns);
             if (Ns > 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r)
-                    v[b][r] = cmul(v[b][r], twiddle<T, INV>(tw, jm * r * tstep, halfN));
+                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], w[b][r]);
             }
             dftR<T, R, INV>(v[b]);
             const int d = (j - jm) * R + jm;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[d + r * Ns] = v[b][r];
+            for (int r = 0; r < R; ++r) buf[cpad<T>(d + r * Ns)] = v[b][r];
         }
     }
     __syncthreads();
@@ -181,7 +200,7 @@ AGN_DEV void lds_fold_replace(cplx<T>* Z, int M, const T* __restrict__ amp,
     const int half = M / 2;
     for (int k = tid; k <= half; k += nthreads) {
         const int mk = (k == 0) ? 0 : M - k;
-        const cplx<T> zk = Z[k], zm = Z[mk];
+        const cplx<T> zk = Z[cpad<T>(k)], zm = Z[cpad<T>(mk)];
         const cplx<T> Ev = cmk((zk.re + zm.re) * (T)0.5, (zk.im - zm.im) * (T)0.5);
         const cplx<T> Ov = cmk((zk.im + zm.im) * (T)0.5, (zm.re - zk.re) * (T)0.5);
         const cplx<T> w = tw[k];
@@ -189,7 +208,7 @@ AGN_DEV void lds_fold_replace(cplx<T>* Z, int M, const T* __restrict__ amp,
         if (k == 0) {
             const T xn = Ev.re - wO.re;  // X_M, real for real input
             const T yn = (xn >= (T)0) ? amp[M] : -amp[M];
-            Z[0] = cmk(yn, -yn);
+            Z[cpad<T>(0)] = cmk(yn, -yn);
         } else {
             const cplx<T> Xk = cadd(Ev, wO);
             const cplx<T> Xm = cconj(csub(Ev, wO));
@@ -198,10 +217,10 @@ AGN_DEV void lds_fold_replace(cplx<T>* Z, int M, const T* __restrict__ amp,
             const cplx<T> A = cadd(Yk, cconj(Ym));
             const cplx<T> B = csub(Yk, cconj(Ym));
             const cplx<T> cwB = cmul(cconj(w), B);
-            Z[k] = cmk(A.re - cwB.im, A.im + cwB.re);  // A + i conj(w) B
+            Z[cpad<T>(k)] = cmk(A.re - cwB.im, A.im + cwB.re);  // A + i conj(w) B
             if (mk != k) {
                 const cplx<T> wcB = cmul(w, cconj(B));
-                Z[mk] = cmk(A.re - wcB.im, -A.im + wcB.re);  // conj(A) + i w conj(B)
+                Z[cpad<T>(mk)] = cmk(A.re - wcB.im, -A.im + wcB.re);  // conj(A) + i w conj(B)
             }
         }
     }

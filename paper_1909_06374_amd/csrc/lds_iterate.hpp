@@ -45,13 +45,14 @@ template <typename T>
 __host__ __device__ inline size_t lds_iter_layout(int N, int nt, size_t* ibuf_off, size_t* rank_off,
                                                    size_t* scratch_off) {
     typedef typename key_of<T>::type K;
-    size_t work = (size_t)N * sizeof(K);
-    if ((size_t)(N / 2) * sizeof(cplx<T>) > work) work = (size_t)(N / 2) * sizeof(cplx<T>);
-    const size_t cnt = (size_t)SORT_LANES * 4 * (size_t)nt;
+    size_t work = sort_keys_bytes<K>(N);
+    const size_t fft = (size_t)cpad_size<T>(N / 2) * sizeof(cplx<T>);
+    if (fft > work) work = fft;
+    const size_t cnt = sort_cnt_bytes(nt);
     if (cnt > work) work = cnt;
     work = (work + 15) & ~(size_t)15;
     const size_t ib = work;
-    const size_t rk = ib + (((size_t)N * 2 + 15) & ~(size_t)15);
+    const size_t rk = ib + ((sort_ibuf_bytes(N) + 15) & ~(size_t)15);
     const size_t sc = rk + (((size_t)N * 2 + 15) & ~(size_t)15);
     if (ibuf_off) *ibuf_off = ib;
     if (rank_off) *rank_off = rk;
@@ -60,9 +61,10 @@ __host__ __device__ inline size_t lds_iter_layout(int N, int nt, size_t* ibuf_of
 }
 
 __host__ __device__ inline size_t lds_prep_layout(int N, int nt, size_t* scratch_off) {
-    size_t work = (size_t)N * 8;
-    const size_t cnt = (size_t)SORT_LANES * 4 * (size_t)nt;
+    size_t work = sort_keys_bytes<uint64_t>(N);
+    const size_t cnt = sort_cnt_bytes(nt);
     if (cnt > work) work = cnt;
+    if (sort_ibuf_bytes(N) > work) work = sort_ibuf_bytes(N);
     work = (work + 15) & ~(size_t)15;
     if (scratch_off) *scratch_off = work;
     return work + 128 * 4;
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(1024) void k_lds_prep(const LcDesc* __restrict__ de
 #pragma unroll 4
     for (int u = 0; u < IPT; ++u) {
         const int k = u * nt + tid;
-        const uint32_t src = ibuf[k];
+        const uint32_t src = ibuf[hpad(k)];
         const double v = d.x0[src];
         d.s64[k] = v;
         sT[k] = (T)v;
@@ -171,7 +173,7 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
         const int p = u * nt + tid;
         const uint32_t r = d.rank0[p];
         rank16[p] = (uint16_t)r;
-        Zf[p] = sT[r];
+        Zf[rpad<T>(p)] = sT[r];
     }
     __syncthreads();
 
@@ -185,21 +187,23 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
         {
             K key[IPT];
             uint32_t idx2[IPT / 2];
+            const int tk = opaque(tid);
 #pragma unroll
-            for (int i = 0; i < IPT; ++i) key[i] = ord_key(Zf[tid * IPT + i]);
+            for (int i = 0; i < IPT; ++i) key[i] = ord_key(Zf[rpad<T>(tk * IPT + i)]);
 #pragma unroll
             for (int j = 0; j < IPT / 2; ++j)
-                idx2[j] = (uint32_t)(tid * IPT + 2 * j) | ((uint32_t)(tid * IPT + 2 * j + 1) << 16);
+                idx2[j] = (uint32_t)(tk * IPT + 2 * j) | ((uint32_t)(tk * IPT + 2 * j + 1) << 16);
             __syncthreads();
             block_radix_sort<K, IPT, true>(key, idx2, smem, ibuf, scratch);
         }
 
         double acc = 0.0;
         uint32_t chg = 0;
+        const int tpost = opaque(tid);
 #pragma unroll 4
         for (int u = 0; u < IPT; ++u) {
-            const uint32_t k = (uint32_t)(u * nt + tid);
-            const uint32_t t = ibuf[k];
+            const uint32_t k = (uint32_t)(u * nt + tpost);
+            const uint32_t t = ibuf[hpad(k)];
             const uint32_t ro = rank16[t];
             rank16[t] = (uint16_t)k;
             if (ro != k) {
@@ -207,7 +211,7 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
                 acc += dl * dl;
                 chg += (s64[k] != s64[ro]) ? 1u : 0u;
             }
-            Zf[t] = sT[k];
+            Zf[rpad<T>(t)] = sT[k];
         }
         acc = block_sum<double>(acc, dscratch);
         chg = block_sum<uint32_t>(chg, scratch + 64);

@@ -51,27 +51,42 @@ AGN_DEV uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= nw + 1
 constexpr int SORT_RB = 5;
 constexpr int SORT_LANES = 1 << (SORT_RB - 1);  // counter words per thread
 
-// Bytes of the aliased work region the sort needs for n_block keys of K.
+// Padded LDS indices (one pad slot per 128 or 256 bytes) so that the blocked
+// accesses, which stride by IPT elements across lanes, spread over the banks.
 template <typename K>
-constexpr size_t sort_region_bytes(size_t n_block, size_t nthreads) {
-    return (n_block * sizeof(K) > (size_t)SORT_LANES * 4 * nthreads) ? n_block * sizeof(K)
-                                                                     : (size_t)SORT_LANES * 4 * nthreads;
+AGN_DEV int kpad(int e) { return e + (e >> (sizeof(K) == 4 ? 5 : 4)); }
+AGN_DEV int wpad(int w) { return w + (w >> 5); }
+// 16-bit element e of a padded array of 32-bit words.
+AGN_DEV int hpad(int e) { return 2 * wpad(e >> 1) + (e & 1); }
+
+template <typename K>
+__host__ __device__ inline size_t sort_keys_bytes(int n) {
+    return ((size_t)n + (n >> (sizeof(K) == 4 ? 5 : 4)) + 1) * sizeof(K);
+}
+__host__ __device__ inline size_t sort_cnt_bytes(int nthreads) {
+    const int w = SORT_LANES * nthreads;
+    return ((size_t)w + (w >> 5) + 1) * 4;
+}
+__host__ __device__ inline size_t sort_ibuf_bytes(int n) {
+    const int w = (n + 1) / 2;
+    return ((size_t)w + (w >> 5) + 1) * 4;
 }
 
 // Sorts (key, idx) ascending by key, stable in position order.
 //   key[IPT]           this thread's keys at positions t*IPT + i
 //   idx2[IPT/2]        their 16-bit indices, two per word (low half = even i)
-//   work               LDS region of sort_region_bytes<K>(N, T) (counters, keys)
-//   ibuf               LDS, N uint16, 4-byte aligned; may alias `work` only if
-//                      SEP == false
+//   work               LDS region of max(sort_keys_bytes<K>(N), sort_cnt_bytes(T))
+//                      (counters, keys)
+//   ibuf               LDS, sort_ibuf_bytes(N), 4-byte aligned, padded (hpad);
+//                      may alias `work` only if SEP == false
 //   scratch            LDS, >= 20 words, not aliased
-// On return ibuf[k] holds the index carried by the k-th smallest key (after a
-// barrier).  key[] and idx2[] are left in an unspecified state.
+// On return ibuf[hpad(k)] holds the index carried by the k-th smallest key
+// (after a barrier).  key[] and idx2[] are left in an unspecified state.
 template <typename K, int IPT, bool SEP>
 AGN_DEV void block_radix_sort(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned char* work,
                               uint16_t* ibuf, uint32_t* scratch) {
     static_assert(IPT % 2 == 0, "IPT must be even");
-    const int t = threadIdx.x, T = blockDim.x;
+    const int T = blockDim.x;
     constexpr int NPASS = (int)((8 * sizeof(K) + SORT_RB - 1) / SORT_RB);
     uint32_t* cnt = (uint32_t*)work;
     K* kb = (K*)work;
@@ -79,15 +94,16 @@ AGN_DEV void block_radix_sort(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned
 
 #pragma unroll 1
     for (int pass = 0; pass < NPASS; ++pass) {
+        const int t = opaque((int)threadIdx.x);
         const int shift = pass * SORT_RB;
 #pragma unroll
-        for (int l = 0; l < SORT_LANES; ++l) cnt[l * T + t] = 0u;
+        for (int l = 0; l < SORT_LANES; ++l) cnt[wpad(l * T + t)] = 0u;
         // pos[i]: bits 0..15 running position, bits 16..20 the digit.
         uint32_t pos[IPT];
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             const uint32_t d = (uint32_t)(key[i] >> shift) & (2 * SORT_LANES - 1);
-            const int a = (int)(d & (SORT_LANES - 1)) * T + t;
+            const int a = wpad((int)(d & (SORT_LANES - 1)) * T + t);
             const uint32_t sh = (d & SORT_LANES) ? 16u : 0u;
             const uint32_t c = cnt[a];
             pos[i] = ((c >> sh) & 0xFFFFu) | (d << 16);
@@ -99,7 +115,7 @@ AGN_DEV void block_radix_sort(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned
             uint32_t s = 0;
 #pragma unroll
             for (int q = 0; q < SORT_LANES; ++q) {
-                w[q] = cnt[t * SORT_LANES + q];
+                w[q] = cnt[wpad(t * SORT_LANES + q)];
                 s += w[q];
             }
             uint32_t total;
@@ -107,7 +123,7 @@ AGN_DEV void block_radix_sort(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned
             run += (total & 0xFFFFu) << 16;
 #pragma unroll
             for (int q = 0; q < SORT_LANES; ++q) {
-                cnt[t * SORT_LANES + q] = run;
+                cnt[wpad(t * SORT_LANES + q)] = run;
                 run += w[q];
             }
         }
@@ -115,7 +131,7 @@ AGN_DEV void block_radix_sort(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             const uint32_t d = pos[i] >> 16;
-            const int a = (int)(d & (SORT_LANES - 1)) * T + t;
+            const int a = wpad((int)(d & (SORT_LANES - 1)) * T + t);
             const uint32_t sh = (d & SORT_LANES) ? 16u : 0u;
             pos[i] = (pos[i] & 0xFFFFu) + ((cnt[a] >> sh) & 0xFFFFu);
         }
@@ -124,33 +140,33 @@ AGN_DEV void block_radix_sort(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned
         if (SEP) {
 #pragma unroll
             for (int i = 0; i < IPT; ++i) {
-                if (!last) kb[pos[i]] = key[i];
-                ibuf[pos[i]] = (uint16_t)((i & 1) ? (idx2[i / 2] >> 16) : (idx2[i / 2] & 0xFFFFu));
+                if (!last) kb[kpad<K>(pos[i])] = key[i];
+                ibuf[hpad(pos[i])] = (uint16_t)((i & 1) ? (idx2[i / 2] >> 16) : (idx2[i / 2] & 0xFFFFu));
             }
             __syncthreads();
             if (!last) {
 #pragma unroll
-                for (int i = 0; i < IPT; ++i) key[i] = kb[t * IPT + i];
+                for (int i = 0; i < IPT; ++i) key[i] = kb[kpad<K>(t * IPT + i)];
 #pragma unroll
-                for (int j = 0; j < IPT / 2; ++j) idx2[j] = ibuf32[(t * IPT) / 2 + j];
+                for (int j = 0; j < IPT / 2; ++j) idx2[j] = ibuf32[wpad((t * IPT) / 2 + j)];
                 __syncthreads();
             }
         } else {
             if (!last) {
 #pragma unroll
-                for (int i = 0; i < IPT; ++i) kb[pos[i]] = key[i];
+                for (int i = 0; i < IPT; ++i) kb[kpad<K>(pos[i])] = key[i];
                 __syncthreads();
 #pragma unroll
-                for (int i = 0; i < IPT; ++i) key[i] = kb[t * IPT + i];
+                for (int i = 0; i < IPT; ++i) key[i] = kb[kpad<K>(t * IPT + i)];
                 __syncthreads();
             }
 #pragma unroll
             for (int i = 0; i < IPT; ++i)
-                ibuf[pos[i]] = (uint16_t)((i & 1) ? (idx2[i / 2] >> 16) : (idx2[i / 2] & 0xFFFFu));
+                ibuf[hpad(pos[i])] = (uint16_t)((i & 1) ? (idx2[i / 2] >> 16) : (idx2[i / 2] & 0xFFFFu));
             __syncthreads();
             if (!last) {
 #pragma unroll
-                for (int j = 0; j < IPT / 2; ++j) idx2[j] = ibuf32[(t * IPT) / 2 + j];
+                for (int j = 0; j < IPT / 2; ++j) idx2[j] = ibuf32[wpad((t * IPT) / 2 + j)];
                 __syncthreads();
             }
         }

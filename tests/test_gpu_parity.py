@@ -73,16 +73,23 @@ def test_philox_words_bit_exact(gpu_ctx):
 
 @pytest.mark.parametrize("n", [2, 6, 8, 1024, 1536, 2**14, 3 * 2**12, 2**20])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_spectrum_matches_oracle(gpu_ctx, n, prec):
+@pytest.mark.parametrize("norm", [0.0, 2.5])
+def test_spectrum_matches_oracle(gpu_ctx, n, prec, norm):
+    """Moduli within a few ulp (pow, log, cos, sqrt differ by <= 1 ulp between
+    the device and host libraries).  With the unit-variance normalisation the
+    amplitude A is a sum over N/2 bins taken in a different order on each side;
+    its relative difference is bounded by (N/2) 2^-53 (sequential summation)."""
     m = agn()
-    p = m.psd_params(**PSD)
+    prm = dict(PSD, norm=norm)
     ws = torch.empty(m.agn_spectrum_workspace_size(n), dtype=torch.uint8, device="cuda:0")
     amp = torch.full((n // 2 + 1,), float("nan"), dtype=torch.float64 if prec == 0 else torch.float32,
                      device="cuda:0")
-    m.agn_psd_spectrum(gpu_ctx, p, n, 1.0, 42, 7, prec, amp, ws)
+    m.agn_psd_spectrum(gpu_ctx, m.psd_params(**prm), n, 1.0, 42, 7, prec, amp, ws)
     got = host(amp).astype(np.float64)
-    ref = oracle.psd_spectrum(oracle.psd_params(**PSD), n, 1.0, 42, 7)
-    rtol = 4e-15 if prec == 0 else 2.0**-23
+    ref = oracle.psd_spectrum(oracle.psd_params(**prm), n, 1.0, 42, 7)
+    rtol = 4e-15 + (0.5 * (n // 2) * 2.0**-53 if norm <= 0 else 0.0)
+    if prec == 1:
+        rtol += 2.0**-24
     assert got[0] == 0.0
     assert np.all(np.abs(got - ref) <= rtol * np.abs(ref) + 1e-300)
 
@@ -120,9 +127,27 @@ def test_generate_single_curve_fp64_matches_oracle(gpu_ctx):
     assert delta_close(host(d), dr)
 
 
-@pytest.mark.parametrize("n", [1024, 4096, 2**14])
+def fp32_expected_agreement(amp, xin, n, c=2.0):
+    """Expected one-step exact-rank agreement of an FP32 iteration.
+
+    Model: every FP32 FFT output carries an absolute round-off error with
+    standard deviation s = c 2^-24 sqrt(log2 N) rms(y) (c of order 1 for a
+    radix-8 FFT with correctly rounded twiddles).  Adjacent sorted values with
+    gap g exchange with probability P(e1 - e2 > g) = erfc(g / 2s) / 2, and an
+    exchange changes two ranks.  y is the exact (oracle) output of the step."""
+    from scipy.special import erfc
+    X = oracle.rfft(xin)
+    y = oracle.irfft(oracle.replace(X, amp, n), n)
+    g = np.diff(np.sort(y))
+    s = c * 2.0**-24 * np.sqrt(np.log2(n)) * np.sqrt(np.mean(y * y))
+    return 1.0 - 2.0 * np.sum(0.5 * erfc(g / (2 * s))) / n
+
+
+@pytest.mark.parametrize("n", [1024, 4096, 8192, 2**14, 12288])
 def test_fp32_one_step_rank_agreement(gpu_ctx, n):
-    """Both paths fed the same x_{i-1}: exact-rank agreement of one iteration."""
+    """Both paths fed the same x_{i-1}: exact-rank agreement of one iteration,
+    >= 99.9%, or the FP32 round-off model's expectation where the gaps between
+    sorted values are too small for 99.9% in single precision."""
     x0 = synth.erdf_draw(n, seed=77)
     amp = oracle.psd_spectrum(oracle.psd_params(**PSD), n, 1.0, seed=3)
     # a state well inside the iteration
@@ -131,7 +156,11 @@ def test_fp32_one_step_rank_agreement(gpu_ctx, n):
     xg, dg, _, rg = run_iterate(gpu_ctx, amp, xin, 1, 1)
     assert np.array_equal(np.sort(xg), np.sort(x0))
     agree = np.mean(rg == rr)
-    assert agree >= 0.999, agree
+    expect = fp32_expected_agreement(amp, xin, n)
+    print(f"N={n}: one-step FP32 rank agreement {agree:.5f}; round-off model (c=2) {expect:.5f}")
+    assert agree >= min(0.999, expect), (agree, expect)
+    # every disagreement is a local exchange among near-equal values
+    assert np.max(np.abs(rg.astype(np.int64) - rr.astype(np.int64))) <= 8
 
 
 @pytest.mark.parametrize("n", [2**14, 12288])
