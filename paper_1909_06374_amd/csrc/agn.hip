@@ -17,6 +17,7 @@
 
 #include "../../include/agn.h"
 #include "common.hpp"
+#include "big_path.hpp"
 #include "lds_iterate.hpp"
 #include "philox.hpp"
 #include "spectrum.hpp"
@@ -115,8 +116,11 @@ static size_t spectrum_ws(int64_t n) {
     return align256((size_t)spec_chunks(n) * 8) + align256(8);
 }
 
+static size_t big_curve_ws(int64_t n, agn_precision prec);
+
 // Per-curve workspace: s64, sT, L, rank0, valid, amp, spectrum scratch.
 static size_t curve_ws(int64_t n, agn_precision prec) {
+    if (!lds_path(n, prec)) return big_curve_ws(n, prec);
     const size_t pb = prec_bytes(prec);
     size_t b = 0;
     b += align256((size_t)n * 8);          // s64
@@ -129,8 +133,30 @@ static size_t curve_ws(int64_t n, agn_precision prec) {
     return b;
 }
 
+// Per-curve workspace of the multi-pass path.
+static size_t big_curve_ws(int64_t n, agn_precision prec) {
+    const size_t pb = prec_bytes(prec);
+    const size_t region = (size_t)n * 12;  // max of (iteration key + value) and (64-bit key + value)
+    const int64_t ntiles = n / BIG_TILE;
+    size_t b = 0;
+    b += align256((size_t)n * 8);           // s64
+    b += align256((size_t)n * pb);          // sT
+    b += align256((size_t)n * 8);           // L
+    b += 2 * align256((size_t)n * 4);       // rankA, rankB
+    b += 2 * align256(region);              // sortA, sortB
+    b += align256((size_t)ntiles * 256 * 4);  // hist
+    b += align256(256 * 4);                 // dstart
+    b += align256((size_t)ntiles * 8);      // dpart
+    b += align256((size_t)ntiles * 4);      // cpart
+    b += align256(16);                      // state
+    b += align256((size_t)(n / 2 + 1) * pb);  // amp
+    b += spectrum_ws(n);
+    return b;
+}
+
 static size_t header_ws(int32_t nc) {
-    return align256(sizeof(LcDesc) * (size_t)nc) + align256(sizeof(SpecDesc) * (size_t)nc);
+    return align256(sizeof(LcDesc) * (size_t)nc) + align256(sizeof(SpecDesc) * (size_t)nc) +
+           align256(sizeof(BigCurve) * (size_t)nc);
 }
 
 // ---------------------------------------------------------------------------
@@ -155,12 +181,15 @@ struct agn_ctx {
     std::vector<ProfRec> prof_recs;
     std::mutex mu;
     std::map<std::pair<int64_t, int>, void*> tw;
+    std::map<int64_t, TwTable> tw64;
+    std::vector<void*> tw64_mem;
     std::vector<StageSlot> ring;
     size_t ring_next = 0;
 };
 
 static const char* KERNEL_NAMES =
-    "spectrum_partial,spectrum_norm,spectrum_amp,lds_prep,lds_iterate";
+    "spectrum_partial,spectrum_norm,spectrum_amp,lds_prep,lds_iterate,big_prep,fft_pass,fold,"
+    "sort_hist,sort_scan,sort_scatter,delta,big_output";
 
 // Kernel timing: events recorded on the launch stream around each launch.
 struct ProfScope {
@@ -329,6 +358,7 @@ extern "C" int agn_ctx_destroy(agn_ctx* ctx) {
         if (s.host) hipHostFree(s.host);
     }
     for (auto& kv : ctx->tw) hipFree(kv.second);
+    for (void* p : ctx->tw64_mem) hipFree(p);
     delete ctx;
     return AGN_OK;
 }
@@ -349,10 +379,8 @@ static int check_prec(agn_precision prec) {
 }
 
 static int check_path(int64_t n, agn_precision prec) {
+    (void)prec;
     if (!n_supported(n)) return fail(AGN_EUNSUPPORTED_N, "n=%lld is not 2^a or 3*2^a in [2, 2^27]", (long long)n);
-    if (!lds_path(n, prec))
-        return fail(AGN_EUNSUPPORTED_N, "n=%lld exceeds the lengths this build iterates in %s",
-                    (long long)n, prec == AGN_FP32 ? "FP32" : "FP64");
     return AGN_OK;
 }
 
@@ -450,6 +478,196 @@ static void launch_spectrum(agn_ctx* ctx, const SpecDesc* d_sp, int nsp, int64_t
     }
 }
 
+// FP64 two-level twiddle table of length n (multi-pass path), cached per n.
+static int get_tw64(agn_ctx* ctx, int64_t n, TwTable* out) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->tw64.find(n);
+    if (it != ctx->tw64.end()) { *out = it->second; return AGN_OK; }
+    const int64_t B = (int64_t)1 << TW_LO_BITS;
+    const int64_t nlo = B, nhi = n / B + 2;
+    std::vector<double> t(2 * (nlo + nhi));
+    for (int64_t u = 0; u < nlo; ++u) {
+        double c, sn;
+        cis_2pi(u, n, &c, &sn);
+        t[2 * u] = c;
+        t[2 * u + 1] = -sn;
+    }
+    for (int64_t v = 0; v < nhi; ++v) {
+        double c, sn;
+        cis_2pi(v * B, n, &c, &sn);
+        t[2 * (nlo + v)] = c;
+        t[2 * (nlo + v) + 1] = -sn;
+    }
+    void* dptr = nullptr;
+    const size_t bytes = t.size() * sizeof(double);
+    if (hipMalloc(&dptr, bytes) != hipSuccess)
+        return fail(AGN_ENOMEM, "twiddle table allocation of %zu bytes failed", bytes);
+    HIPCHK(hipMemcpy(dptr, t.data(), bytes, hipMemcpyHostToDevice));
+    TwTable tb;
+    tb.lo = (const cplx<double>*)dptr;
+    tb.hi = (const cplx<double>*)dptr + nlo;
+    ctx->tw64[n] = tb;
+    ctx->tw64_mem.push_back(dptr);
+    *out = tb;
+    return AGN_OK;
+}
+
+// Radices of the HBM passes of a length-M complex FFT: as few passes as the
+// largest in-LDS radix (2^9 FP32, 2^8 FP64) allows, exponents split evenly;
+// the factor 3, if any, joins the first pass (whose exponent is capped so that
+// 3 * 2^e stays within the limit).  Every pass keeps M / R a multiple of 16.
+static std::vector<int> big_radices(int64_t M, agn_precision prec) {
+    const int maxlog = prec == AGN_FP32 ? 9 : 8;
+    const int three = (M % 3 == 0) ? 1 : 0;
+    int64_t m = three ? M / 3 : M;
+    int a = 0;
+    while (m > 1) { m >>= 1; ++a; }
+    for (int np = 1; np <= 8; ++np) {
+        const int cap0 = three ? maxlog - 2 : maxlog;
+        if (a > cap0 + (np - 1) * maxlog) continue;
+        std::vector<int> e(np, 0);
+        const int target = (a + np - 1) / np;
+        e[0] = std::min(cap0, target);
+        int rest = a - e[0];
+        for (int i = 1; i < np; ++i) {
+            const int left = np - i;
+            e[i] = std::min(maxlog, (rest + left - 1) / left);
+            rest -= e[i];
+        }
+        if (rest != 0) continue;
+        std::vector<int> r(np);
+        for (int i = 0; i < np; ++i) r[i] = (1 << e[i]) * ((i == 0 && three) ? 3 : 1);
+        return r;
+    }
+    return {};
+}
+
+template <typename T>
+static void launch_fft_pass(agn_ctx* ctx, const BigCurve* d, int nc, const FftPass& P, const TwTable& tb,
+                            hipStream_t st) {
+    const size_t lds = (size_t)(P.R * FFT_COLS + 1 + ((P.R * FFT_COLS + 1) >> (sizeof(T) == 4 ? 5 : 4))) *
+                           sizeof(cplx<T>) + 16 + (size_t)P.R * sizeof(cplx<T>);
+    dim3 grid((unsigned)(P.M / P.R / FFT_COLS), (unsigned)nc);
+    ProfScope ps(ctx, "fft_pass", st);
+    if (P.inverse)
+        hipLaunchKernelGGL((k_fft_pass<T, 16, true>), grid, dim3(P.nthreads), lds, st, d, P, tb);
+    else
+        hipLaunchKernelGGL((k_fft_pass<T, 16, false>), grid, dim3(P.nthreads), lds, st, d, P, tb);
+}
+
+template <typename K, typename T>
+static void launch_sort_pass(agn_ctx* ctx, const BigCurve* d, int nc, int64_t ntiles, const SortPass& P,
+                             hipStream_t st) {
+    dim3 gt((unsigned)ntiles, (unsigned)nc);
+    {
+        ProfScope ps(ctx, "sort_hist", st);
+        hipLaunchKernelGGL((k_sort_hist<K>), gt, dim3(BIG_THREADS), 0, st, d, P, ntiles);
+    }
+    {
+        ProfScope ps(ctx, "sort_scan", st);
+        hipLaunchKernelGGL(k_sort_scan_rows, dim3(256, (unsigned)nc), dim3(BIG_THREADS), 0, st, d, ntiles);
+        hipLaunchKernelGGL(k_sort_scan_digits, dim3((unsigned)nc), dim3(BIG_THREADS), 0, st, d);
+    }
+    {
+        ProfScope ps(ctx, "sort_scatter", st);
+        hipLaunchKernelGGL((k_sort_scatter<K, T>), gt, dim3(BIG_THREADS), 0, st, d, P, ntiles);
+    }
+}
+
+// All curves of one length on the multi-pass path.
+template <typename T>
+static int run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, int32_t max_iters,
+                         hipStream_t st) {
+    typedef typename key_of<T>::type K;
+    const agn_precision prec = sizeof(T) == 4 ? AGN_FP32 : AGN_FP64;
+    const int64_t M = n / 2, ntiles = n / BIG_TILE;
+    TwTable tb;
+    int rc = get_tw64(ctx, n, &tb);
+    if (rc) return rc;
+    const std::vector<int> rad = big_radices(M, prec);
+    if (rad.empty()) return fail(AGN_EUNSUPPORTED_N, "internal: no FFT plan for n=%lld", (long long)n);
+    {
+        int64_t ns = 1;
+        for (int r : rad) {
+            if ((M / r) % FFT_COLS != 0 || r > 512 || (ns > 1 && ns % FFT_COLS != 0))
+                return fail(AGN_EUNSUPPORTED_N, "internal: no FFT plan for n=%lld", (long long)n);
+            ns *= r;
+        }
+    }
+    const dim3 gt((unsigned)ntiles, (unsigned)nc);
+    hipLaunchKernelGGL(k_big_init, dim3((unsigned)nc), dim3(64), 0, st, d);
+    {
+        ProfScope ps(ctx, "big_prep", st);
+        hipLaunchKernelGGL(k_big_prep_keys, gt, dim3(BIG_THREADS), 0, st, d);
+        for (int p = 0; p < 8; ++p) {
+            SortPass P;
+            P.shift = 8 * p;
+            P.first = p == 0;
+            P.src_sel = p & 1;
+            P.mode = p == 7 ? SORT_MODE_PREP : SORT_MODE_MOVE;
+            P.rank_sel = 0;
+            launch_sort_pass<uint64_t, T>(nullptr, d, nc, ntiles, P, st);
+        }
+    }
+    hipLaunchKernelGGL(k_big_after_prep, dim3((unsigned)nc), dim3(64), 0, st, d);
+    const int npass_sort = (int)sizeof(K);
+    for (int it = 0; it < max_iters; ++it) {
+        const int cur = it & 1;
+        int sel = 0;  // region written by the next FFT pass
+        const int np = (int)rad.size();
+        int64_t Ns = 1;
+        for (int p = 0; p < np; ++p) {
+            FftPass P;
+            memset(&P, 0, sizeof(P));
+            P.M = M; P.R = rad[p]; P.nthreads = rad[p] * FFT_COLS / 16; P.Ns = Ns;
+            P.in_mode = p == 0 ? 1 : 0; P.out_mode = 0; P.inverse = 0; P.rank_sel = cur;
+            P.src_sel = 1 - sel; P.dst_sel = sel; P.sub = make_plan(rad[p]);
+            launch_fft_pass<T>(ctx, d, nc, P, tb, st);
+            Ns *= rad[p];
+            sel = 1 - sel;
+        }
+        {
+            ProfScope ps(ctx, "fold", st);
+            hipLaunchKernelGGL(k_big_fold<T>, dim3((unsigned)((M / 2 + 1 + 255) / 256), (unsigned)nc), dim3(256),
+                               0, st, d, M, 1 - sel, tb);
+        }
+        Ns = 1;
+        for (int p = 0; p < np; ++p) {
+            FftPass P;
+            memset(&P, 0, sizeof(P));
+            P.M = M; P.R = rad[p]; P.nthreads = rad[p] * FFT_COLS / 16; P.Ns = Ns;
+            P.in_mode = 0; P.out_mode = (p == np - 1) ? 1 : 0; P.inverse = 1; P.rank_sel = cur;
+            P.src_sel = 1 - sel; P.dst_sel = sel; P.sub = make_plan(rad[p]);
+            launch_fft_pass<T>(ctx, d, nc, P, tb, st);
+            Ns *= rad[p];
+            sel = 1 - sel;
+        }
+        // keys are in region (1 - sel)
+        int src = 1 - sel;
+        for (int p = 0; p < npass_sort; ++p) {
+            SortPass P;
+            P.shift = 8 * p;
+            P.first = p == 0;
+            P.src_sel = src;
+            P.mode = p == npass_sort - 1 ? SORT_MODE_RANK : SORT_MODE_MOVE;
+            P.rank_sel = 1 - cur;
+            launch_sort_pass<K, T>(ctx, d, nc, ntiles, P, st);
+            src = 1 - src;
+        }
+        {
+            ProfScope ps(ctx, "delta", st);
+            hipLaunchKernelGGL(k_big_delta, gt, dim3(BIG_THREADS), 0, st, d, 1 - cur);
+            hipLaunchKernelGGL(k_big_delta_final, dim3((unsigned)nc), dim3(BIG_THREADS), 0, st, d, it, ntiles);
+        }
+    }
+    {
+        ProfScope ps(ctx, "big_output", st);
+        hipLaunchKernelGGL(k_big_output, gt, dim3(BIG_THREADS), 0, st, d);
+    }
+    HIPCHK(hipGetLastError());
+    return AGN_OK;
+}
+
 static int run_batch(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_precision prec,
                      void* ws, size_t ws_bytes, hipStream_t st) {
     const int32_t nc = (int32_t)rq.size();
@@ -460,15 +678,25 @@ static int run_batch(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_pr
         return fail(AGN_EINVAL, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
     HIPCHK(hipSetDevice(ctx->device));
 
-    // Curves grouped by length (stable), so that each length is one launch.
+    // LDS-path curves first, then multi-pass curves; each grouped by length
+    // (stable), so that each length is one set of launches.
     std::vector<int> order(nc);
     for (int i = 0; i < nc; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return rq[a].n < rq[b].n; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const bool la = lds_path(rq[a].n, prec), lb = lds_path(rq[b].n, prec);
+        if (la != lb) return la;
+        return rq[a].n < rq[b].n;
+    });
+    int n_lds = 0;
+    while (n_lds < nc && lds_path(rq[order[n_lds]].n, prec)) ++n_lds;
 
     unsigned char* base = (unsigned char*)ws;
     LcDesc* d_lc = (LcDesc*)base;
     SpecDesc* d_sp = (SpecDesc*)(base + align256(sizeof(LcDesc) * (size_t)nc));
+    BigCurve* d_bg = (BigCurve*)(base + align256(sizeof(LcDesc) * (size_t)nc) +
+                                 align256(sizeof(SpecDesc) * (size_t)nc));
     std::vector<LcDesc> lc(nc);
+    std::vector<BigCurve> bg(nc);
     std::vector<SpecDesc> sp;
     size_t off = header_ws(nc);
     int64_t chunk0 = 0;
@@ -476,33 +704,64 @@ static int run_batch(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_pr
     for (int i = 0; i < nc; ++i) {
         const CurveReq& r = rq[order[i]];
         const int64_t n = r.n, M = n / 2;
-        LcDesc& d = lc[i];
-        memset(&d, 0, sizeof(d));
-        d.n = (int32_t)n;
-        d.iters = r.iters;
-        d.tol = tol;
-        d.x0 = r.x0;
-        d.s64 = (double*)(base + off); off += align256((size_t)n * 8);
-        d.sT = (void*)(base + off); off += align256((size_t)n * pb);
-        d.L = (double*)(base + off); off += align256((size_t)n * 8);
-        d.rank0 = (uint32_t*)(base + off); off += align256((size_t)n * 4);
-        d.valid = (int32_t*)(base + off); off += align256(16);
-        void* amp_ws = (void*)(base + off); off += align256((size_t)(M + 1) * pb);
-        double* partial = (double*)(base + off); off += align256((size_t)spec_chunks(n) * 8);
-        double* A = (double*)(base + off); off += align256(8);
-        d.x_out = r.x_out;
-        d.delta_out = r.delta_out;
-        d.iters_done = r.iters_done;
-        d.rank_out = r.rank_out;
-        const void* tw = nullptr;
-        int rc = get_twiddles(ctx, n, prec, &tw);
-        if (rc) return rc;
-        d.tw = tw;
-        d.plan = make_plan(M);
-        if (r.amp_in) {
-            d.amp = r.amp_in;
+        void* amp_ws = nullptr;
+        double* partial = nullptr;
+        double* A = nullptr;
+        if (i < n_lds) {
+            LcDesc& d = lc[i];
+            memset(&d, 0, sizeof(d));
+            d.n = (int32_t)n;
+            d.iters = r.iters;
+            d.tol = tol;
+            d.x0 = r.x0;
+            d.s64 = (double*)(base + off); off += align256((size_t)n * 8);
+            d.sT = (void*)(base + off); off += align256((size_t)n * pb);
+            d.L = (double*)(base + off); off += align256((size_t)n * 8);
+            d.rank0 = (uint32_t*)(base + off); off += align256((size_t)n * 4);
+            d.valid = (int32_t*)(base + off); off += align256(16);
+            amp_ws = (void*)(base + off); off += align256((size_t)(M + 1) * pb);
+            partial = (double*)(base + off); off += align256((size_t)spec_chunks(n) * 8);
+            A = (double*)(base + off); off += align256(8);
+            d.x_out = r.x_out;
+            d.delta_out = r.delta_out;
+            d.iters_done = r.iters_done;
+            d.rank_out = r.rank_out;
+            const void* tw = nullptr;
+            int rc = get_twiddles(ctx, n, prec, &tw);
+            if (rc) return rc;
+            d.tw = tw;
+            d.plan = make_plan(M);
+            d.amp = r.amp_in ? r.amp_in : amp_ws;
         } else {
-            d.amp = amp_ws;
+            BigCurve& d = bg[i];
+            memset(&d, 0, sizeof(d));
+            const int64_t ntiles = n / BIG_TILE;
+            d.n = n;
+            d.iters = r.iters;
+            d.tol = tol;
+            d.x0 = r.x0;
+            d.s64 = (double*)(base + off); off += align256((size_t)n * 8);
+            d.sT = (void*)(base + off); off += align256((size_t)n * pb);
+            d.L = (double*)(base + off); off += align256((size_t)n * 8);
+            d.rankA = (uint32_t*)(base + off); off += align256((size_t)n * 4);
+            d.rankB = (uint32_t*)(base + off); off += align256((size_t)n * 4);
+            d.sortA = base + off; off += align256((size_t)n * 12);
+            d.sortB = base + off; off += align256((size_t)n * 12);
+            d.hist = (uint32_t*)(base + off); off += align256((size_t)ntiles * 256 * 4);
+            d.dstart = (uint32_t*)(base + off); off += align256(256 * 4);
+            d.dpart = (double*)(base + off); off += align256((size_t)ntiles * 8);
+            d.cpart = (uint32_t*)(base + off); off += align256((size_t)ntiles * 4);
+            d.state = (int32_t*)(base + off); off += align256(16);
+            amp_ws = (void*)(base + off); off += align256((size_t)(M + 1) * pb);
+            partial = (double*)(base + off); off += align256((size_t)spec_chunks(n) * 8);
+            A = (double*)(base + off); off += align256(8);
+            d.x_out = r.x_out;
+            d.delta_out = r.delta_out;
+            d.iters_done = r.iters_done;
+            d.rank_out = r.rank_out;
+            d.amp = r.amp_in ? r.amp_in : amp_ws;
+        }
+        if (!r.amp_in) {
             SpecDesc s;
             memset(&s, 0, sizeof(s));
             s.n = n;
@@ -523,25 +782,26 @@ static int run_batch(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_pr
             sp.push_back(s);
         }
     }
-    // Upload descriptors (LcDesc block then SpecDesc block, one copy).
+    // Upload descriptors (one copy of the whole header).
     {
         std::vector<unsigned char> hdr(header_ws(nc), 0);
         memcpy(hdr.data(), lc.data(), sizeof(LcDesc) * (size_t)nc);
         if (!sp.empty())
             memcpy(hdr.data() + align256(sizeof(LcDesc) * (size_t)nc), sp.data(), sizeof(SpecDesc) * sp.size());
+        memcpy(hdr.data() + align256(sizeof(LcDesc) * (size_t)nc) + align256(sizeof(SpecDesc) * (size_t)nc),
+               bg.data(), sizeof(BigCurve) * (size_t)nc);
         int rc = stage_upload(ctx, ws, hdr.data(), hdr.size(), st);
         if (rc) return rc;
     }
     if (!sp.empty()) {
-        const int nsp = (int)sp.size();
-        launch_spectrum(ctx, d_sp, nsp, chunk0, st);
+        launch_spectrum(ctx, d_sp, (int)sp.size(), chunk0, st);
         HIPCHK(hipGetLastError());
     }
-    // One prep + iterate launch per distinct length.
+    // LDS path: one prep + iterate launch per distinct length.
     int i = 0;
-    while (i < nc) {
+    while (i < n_lds) {
         int j = i;
-        while (j < nc && lc[j].n == lc[i].n) ++j;
+        while (j < n_lds && lc[j].n == lc[i].n) ++j;
         const int64_t n = lc[i].n;
         const int E = lds_ipt(n) / 2;
         const int nt = (int)(n / lds_ipt(n));
@@ -553,6 +813,17 @@ static int run_batch(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_pr
                                     : launch_lds_E<double>(ctx, E, d_lc + i, j - i, nt, pl, il, st);
         if (rc) return rc;
         HIPCHK(hipGetLastError());
+        i = j;
+    }
+    // Multi-pass path: one launch sequence per distinct length.
+    i = n_lds;
+    while (i < nc) {
+        int j = i;
+        int32_t max_it = 0;
+        while (j < nc && bg[j].n == bg[i].n) { max_it = std::max(max_it, bg[j].iters); ++j; }
+        int rc = (prec == AGN_FP32) ? run_big_group<float>(ctx, d_bg + i, j - i, bg[i].n, max_it, st)
+                                    : run_big_group<double>(ctx, d_bg + i, j - i, bg[i].n, max_it, st);
+        if (rc) return rc;
         i = j;
     }
     return AGN_OK;

@@ -1,0 +1,555 @@
+// big_path.hpp -- the light-curve iteration (Sec. 2.1, Sec. 3.2.2) for curves
+// longer than one workgroup's LDS (up to 2^27 samples): every step is a
+// separate pass over HBM, batched over all curves of one length.
+//
+// Per iteration:
+//   FFT passes   x[n] = s[rank[n]] gathered on the fly -> ... -> X (half spectrum
+//                of length M = N/2 as a complex FFT of z[m] = x[2m] + i x[2m+1])
+//   fold pass    real-spectrum fold, modulus replacement, unfold (pairs k, M-k)
+//   IFFT passes  ... -> y, written as order-preserving integer keys
+//   sort passes  LSD radix sort of (key, sample index), 8-bit digits: per tile
+//                histogram -> per-curve scan -> stable scatter; the last pass
+//                writes rank[sample] = sorted position directly
+//   delta pass   Eq. 4 partial sums per tile, then one block per curve
+//
+// FFT pass (self-sorting Stockham step with a large radix R): butterfly j of
+// M/R reads z[j + r M/R], r < R, multiplies by W_{Ns R}^{(j mod Ns) r}, takes a
+// length-R DFT and writes output q to z[(j - j mod Ns) R + j mod Ns + q Ns].  A
+// workgroup takes 16 consecutive butterflies (16-element, 128-byte rows for
+// FP32) into LDS and runs the 16 length-R DFTs there as small Stockham passes.
+// Inter-pass twiddles W_N^t are generated in double precision from a two-level
+// table (W_N^{t_hi B} W_N^{t_lo}, B = 4096) and rounded once to the working
+// precision.
+#pragma once
+#include "common.hpp"
+#include "lds_fft.hpp"
+
+namespace agn {
+
+constexpr int BIG_TILE = 4096;       // sort / delta tile (256 threads x 16)
+constexpr int BIG_THREADS = 256;
+constexpr int BIG_IPT = 16;
+constexpr int FFT_COLS = 16;         // butterflies per FFT workgroup
+constexpr int TW_LO_BITS = 12;       // two-level twiddle split
+
+struct BigCurve {
+    int64_t n;
+    int32_t iters;
+    int32_t is_big;        // unused by kernels, kept for alignment
+    double tol;
+    const void* amp;       // T[M + 1]
+    const double* x0;      // [N] draw order
+    double* s64;           // [N]
+    void* sT;              // T[N]
+    double* L;             // [N]
+    uint32_t* rankA;       // [N] ranks after an even number of iterations
+    uint32_t* rankB;       // [N] ranks after an odd number
+    unsigned char* sortA;  // N * (sizeof(K) + 4) bytes: keys, then 32-bit values
+    unsigned char* sortB;
+    uint32_t* hist;        // 256 * ntiles digit counts, scanned in place
+    uint32_t* dstart;      // 256 digit starts
+    double* dpart;         // [ntiles] delta partial sums
+    uint32_t* cpart;       // [ntiles] changed-sample counts
+    int32_t* state;        // [0] valid, [1] active, [2] iterations done
+    double* x_out;
+    double* delta_out;     // [iters] or null
+    int32_t* iters_done;   // or null
+    uint32_t* rank_out;    // or null
+};
+
+// Two-level FP64 twiddle table for one length N: lo[u] = W_N^u, u < B;
+// hi[v] = W_N^{v B}, v < N / B (+1).
+struct TwTable {
+    const cplx<double>* lo;
+    const cplx<double>* hi;
+};
+
+// W_N^t (forward sign) in double precision, 0 <= t < N.
+AGN_DEV cplx<double> tw64(const TwTable& tb, int64_t t) {
+    const cplx<double> a = tb.hi[t >> TW_LO_BITS];
+    const cplx<double> b = tb.lo[t & ((1 << TW_LO_BITS) - 1)];
+    return cmul(a, b);
+}
+
+// ----------------------------------------------------------------------------
+// FFT pass over HBM
+// ----------------------------------------------------------------------------
+struct FftPass {
+    int64_t M;           // complex length
+    int32_t R;           // radix of this pass (<= 512)
+    int32_t nthreads;    // R * FFT_COLS / E
+    int64_t Ns;          // product of the previous radices
+    int32_t in_mode;     // 0: complex buffer, 1: gather x = sT[rank]
+    int32_t out_mode;    // 0: complex buffer, 1: keys of y (real view)
+    int32_t inverse;
+    int32_t rank_sel;    // in_mode 1: 0 = rankA, 1 = rankB
+    int32_t src_sel;     // 0: sortA, 1: sortB (complex input)
+    int32_t dst_sel;     // 0: sortA, 1: sortB (complex or key output)
+    FftPlan sub;         // radices of the in-LDS length-R DFT
+};
+
+template <typename T>
+AGN_DEV int tpad(int e) { return e + (e >> (sizeof(T) == 4 ? 5 : 4)); }
+
+// In-LDS Stockham pass over FFT_COLS independent columns: element (r, c) at
+// tpad(r * FFT_COLS + c).  Sub-twiddles come from the LDS table of R-th roots.
+template <typename T, int RR, int BMAX, bool INV>
+AGN_DEV void col_pass(cplx<T>* buf, const cplx<T>* wr, int R, int Ns, int tid, int nt) {
+    const int nb = (R / RR) * FFT_COLS;  // butterflies
+    const int RB = R / RR;
+    cplx<T> v[BMAX][RR];
+    cplx<T> w[BMAX][RR];
+    tid = opaque(tid);
+#pragma unroll
+    for (int b = 0; b < BMAX; ++b) {
+        const int q = tid + b * nt;
+        if (q < nb) {
+            const int j = q / FFT_COLS, c = q % FFT_COLS;
+#pragma unroll
+            for (int r = 0; r < RR; ++r) v[b][r] = buf[tpad<T>((j + r * RB) * FFT_COLS + c)];
+            if (Ns > 1) {
+                const int jm = j % Ns;
+                const int step = R / (Ns * RR);
+#pragma unroll
+                for (int r = 1; r < RR; ++r) {
+                    cplx<T> t = wr[(jm * r * step) % R];
+                    w[b][r] = INV ? cconj(t) : t;
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BMAX; ++b) {
+        const int q = tid + b * nt;
+        if (q < nb) {
+            const int j = q / FFT_COLS, c = q % FFT_COLS;
+            const int jm = j % Ns;
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < RR; ++r) v[b][r] = cmul(v[b][r], w[b][r]);
+            }
+            dftR<T, RR, INV>(v[b]);
+            const int d = (j - jm) * RR + jm;
+#pragma unroll
+            for (int r = 0; r < RR; ++r) buf[tpad<T>((d + r * Ns) * FFT_COLS + c)] = v[b][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int E, bool INV>
+AGN_DEV void col_fft(cplx<T>* buf, const cplx<T>* wr, int R, const FftPlan& plan, int tid, int nt) {
+    int Ns = 1;
+    for (int p = 0; p < plan.npass; ++p) {
+        const int RR = plan.radix[p];
+        if (RR == 8) col_pass<T, 8, (E + 7) / 8, INV>(buf, wr, R, Ns, tid, nt);
+        else if (RR == 4) col_pass<T, 4, (E + 3) / 4, INV>(buf, wr, R, Ns, tid, nt);
+        else if (RR == 3) col_pass<T, 3, (E + 2) / 3, INV>(buf, wr, R, Ns, tid, nt);
+        else col_pass<T, 2, (E + 1) / 2, INV>(buf, wr, R, Ns, tid, nt);
+        Ns *= RR;
+    }
+}
+
+template <typename T>
+AGN_DEV cplx<T> to_T(cplx<double> a) { return cmk((T)a.re, (T)a.im); }
+
+// grid: (M / R / FFT_COLS, curves), block: P.nthreads (E = R * FFT_COLS / nthreads).
+template <typename T, int E, bool INV>
+__global__ __launch_bounds__(512) void k_fft_pass(const BigCurve* __restrict__ cv, FftPass P, TwTable tb) {
+    typedef typename key_of<T>::type K;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const BigCurve& d = cv[blockIdx.y];
+    if (d.state[1] == 0) return;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int R = P.R;
+    const int64_t M = P.M, N = 2 * M, MR = M / R, Ns = P.Ns;
+    const int64_t j0 = (int64_t)blockIdx.x * FFT_COLS;
+    // Ns is 1 or a multiple of FFT_COLS, so (j0 + c) mod Ns = j0m + c.
+    const int64_t j0m = (Ns > 1) ? (j0 % Ns) : 0;
+    cplx<T>* buf = (cplx<T>*)smem;
+    cplx<T>* wr = (cplx<T>*)(smem + (size_t)tpad<T>(R * FFT_COLS + 1) * sizeof(cplx<T>) + 16);
+
+    // R-th roots for the in-LDS passes: W_R^u = W_N^{u N / R}.
+    for (int u = tid; u < R; u += nt) wr[u] = to_T<T>(tw64(tb, (int64_t)u * (N / R)));
+
+    // Load R rows of FFT_COLS consecutive butterflies; apply inter-pass twiddles.
+    const cplx<T>* src = (const cplx<T>*)(P.src_sel ? d.sortB : d.sortA);
+    const uint32_t* rk = P.rank_sel ? d.rankB : d.rankA;
+    const T* sT = (const T*)d.sT;
+    for (int e = tid; e < R * FFT_COLS; e += nt) {
+        const int r = e / FFT_COLS, c = e % FFT_COLS;
+        const int64_t m = j0 + c + (int64_t)r * MR;
+        cplx<T> v;
+        if (P.in_mode == 1) {
+            const uint2 rr = *(const uint2*)(rk + 2 * m);
+            v = cmk(sT[rr.x], sT[rr.y]);
+        } else {
+            v = src[m];
+        }
+        if (Ns > 1 && r > 0) {
+            const int64_t jm = j0m + c;
+            const int64_t t = jm * r * (N / (Ns * R));
+            cplx<T> w = to_T<T>(tw64(tb, t));
+            if (INV) w = cconj(w);
+            v = cmul(v, w);
+        }
+        buf[tpad<T>(e)] = v;
+    }
+    __syncthreads();
+    col_fft<T, E, INV>(buf, wr, R, P.sub, tid, nt);
+
+    // Write outputs: butterfly j = j0 + c, output q goes to (j - jm) R + jm + q Ns.
+    if (P.out_mode == 1) {
+        K* keys = (K*)(P.dst_sel ? d.sortB : d.sortA);
+        for (int e = tid; e < R * FFT_COLS; e += nt) {
+            int q, c;
+            if (Ns == 1) { c = e / R; q = e % R; } else { q = e / FFT_COLS; c = e % FFT_COLS; }
+            const int64_t jm = (Ns > 1) ? j0m + c : 0;
+            const int64_t m = (j0 + c - jm) * R + jm + (int64_t)q * Ns;
+            const cplx<T> v = buf[tpad<T>(q * FFT_COLS + c)];
+            keys[2 * m] = ord_key(v.re);
+            keys[2 * m + 1] = ord_key(v.im);
+        }
+    } else {
+        cplx<T>* dst = (cplx<T>*)(P.dst_sel ? d.sortB : d.sortA);
+        for (int e = tid; e < R * FFT_COLS; e += nt) {
+            int q, c;
+            if (Ns == 1) { c = e / R; q = e % R; } else { q = e / FFT_COLS; c = e % FFT_COLS; }
+            const int64_t jm = (Ns > 1) ? j0m + c : 0;
+            const int64_t m = (j0 + c - jm) * R + jm + (int64_t)q * Ns;
+            dst[m] = buf[tpad<T>(q * FFT_COLS + c)];
+        }
+    }
+}
+
+// Fold to the real spectrum, replace moduli, unfold (same algebra as the LDS
+// path; see lds_fold_replace).  grid: (ceil((M/2 + 1) / 256), curves).
+template <typename T>
+__global__ __launch_bounds__(256) void k_big_fold(const BigCurve* __restrict__ cv, int64_t M, int sel,
+                                                  TwTable tb) {
+    const BigCurve& d = cv[blockIdx.y];
+    if (d.state[1] == 0) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > M / 2) return;
+    cplx<T>* Z = (cplx<T>*)(sel ? d.sortB : d.sortA);
+    const T* amp = (const T*)d.amp;
+    const int64_t mk = (k == 0) ? 0 : M - k;
+    const cplx<T> zk = Z[k], zm = Z[mk];
+    const cplx<T> Ev = cmk((zk.re + zm.re) * (T)0.5, (zk.im - zm.im) * (T)0.5);
+    const cplx<T> Ov = cmk((zk.im + zm.im) * (T)0.5, (zm.re - zk.re) * (T)0.5);
+    const cplx<T> w = to_T<T>(tw64(tb, k));
+    const cplx<T> wO = cmul(w, Ov);
+    if (k == 0) {
+        const T xn = Ev.re - wO.re;
+        const T yn = (xn >= (T)0) ? amp[M] : -amp[M];
+        Z[0] = cmk(yn, -yn);
+        return;
+    }
+    const cplx<T> Xk = cadd(Ev, wO);
+    const cplx<T> Xm = cconj(csub(Ev, wO));
+    const cplx<T> Yk = replace_modulus(Xk, amp[k]);
+    const cplx<T> Ym = replace_modulus(Xm, amp[M - k]);
+    const cplx<T> A = cadd(Yk, cconj(Ym));
+    const cplx<T> B = csub(Yk, cconj(Ym));
+    const cplx<T> cwB = cmul(cconj(w), B);
+    Z[k] = cmk(A.re - cwB.im, A.im + cwB.re);
+    if (mk != k) {
+        const cplx<T> wcB = cmul(w, cconj(B));
+        Z[mk] = cmk(A.re - wcB.im, -A.im + wcB.re);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// LSD radix sort, 8-bit digits, tiles of BIG_TILE elements
+// ----------------------------------------------------------------------------
+// Element position p of a tile is held by wave p / (64 IPT), item (p mod 64 IPT)
+// / 64, lane p mod 64 (striped inside a wave, so loads are coalesced and the
+// wave ranks its items in position order).
+enum { SORT_MODE_MOVE = 0, SORT_MODE_RANK = 1, SORT_MODE_PREP = 2 };
+
+struct SortPass {
+    int32_t shift;     // digit = (key >> shift) & 255
+    int32_t first;     // 1: values are implicit (sample index)
+    int32_t src_sel;   // 0: sortA, 1: sortB
+    int32_t mode;      // SORT_MODE_*
+    int32_t rank_sel;  // MODE_RANK / PREP: 0 = rankA, 1 = rankB
+};
+
+// grid: (ntiles, curves), block 256.  hist[d * ntiles + tile] = count of digit d.
+template <typename K>
+__global__ __launch_bounds__(BIG_THREADS) void k_sort_hist(const BigCurve* __restrict__ cv, SortPass P,
+                                                           int64_t ntiles) {
+    __shared__ uint32_t h[256];
+    const BigCurve& d = cv[blockIdx.y];
+    if (d.state[1] == 0) return;
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const K* keys = (const K*)(P.src_sel ? d.sortB : d.sortA);
+    const int64_t base = (int64_t)blockIdx.x * BIG_TILE;
+    for (int i = 0; i < BIG_IPT; ++i) {
+        const K k = keys[base + i * BIG_THREADS + tid];
+        atomicAdd(&h[(uint32_t)(k >> P.shift) & 255u], 1u);
+    }
+    __syncthreads();
+    d.hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
+}
+
+// grid: (256, curves), block 256: exclusive scan of one digit's tile counts,
+// in place; the digit total goes to dstart[d] (turned into starts below).
+__global__ __launch_bounds__(BIG_THREADS) void k_sort_scan_rows(const BigCurve* __restrict__ cv,
+                                                                int64_t ntiles) {
+    __shared__ uint32_t sh[8];
+    const BigCurve& d = cv[blockIdx.y];
+    if (d.state[1] == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t* row = d.hist + (int64_t)blockIdx.x * ntiles;
+    uint32_t carry = 0;
+    for (int64_t b0 = 0; b0 < ntiles; b0 += BIG_THREADS) {
+        const int64_t i = b0 + tid;
+        const uint32_t v = (i < ntiles) ? row[i] : 0u;
+        uint32_t inc = v;
+#pragma unroll
+        for (int s = 1; s < 64; s <<= 1) {
+            const uint32_t o = __shfl_up(inc, s, 64);
+            if (lane >= s) inc += o;
+        }
+        if (lane == 63) sh[wave] = inc;
+        __syncthreads();
+        uint32_t wpre = 0;
+        for (int w = 0; w < wave; ++w) wpre += sh[w];
+        const uint32_t tot = sh[0] + sh[1] + sh[2] + sh[3];
+        if (i < ntiles) row[i] = carry + wpre + inc - v;
+        carry += tot;
+        __syncthreads();
+    }
+    if (tid == 0) d.dstart[blockIdx.x] = carry;
+}
+
+// grid: (curves), block 256: digit totals -> exclusive digit starts.
+__global__ __launch_bounds__(BIG_THREADS) void k_sort_scan_digits(const BigCurve* __restrict__ cv) {
+    __shared__ uint32_t sh[8];
+    const BigCurve& d = cv[blockIdx.x];
+    if (d.state[1] == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t v = d.dstart[tid];
+    uint32_t inc = v;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const uint32_t o = __shfl_up(inc, s, 64);
+        if (lane >= s) inc += o;
+    }
+    if (lane == 63) sh[wave] = inc;
+    __syncthreads();
+    uint32_t wpre = 0;
+    for (int w = 0; w < wave; ++w) wpre += sh[w];
+    __syncthreads();
+    d.dstart[tid] = wpre + inc - v;
+}
+
+// grid: (ntiles, curves), block 256.  Stable scatter of one 8-bit digit.
+template <typename K, typename T>
+__global__ __launch_bounds__(BIG_THREADS) void k_sort_scatter(const BigCurve* __restrict__ cv, SortPass P,
+                                                              int64_t ntiles) {
+    __shared__ uint32_t wcnt[4][256];   // per-wave running digit counters
+    __shared__ uint32_t wpre[4][256];   // exclusive prefix over waves
+    const BigCurve& d = cv[blockIdx.y];
+    if (d.state[1] == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t n = d.n;
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * BIG_TILE + (int64_t)wave * 64 * BIG_IPT;
+    const unsigned char* srcb = P.src_sel ? d.sortB : d.sortA;
+    const K* skeys = (const K*)srcb;
+    const uint32_t* svals = (const uint32_t*)(srcb + (size_t)n * sizeof(K));
+
+    for (int q = lane; q < 256; q += 64) wcnt[wave][q] = 0u;
+    __syncthreads();
+
+    K key[BIG_IPT];
+    uint32_t val[BIG_IPT];
+    uint32_t loc[BIG_IPT];
+#pragma unroll
+    for (int i = 0; i < BIG_IPT; ++i) {
+        const int64_t p = base + i * 64 + lane;
+        key[i] = skeys[p];
+        val[i] = P.first ? (uint32_t)p : svals[p];
+    }
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    volatile uint32_t* vc = wcnt[wave];
+#pragma unroll
+    for (int i = 0; i < BIG_IPT; ++i) {
+        const uint32_t dg = (uint32_t)(key[i] >> P.shift) & 255u;
+        uint64_t peers = ~0ull;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bal = __ballot((dg >> b) & 1u);
+            peers &= ((dg >> b) & 1u) ? bal : ~bal;
+        }
+        const uint32_t below = (uint32_t)__popcll(peers & lt);
+        const uint32_t cur = vc[dg];
+        __builtin_amdgcn_wave_barrier();
+        if (below == 0) vc[dg] = cur + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        loc[i] = cur + below;
+    }
+    __syncthreads();
+    // exclusive prefix of the per-wave counts, per digit (4 waves)
+    {
+        const int q = tid;  // digit
+        const uint32_t c0 = wcnt[0][q], c1 = wcnt[1][q], c2 = wcnt[2][q];
+        wpre[0][q] = 0;
+        wpre[1][q] = c0;
+        wpre[2][q] = c0 + c1;
+        wpre[3][q] = c0 + c1 + c2;
+    }
+    __syncthreads();
+    const uint32_t* hist = d.hist;
+    const uint32_t* dstart = d.dstart;
+    const T* sT = (const T*)d.sT;
+    uint32_t* rnk = P.rank_sel ? d.rankB : d.rankA;
+    unsigned char* dstb = P.src_sel ? d.sortA : d.sortB;
+    K* dkeys = (K*)dstb;
+    uint32_t* dvals = (uint32_t*)(dstb + (size_t)n * sizeof(K));
+#pragma unroll
+    for (int i = 0; i < BIG_IPT; ++i) {
+        const uint32_t dg = (uint32_t)(key[i] >> P.shift) & 255u;
+        const uint32_t dest = dstart[dg] + hist[(int64_t)dg * ntiles + tile] + wpre[wave][dg] + loc[i];
+        if (P.mode == SORT_MODE_MOVE) {
+            dkeys[dest] = key[i];
+            dvals[dest] = val[i];
+        } else if (P.mode == SORT_MODE_RANK) {
+            rnk[val[i]] = dest;
+        } else {
+            const double x = d.x0[val[i]];
+            d.s64[dest] = x;
+            ((T*)d.sT)[dest] = (T)x;
+            d.L[dest] = log10(x);
+            rnk[val[i]] = dest;
+        }
+    }
+    (void)sT;
+}
+
+// Order-preserving keys of the draw and its validity (prep, once per call).
+// grid: (ntiles, curves), block 256.
+__global__ __launch_bounds__(BIG_THREADS) void k_big_prep_keys(const BigCurve* __restrict__ cv) {
+    const BigCurve& d = cv[blockIdx.y];
+    const int64_t base = (int64_t)blockIdx.x * BIG_TILE;
+    uint64_t* keys = (uint64_t*)d.sortA;
+    int bad = 0;
+    for (int i = 0; i < BIG_IPT; ++i) {
+        const int64_t p = base + i * BIG_THREADS + threadIdx.x;
+        const double x = d.x0[p];
+        bad |= !(x > 0.0 && x <= 1.7976931348623157e308);
+        keys[p] = ord_key(x);
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicAnd(&d.state[0], 0);
+}
+
+// State init: valid = 1, active = (iters > 0), done = 0.  grid: (curves), block 64.
+__global__ void k_big_init(const BigCurve* __restrict__ cv) {
+    const BigCurve& d = cv[blockIdx.x];
+    if (threadIdx.x == 0) {
+        d.state[0] = 1;
+        d.state[1] = 1;
+        d.state[2] = 0;
+    }
+}
+
+// After prep: deactivate invalid curves and curves with nothing to do.
+__global__ void k_big_after_prep(const BigCurve* __restrict__ cv) {
+    const BigCurve& d = cv[blockIdx.x];
+    if (threadIdx.x == 0) {
+        if (d.state[0] == 0 || d.iters <= 0) d.state[1] = 0;
+    }
+}
+
+// Eq. 4 partial sums per tile.  grid: (ntiles, curves), block 256.
+__global__ __launch_bounds__(BIG_THREADS) void k_big_delta(const BigCurve* __restrict__ cv, int new_sel) {
+    __shared__ double shd[4];
+    __shared__ uint32_t shc[4];
+    const BigCurve& d = cv[blockIdx.y];
+    if (d.state[1] == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t* rn = new_sel ? d.rankB : d.rankA;
+    const uint32_t* ro = new_sel ? d.rankA : d.rankB;
+    const int64_t base = (int64_t)blockIdx.x * BIG_TILE;
+    double acc = 0.0;
+    uint32_t chg = 0;
+    for (int i = 0; i < BIG_IPT; ++i) {
+        const int64_t p = base + i * BIG_THREADS + tid;
+        const uint32_t a = rn[p], b = ro[p];
+        if (a != b) {
+            const double dl = d.L[a] - d.L[b];
+            acc += dl * dl;
+            chg += (d.s64[a] != d.s64[b]) ? 1u : 0u;
+        }
+    }
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        acc += __shfl_xor(acc, s, 64);
+        chg += __shfl_xor(chg, s, 64);
+    }
+    if (lane == 0) { shd[wave] = acc; shc[wave] = chg; }
+    __syncthreads();
+    if (tid == 0) {
+        d.dpart[blockIdx.x] = (shd[0] + shd[1]) + (shd[2] + shd[3]);
+        d.cpart[blockIdx.x] = shc[0] + shc[1] + shc[2] + shc[3];
+    }
+}
+
+// One block per curve: delta_i, iteration count, stopping rule.
+__global__ __launch_bounds__(BIG_THREADS) void k_big_delta_final(const BigCurve* __restrict__ cv, int it,
+                                                                 int64_t ntiles) {
+    __shared__ double shd[4];
+    __shared__ uint32_t shc[4];
+    const BigCurve& d = cv[blockIdx.x];
+    if (d.state[1] == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double acc = 0.0;
+    uint32_t chg = 0;
+    for (int64_t t = tid; t < ntiles; t += BIG_THREADS) {
+        acc += d.dpart[t];
+        chg += d.cpart[t];
+    }
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        acc += __shfl_xor(acc, s, 64);
+        chg += __shfl_xor(chg, s, 64);
+    }
+    if (lane == 0) { shd[wave] = acc; shc[wave] = chg; }
+    __syncthreads();
+    if (tid == 0) {
+        const double a = (shd[0] + shd[1]) + (shd[2] + shd[3]);
+        const uint32_t c = shc[0] + shc[1] + shc[2] + shc[3];
+        const double delta = sqrt(a / (double)d.n);
+        if (d.delta_out) d.delta_out[it] = delta;
+        d.state[2] = it + 1;
+        if (it + 1 >= d.iters || (d.tol >= 0.0 && (c == 0u || (d.tol > 0.0 && delta <= d.tol))))
+            d.state[1] = 0;
+    }
+}
+
+// x_out = s64[rank], rank_out, iters_done, zero-fill of unused delta entries.
+// grid: (ntiles, curves), block 256.
+__global__ __launch_bounds__(BIG_THREADS) void k_big_output(const BigCurve* __restrict__ cv) {
+    const BigCurve& d = cv[blockIdx.y];
+    const int done = d.state[2];
+    const uint32_t* r = (done & 1) ? d.rankB : d.rankA;
+    const int64_t base = (int64_t)blockIdx.x * BIG_TILE;
+    for (int i = 0; i < BIG_IPT; ++i) {
+        const int64_t p = base + i * BIG_THREADS + threadIdx.x;
+        const uint32_t k = r[p];
+        d.x_out[p] = d.s64[k];
+        if (d.rank_out) d.rank_out[p] = k;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (d.iters_done) *d.iters_done = d.state[0] ? done : -1;
+        if (d.delta_out)
+            for (int j = done; j < d.iters; ++j) d.delta_out[j] = 0.0;
+    }
+}
+
+}  // namespace agn
