@@ -26,6 +26,16 @@ class PsdParams(C.Structure):
                 ("a_low", C.c_double), ("a_high", C.c_double)]
 
 
+class ErdfParams(C.Structure):
+    """Sharp broken power law in dN/dlog10(lambda) (Eq. 1 slope convention)."""
+    _fields_ = [("u_min", C.c_double), ("u_max", C.c_double), ("u_br", C.c_double),
+                ("d1", C.c_double), ("d2", C.c_double)]
+
+
+def erdf_params(u_min=-4.0, u_max=0.0, u_br=-1.5, d1=0.4, d2=2.5):
+    return ErdfParams(float(u_min), float(u_max), float(u_br), float(d1), float(d2))
+
+
 def _load():
     global _lib
     if _lib is not None:
@@ -54,6 +64,8 @@ def _load():
     lib.agn_oracle_generate.argtypes = [C.POINTER(PsdParams), pd, i64, d, i32, d, u64, u32,
                                         pd, pd, pi32, pu32]
     lib.agn_oracle_periodogram.argtypes = [pd, i64, pd]
+    lib.agn_oracle_erdf_bpl.argtypes = [C.POINTER(ErdfParams), i64, u64, u32, pd]
+    lib.agn_oracle_erdf_bpl.restype = C.c_int
     for name in ("psd_spectrum", "dft", "rfft", "irfft", "replace", "argsort",
                  "iterate", "generate", "periodogram"):
         getattr(lib, "agn_oracle_" + name).restype = C.c_int
@@ -178,6 +190,13 @@ def generate(params: PsdParams, erdf, dt, iters, seed, curve_id=0, tol=-1.0):
                                      float(tol), int(seed), int(curve_id), _pd(x), _pd(delta),
                                      C.byref(done), _pu32(rank)), "generate")
     return x, delta[:iters], int(done.value), rank
+
+
+def erdf_bpl(params: ErdfParams, n, seed, curve_id=0):
+    out = np.full(n, np.nan, dtype=np.float64)
+    _chk(_load().agn_oracle_erdf_bpl(C.byref(params), int(n), int(seed), int(curve_id), _pd(out)),
+         "erdf_bpl")
+    return out
 
 
 def periodogram(x):

@@ -378,6 +378,40 @@ int agn_oracle_generate(const agn_oracle_psd_params* p, const double* erdf, int6
     return rc;
 }
 
+/* ------------------------------------------------------------------------ */
+/* PDF draw: inverse CDF of the sharp broken power law in u = log10(lambda). */
+/*   M1 = int_{u_min}^{u_br} 10^{-d1 (u - u_br)} du                          */
+/*      = (10^{d1 (u_br - u_min)} - 1) / (d1 ln 10)                           */
+/*   M2 = int_{u_br}^{u_max} 10^{-d2 (u - u_br)} du                          */
+/*      = (1 - 10^{-d2 (u_max - u_br)}) / (d2 ln 10)                          */
+/* t = U (M1 + M2); below the break the CDF integral equals t at             */
+/*   u = u_br - log10(10^{d1 (u_br - u_min)} - t d1 ln 10) / d1,             */
+/* above it at u = u_br - log10(1 - (t - M1) d2 ln 10) / d2.                 */
+/* ------------------------------------------------------------------------ */
+int agn_oracle_erdf_bpl(const agn_oracle_erdf_params* p, int64_t n, uint64_t seed,
+                        uint32_t curve_id, double* out)
+{
+    if (!p || !out || n < 0) return E_INVAL;
+    if (!(p->u_min < p->u_br && p->u_br < p->u_max) || !(p->d1 != 0.0) || !(p->d2 != 0.0)) return E_INVAL;
+    const double ln10 = log(10.0);
+    const double m1 = (pow(10.0, p->d1 * (p->u_br - p->u_min)) - 1.0) / (p->d1 * ln10);
+    const double m2 = (1.0 - pow(10.0, -p->d2 * (p->u_max - p->u_br))) / (p->d2 * ln10);
+    for (int64_t k = 0; k < n; ++k) {
+        const double U = agn_oracle_uniform(seed, 1, curve_id, (uint64_t)k);
+        const double t = U * (m1 + m2);
+        double u;
+        if (t < m1) {
+            u = p->u_br - log10(pow(10.0, p->d1 * (p->u_br - p->u_min)) - t * p->d1 * ln10) / p->d1;
+        } else {
+            u = p->u_br - log10(1.0 - (t - m1) * p->d2 * ln10) / p->d2;
+        }
+        if (u < p->u_min) u = p->u_min;
+        if (u > p->u_max) u = p->u_max;
+        out[k] = pow(10.0, u);
+    }
+    return E_OK;
+}
+
 /* Periodogram, Eq. A2 (Appendix A): P(f_j) = 2 / N^2 |DFT(f_j)|^2, j = 0..N/2. */
 int agn_oracle_periodogram(const double* x, int64_t n, double* P)
 {

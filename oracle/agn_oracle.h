@@ -73,6 +73,21 @@ int agn_oracle_generate(const agn_oracle_psd_params* p, const double* erdf, int6
                         uint32_t curve_id, double* x_out, double* delta_out,
                         int32_t* iters_done, uint32_t* rank_out);
 
+/* PDF draw (Sec. 2.1 step ii) from a sharp broken power law in dN/dlog10(lambda)
+ * with Eq. 1's slope convention: density 10^(-d1 (u - u_br)) below the break and
+ * 10^(-d2 (u - u_br)) above it, u = log10(lambda) in [u_min, u_max].  Inverse CDF
+ * of uniform #k of Philox stream 1 (key (seed, 1 << 32 | curve_id)); out[k] = 10^u. */
+typedef struct {
+    double u_min;
+    double u_max;
+    double u_br;
+    double d1;
+    double d2;
+} agn_oracle_erdf_params;
+
+int agn_oracle_erdf_bpl(const agn_oracle_erdf_params* p, int64_t n, uint64_t seed,
+                        uint32_t curve_id, double* out);
+
 /* Periodogram, Eq. A2: P[j] = 2/n^2 |DFT_j|^2 for j = 0..n/2. */
 int agn_oracle_periodogram(const double* x, int64_t n, double* P);
 

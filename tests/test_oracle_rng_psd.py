@@ -120,3 +120,26 @@ def test_spectrum_rejects_bad_input():
             oracle.psd_spectrum(p, n, 1.0, 0)
     with pytest.raises(oracle.OracleError):
         oracle.psd_spectrum(oracle.psd_params(0.0, -1.0, 1.0, 2.0), 8, 1.0, 0)
+
+
+def test_erdf_sampler_closed_form_cdf():
+    """PDF draw (Sec. 2.1 step ii): KS against the closed-form CDF of the
+    sharp broken power law, mass below the break, support, seeding."""
+    from paper_1909_06374_amd import synth
+    p = oracle.erdf_params()
+    lam = oracle.erdf_bpl(p, 100000, seed=9, curve_id=4)
+    u = np.log10(lam)
+    assert np.all((u >= -4.0) & (u <= 0.0))
+    assert stats.kstest(u, synth.erdf_bpl_cdf).pvalue > 1e-3
+    frac = np.mean(u < -1.5)
+    assert abs(frac - 0.98254) < 5 * math.sqrt(0.98254 * 0.01746 / len(u))
+    # uniform #k of stream 1 drives draw k through the inverse CDF
+    U = np.array([oracle.uniform(9, 1, 4, k) for k in range(50)])
+    assert np.allclose(np.log10(lam[:50]), synth.erdf_bpl_u_from_uniform(U), rtol=0, atol=1e-13)
+    assert not np.array_equal(oracle.erdf_bpl(p, 64, 9, 4), oracle.erdf_bpl(p, 64, 9, 5))
+    # other parameters: a single slope (d1 = d2) is an exponential law in u
+    q = oracle.erdf_params(-3.0, 0.0, -1.0, 1.0, 1.0)
+    u2 = np.log10(oracle.erdf_bpl(q, 50000, 1, 0))
+    lam_rate = np.log(10.0)
+    cdf = lambda x: (1 - np.exp(-lam_rate * (x + 3.0))) / (1 - np.exp(-lam_rate * 3.0))
+    assert stats.kstest(u2, cdf).pvalue > 1e-3
