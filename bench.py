@@ -53,12 +53,30 @@ def lds_bytes_per_sample_iter(n, prec_bytes):
     return fft + sort + post
 
 
+def hbm_bytes_per_sample(kernel, prec_bytes):
+    """Algorithmic HBM bytes per real sample for one launch of a multi-pass
+    kernel (average over the launches of one iteration).  FFT pass: read and
+    write the complex buffer (2 x prec bytes per sample each way).  Sort
+    scatter (8-bit LSD, key of prec bytes + 32-bit index): read key and index,
+    write both.  Histogram: read the key."""
+    if kernel == "fft_pass":
+        return 4 * prec_bytes
+    if kernel == "sort_scatter":
+        return 2 * (prec_bytes + 4)
+    if kernel == "sort_hist":
+        return prec_bytes
+    if kernel == "fold":
+        return 2 * prec_bytes + prec_bytes // 2
+    return 8
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ptf_batch", choices=["ptf_batch", "single_curve"])
+    ap.add_argument("--workload", default="ptf_batch",
+                    choices=["ptf_batch", "single_curve", "lsst_long", "lsst_long_fp64", "uneven_batch", "serving"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (reference for HBM byte counters)")
@@ -85,6 +103,12 @@ def main():
     from paper_1909_06374_amd import synth
 
     dev = "cuda:0"
+    if args.workload == "uneven_batch":
+        print(json.dumps(run_uneven(args, agn, synth, np, torch)))
+        return
+    if args.workload == "serving":
+        print(json.dumps(run_serving(args, agn, np, torch)))
+        return
     if args.workload == "ptf_batch":
         n_curves, n, iters, prec = 1024, 2**14, 100, agn.AGN_FP32
         w = synth.ptf_batch(n_curves=n_curves, n=n, seed=1)
@@ -92,12 +116,21 @@ def main():
         erdf = w["erdf"].reshape(-1)
         desc = (f"ptf_batch: {n_curves} curves x N={n}, dt=1 d, per-curve Eq.3 slopes/break, "
                 f"broken-power-law PDF draws, {iters} iterations, FP32 form")
+    elif args.workload.startswith("lsst_long"):
+        n_curves, n, iters = 4, 2**26, 100
+        prec = agn.AGN_FP64 if args.workload.endswith("fp64") else agn.AGN_FP32
+        params = [agn.psd_params(0.0, 1.0 / (10 * synth.YEAR), 1.0, 2.0)] * n_curves
+        erdf = np.concatenate([synth.erdf_draw(n, seed=2, curve_id=c) for c in range(n_curves)])
+        desc = (f"lsst_long: {n_curves} curves x N=2^26, dt=7 d (~1.29 Myr), Eq.3 slopes (1, 2), "
+                f"break 1/(10 yr), broken-power-law PDF draws, {iters} iterations, "
+                f"{'FP64' if prec == agn.AGN_FP64 else 'FP32 form'}")
     else:
         n_curves, n, iters, prec = 1, 1024, 50, agn.AGN_FP64
         w = synth.single_curve(n=n, seed=0)
         params = [agn.psd_params(**w["params"])]
         erdf = w["erdf"]
         desc = "single_curve: 1 curve x N=1024, dt=1 d, bending power law, 50 iterations, FP64"
+    dt_days = 7.0 if args.workload.startswith("lsst_long") else 1.0
 
     ns = [n] * n_curves
     offs = [c * n for c in range(n_curves)]
@@ -111,8 +144,8 @@ def main():
     ws = torch.empty(agn.agn_batch_workspace_size(ns, prec), dtype=torch.uint8, device=dev)
 
     def step():
-        agn.agn_lc_generate_batch(ctx, ns, offs, params, [1.0] * n_curves, [iters] * n_curves, seeds, ids,
-                                  erdf_t, -1.0, prec, x, delta, done, ws)
+        agn.agn_lc_generate_batch(ctx, ns, offs, params, [dt_days] * n_curves, [iters] * n_curves, seeds,
+                                  ids, erdf_t, -1.0, prec, x, delta, done, ws)
 
     for _ in range(args.warmup):
         step()
@@ -140,12 +173,19 @@ def main():
     dom = max(kt, key=lambda k: kt[k][0])
     dom_ms = kt[dom][0] / max(kt[dom][1], 1)
     pb = 4 if prec == agn.AGN_FP32 else 8
-    per = lds_bytes_per_sample_iter(n, pb)
-    lds_bytes = per * samples * iters
-    achieved = lds_bytes / (dom_ms / 1000.0) / 1e9
-    roof = {"bound": "lds", "kernel": dom, "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1),
-            "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4), "traffic": None,
-            "bytes_per_sample_iter": per, "avg_launch_ms": round(dom_ms, 4)}
+    if dom == "lds_iterate":
+        per = lds_bytes_per_sample_iter(n, pb)
+        lds_bytes = per * samples * iters
+        achieved = lds_bytes / (dom_ms / 1000.0) / 1e9
+        roof = {"bound": "lds", "kernel": dom, "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1),
+                "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_sample_iter": per, "avg_launch_ms": round(dom_ms, 4)}
+    else:
+        per = hbm_bytes_per_sample(dom, pb)
+        achieved = per * samples / (dom_ms / 1000.0) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_sample_per_launch": per, "avg_launch_ms": round(dom_ms, 4)}
 
     out = {
         "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
@@ -154,22 +194,213 @@ def main():
         "config": {"workload": desc, "n_curves": n_curves, "n": n, "iters": iters,
                    "precision": "fp32" if prec == agn.AGN_FP32 else "fp64"},
         "sample_iterations_per_s": value * iters,
+        "hbm_bytes_alloc_gib": round((ws.numel() + x.numel() * 8 + erdf_t.numel() * 8) / 2**30, 2),
         "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]},
         "roofline": roof,
     }
 
     if not args.no_cpu_baseline:
         import oracle
-        k = 4 if args.workload == "ptf_batch" else 1
+        if args.workload.startswith("lsst_long"):
+            # bounded sample: one 2^20-sample piece of the first curve, 3 iterations,
+            # scaled per sample-iteration to the full 100-iteration run
+            k, ns_, it_ = 1, 2**20, 3
+            t = time.perf_counter()
+            op = oracle.psd_params(params[0].norm, params[0].f_br, params[0].a_low, params[0].a_high)
+            oracle.generate(op, erdf[:ns_], dt_days, it_, seeds[0], ids[0])
+            el = time.perf_counter() - t
+            rate = ns_ * it_ / el / iters
+            out["cpu_baseline"] = {"value": rate, "unit": "samples/s", "cores": 1, "kind": "oracle",
+                                   "sample": f"N=2^20 x {it_} iterations of the single-threaded FP64 oracle "
+                                             f"({el:.1f} s), scaled per sample-iteration to {iters} iterations"}
+        else:
+            k = 4 if args.workload == "ptf_batch" else 1
+            t = time.perf_counter()
+            for c in range(k):
+                op = oracle.psd_params(params[c].norm, params[c].f_br, params[c].a_low, params[c].a_high)
+                oracle.generate(op, erdf[c * n:(c + 1) * n], dt_days, iters, seeds[c], ids[c])
+            el = time.perf_counter() - t
+            out["cpu_baseline"] = {"value": k * n / el, "unit": "samples/s", "cores": 1, "kind": "oracle",
+                                   "sample": f"first {k} curve(s) of the workload, all {iters} iterations, "
+                                             f"single-threaded FP64 oracle ({el:.1f} s)"}
+    print(json.dumps(out))
+
+
+def run_uneven(args, agn, synth, np, torch):
+    """Uneven batch: 8192 curves, lengths drawn uniformly from the 21 grid
+    points 2^10..2^20 and 3 * 2^9..3 * 2^18, PTF-like per-curve PSD
+    parameters, PDF draws made on the device (Philox stream 1), 100 FP32
+    iterations.  The batch is a plan captured into a HIP graph with the
+    number of concurrent launch chains chosen by the autotuner; a step is one
+    graph launch."""
+    dev = "cuda:0"
+    n_curves, iters, prec, seed = 8192, 100, agn.AGN_FP32, 3
+    ns = [int(v) for v in synth.uneven_sizes(n_curves, seed)]
+    a_low, a_high, f_b = synth.curve_params(n_curves, seed)
+    params = [agn.psd_params(0.0, f_b[c], a_low[c], a_high[c]) for c in range(n_curves)]
+    offs = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
+    total = int(np.sum(ns))
+    ctx = agn.Context(0)
+    erdf_t = torch.empty(total, dtype=torch.float64, device=dev)
+    ep = agn.erdf_params()
+    for c in range(n_curves):
+        agn.agn_erdf_draw(ctx, ep, ns[c], seed, c, erdf_t[int(offs[c]):int(offs[c]) + ns[c]])
+    x = torch.empty(total, dtype=torch.float64, device=dev)
+    delta = torch.empty(n_curves * iters, dtype=torch.float64, device=dev)
+    done = torch.empty(n_curves, dtype=torch.int32, device=dev)
+    ws = torch.empty(agn.agn_batch_workspace_size(ns, prec), dtype=torch.uint8, device=dev)
+    seeds = [1000 + c for c in range(n_curves)]
+    ids = list(range(n_curves))
+    t_plan = time.perf_counter()
+    plan = agn.agn_batch_plan_create(ctx, ns, offs, params, [1.0] * n_curves, [iters] * n_curves, seeds, ids,
+                                     erdf_t, -1.0, prec, x, delta, done,
+                                     flags=agn.AGN_PLAN_GRAPH | agn.AGN_PLAN_AUTOTUNE, ws=ws)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t_plan
+    info = plan.info()
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        agn.agn_batch_plan_launch(plan)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(args.steps):
+        agn.agn_batch_plan_launch(plan)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    assert int(done.min().item()) == iters, "a curve did not complete its iterations"
+    # kernel breakdown: one eager (non-graph) profiled run after the timed steps
+    ctx.kernel_times(reset=True)
+    ctx.set_profiling(True)
+    agn.agn_lc_generate_batch(ctx, ns, offs, params, [1.0] * n_curves, [iters] * n_curves, seeds, ids,
+                              erdf_t, -1.0, prec, x, delta, done, ws)
+    torch.cuda.synchronize()
+    ctx.set_profiling(False)
+    kt = ctx.kernel_times(reset=True)
+    value = total / (ms / 1000.0)
+    dom = max(kt, key=lambda k: kt[k][0])
+    dom_ms = kt[dom][0] / max(kt[dom][1], 1)
+    share = {k: round(v[0] / sum(u[0] for u in kt.values()), 4) for k, v in kt.items() if v[1]}
+    out = {
+        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"uneven_batch: {n_curves} curves, N uniform over the 21 lengths 2^10..2^20 and "
+                               f"3*2^9..3*2^18 (sum N = {total}), PTF-like per-curve Eq.3 parameters, device PDF "
+                               f"draws, {iters} iterations, FP32 form, HIP-graph plan",
+                   "n_curves": n_curves, "sum_n": total, "iters": iters, "precision": "fp32"},
+        "sample_iterations_per_s": value * iters,
+        "plan": dict(info, create_s=round(t_plan, 2)),
+        "hbm_bytes_alloc_gib": round((ws.numel() + x.numel() * 8 + erdf_t.numel() * 8) / 2**30, 2),
+        "kernel_time_share_eager": share,
+        "roofline": {"bound": "hbm" if dom != "lds_iterate" else "alu", "kernel": dom,
+                     "avg_launch_ms": round(dom_ms, 4), "note": "per-kernel times from one eager profiled run"},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        # bounded sample: the first curves of the batch up to 2^21 samples, 3 iterations
+        # each, scaled per sample-iteration to the full iteration count
+        k, acc = 0, 0
+        while acc < 2**21:
+            acc += ns[k]
+            k += 1
+        it_ = 3
+        host_erdf = erdf_t[:acc].cpu().numpy()
         t = time.perf_counter()
         for c in range(k):
-            op = oracle.psd_params(params[c].norm, params[c].f_br, params[c].a_low, params[c].a_high)
-            oracle.generate(op, erdf[c * n:(c + 1) * n], 1.0, iters, seeds[c], ids[c])
+            op = oracle.psd_params(0.0, float(f_b[c]), float(a_low[c]), float(a_high[c]))
+            oracle.generate(op, host_erdf[int(offs[c]):int(offs[c]) + ns[c]], 1.0, it_, seeds[c], ids[c])
         el = time.perf_counter() - t
-        out["cpu_baseline"] = {"value": k * n / el, "unit": "samples/s", "cores": 1, "kind": "oracle",
-                               "sample": f"first {k} curve(s) of the workload, all {iters} iterations, "
-                                         f"single-threaded FP64 oracle ({el:.1f} s)"}
-    print(json.dumps(out))
+        out["cpu_baseline"] = {"value": acc * it_ / el / iters, "unit": "samples/s", "cores": 1, "kind": "oracle",
+                               "sample": f"first {k} curves ({acc} samples) x {it_} iterations of the "
+                                         f"single-threaded FP64 oracle ({el:.1f} s), scaled per "
+                                         f"sample-iteration to {iters} iterations"}
+    plan.close()
+    return out
+
+
+def run_serving(args, agn, np, torch):
+    """Request serving: Poisson arrivals, N uniform over the 2^a / 3 * 2^a grid
+    in [2^12, 2^22], 50-200 iterations, PTF-like PSD parameters, FP32 form,
+    continuous batching over 4 streams with HBM-footprint admission.
+    Capacity = request rate served with every request queued at time zero;
+    then a load sweep at 25/50/75/100% of capacity and the specified 2000/s
+    offered load (each over a bounded arrival window); `value` is the
+    saturated throughput in samples/s.  Baseline: FP64, one request at a time."""
+    from paper_1909_06374_amd.serving import GpuBackend, Request, Server, make_requests
+    ctx = agn.Context(0)
+    free, _ = torch.cuda.mem_get_info(0)
+    budget = int(min(0.6 * free, 160 * 2**30))
+    be = GpuBackend(ctx, n_slots=4, prec=agn.AGN_FP32)
+    srv = Server(be, budget_bytes=budget)
+    # warm-up: one small request of each path
+    srv.run([Request(rid=10**6 + i, n=n, iters=3, f_br=0.01, a_low=1.0, a_high=2.0, seed=i, arrival=0.0)
+             for i, n in enumerate([4096, 2**20])])
+    base = make_requests(rate_hz=2000.0, duration_s=60.0, seed=4)
+    n_cap = 192
+    cap_reqs = [Request(**{**r.__dict__, "arrival": 0.0}) for r in base[:n_cap]]
+    st = srv.run(cap_reqs)
+    cap_rps = st.completed / max(r.done for r in cap_reqs)
+    cap_sps = st.samples / max(r.done for r in cap_reqs)
+    sweep = []
+    window = 6.0
+    for frac in (0.25, 0.5, 0.75, 1.0):
+        rate = frac * cap_rps
+        reqs = make_requests(rate_hz=rate, duration_s=window, seed=40 + int(100 * frac))
+        if not reqs:
+            continue
+        st = srv.run(reqs)
+        span = max(r.done for r in reqs)
+        sweep.append({"offered_frac_of_capacity": frac, "offered_req_per_s": round(rate, 2),
+                      "requests": st.completed, "p50_latency_s": round(st.latency_p50_s, 4),
+                      "p99_latency_s": round(st.latency_p99_s, 4), "samples_per_s": st.samples / span,
+                      "batches": st.batches, "mean_batch": round(st.mean_batch, 2)})
+        print(f"serving sweep {frac:.2f}: p50 {st.latency_p50_s:.3f} s p99 {st.latency_p99_s:.3f} s",
+              file=sys.stderr, flush=True)
+    spec_window = 1.0
+    reqs = make_requests(rate_hz=2000.0, duration_s=spec_window, seed=4)
+    st = srv.run(reqs)
+    span = max(r.done for r in reqs)
+    spec = {"offered_req_per_s": 2000.0, "arrival_window_s": spec_window, "requests": st.completed,
+            "p50_latency_s": round(st.latency_p50_s, 4), "p99_latency_s": round(st.latency_p99_s, 4),
+            "samples_per_s": st.samples / span, "max_footprint_gib": round(st.max_footprint / 2**30, 2)}
+    # FP64 one request at a time
+    k = 6
+    one = base[:k]
+    ws = None
+    t_ev0 = torch.cuda.Event(enable_timing=True)
+    t_ev1 = torch.cuda.Event(enable_timing=True)
+    bufs = []
+    for r in one:
+        e = torch.empty(r.n, dtype=torch.float64, device="cuda:0")
+        agn.agn_erdf_draw(ctx, agn.erdf_params(), r.n, r.seed, r.rid, e)
+        bufs.append(e)
+    mx = max(r.n for r in one)
+    ws = torch.empty(agn.agn_workspace_size(mx, agn.AGN_FP64), dtype=torch.uint8, device="cuda:0")
+    xo = torch.empty(mx, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    t_ev0.record()
+    for r, e in zip(one, bufs):
+        agn.agn_lc_generate(ctx, agn.psd_params(0.0, r.f_br, r.a_low, r.a_high), e, r.n, 1.0, r.iters, -1.0,
+                            r.seed, r.rid, agn.AGN_FP64, xo[:r.n], None, None, ws)
+        torch.cuda.synchronize()
+    t_ev1.record()
+    torch.cuda.synchronize()
+    el = t_ev0.elapsed_time(t_ev1) / 1000.0
+    fp64 = {"requests": k, "req_per_s": k / el, "samples_per_s": sum(r.n for r in one) / el,
+            "sample": f"first {k} requests of the 2000/s stream, FP64, one agn_lc_generate call each"}
+    return {
+        "metric": METRIC, "value": cap_sps, "unit": "samples/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1000.0 / cap_rps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serving: Poisson arrivals, N uniform over 2^12..2^22 (2^a and 3*2^a), 50-200 "
+                               "iterations, PTF-like PSD parameters, device PDF draws, FP32 form, 4 streams, "
+                               "HBM-footprint admission", "budget_gib": round(budget / 2**30, 1)},
+        "capacity_req_per_s": cap_rps, "capacity_requests": n_cap,
+        "load_sweep": sweep, "offered_2000_per_s": spec, "fp64_one_at_a_time": fp64,
+    }
 
 
 if __name__ == "__main__":

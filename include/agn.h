@@ -175,6 +175,72 @@ int agn_lc_generate_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n,
                           double* delta_out, int32_t* iters_done, void* ws, size_t ws_bytes,
                           void* stream);
 
+/*
+ * Batch plans -- agn_lc_generate_batch split into a set-up call and a launch
+ * call, for callers that run the same batch layout (same lengths, same device
+ * buffers) many times.  The method is the same as agn_lc_generate_batch (Sec.
+ * 2.1, Eq. 3-4): results of every launch are bit-identical to it.
+ *
+ * agn_batch_plan_create takes the arguments of agn_lc_generate_batch (same
+ * meaning, layout and ownership; the host arrays are read during the call
+ * only; the device buffers erdf, x_out, delta_out, iters_done and ws must
+ * stay allocated, and are read or written by every launch, until the plan is
+ * destroyed) plus:
+ *   flags      AGN_PLAN_GRAPH: the first launch captures the plan's kernels
+ *              into a HIP graph on a private stream; every launch replays it
+ *              with hipGraphLaunch (no per-kernel host work).
+ *              AGN_PLAN_AUTOTUNE: choose the number of concurrent launch
+ *              chains (1, 2 or 4; the lengths are dealt to chains longest
+ *              first) by timing each on the batch cut to two iterations per
+ *              curve; the choice is cached in ctx per batch layout.  This
+ *              synchronises `stream` and runs kernels that write x_out.
+ *              The chain count changes only the order in which independent
+ *              curves run, never their arithmetic.
+ *   branches   chain count when AGN_PLAN_AUTOTUNE is not set (0 or 1: one
+ *              chain; at most 8).  Chains run on plan-owned streams of
+ *              default priority that fork from and join back into the
+ *              launch stream.
+ *   out        receives the plan (destroy with agn_batch_plan_destroy).
+ * The descriptors are uploaded into ws on `stream` during create.
+ * agn_batch_plan_launch enqueues one complete run of the batch on `stream`;
+ * launches of one plan must not overlap in time (they share ws).
+ */
+typedef struct agn_batch_plan agn_batch_plan;
+enum { AGN_PLAN_GRAPH = 1, AGN_PLAN_AUTOTUNE = 2 };
+
+int agn_batch_plan_create(agn_ctx* ctx, int32_t n_curves, const int64_t* n, const int64_t* offset,
+                          const agn_psd_params* p, const double* dt, const int32_t* iters,
+                          const uint64_t* seed, const uint32_t* curve_id, const double* erdf, double tol,
+                          agn_precision prec, double* x_out, double* delta_out, int32_t* iters_done,
+                          int flags, int branches, void* ws, size_t ws_bytes, void* stream,
+                          agn_batch_plan** out);
+int agn_batch_plan_launch(agn_batch_plan* plan, void* stream);
+/* Chain count in use, number of launch groups (distinct lengths per path), 1 if graph mode. */
+int agn_batch_plan_info(const agn_batch_plan* plan, int32_t* branches, int32_t* groups, int32_t* uses_graph);
+int agn_batch_plan_destroy(agn_batch_plan* plan);
+
+/* Parameters of the PDF draw: a sharp broken power law in dN/dlog10(lambda)
+ * with the slope convention of Eq. 1 -- density 10^(-d1 (u - u_br)) below the
+ * break and 10^(-d2 (u - u_br)) above it, u = log10(lambda) in [u_min, u_max].
+ * Requires u_min < u_br < u_max and d1, d2 != 0. */
+typedef struct {
+    double u_min;
+    double u_max;
+    double u_br;
+    double d1;
+    double d2;
+} agn_erdf_params;
+
+/*
+ * agn_erdf_draw -- the PDF draw of Sec. 2.1 step (ii): n i.i.d. values of
+ * L/L_Edd, lambda = 10^u, by the closed-form inverse CDF of the broken power
+ * law applied to uniform #k of Philox stream 1 (key (seed, 1 << 32 |
+ * curve_id), same counter layout and uniform mapping as agn_psd_spectrum).
+ *   p    host parameters; out: device, n doubles, in draw order.
+ */
+int agn_erdf_draw(agn_ctx* ctx, const agn_erdf_params* p, int64_t n, uint64_t seed,
+                  uint32_t curve_id, double* out, void* stream);
+
 /* ---- instrumentation ----------------------------------------------------- */
 
 /* Turns per-kernel timing on (1) or off (0) for calls made with this context.

@@ -45,6 +45,16 @@ def psd_params(norm=0.0, f_br=1.0, a_low=1.0, a_high=2.0):
     return agn_psd_params(float(norm), float(f_br), float(a_low), float(a_high))
 
 
+class agn_erdf_params(C.Structure):
+    """Broken power law in dN/dlog10(lambda): u_min, u_max, u_br, d1, d2."""
+    _fields_ = [("u_min", C.c_double), ("u_max", C.c_double), ("u_br", C.c_double),
+                ("d1", C.c_double), ("d2", C.c_double)]
+
+
+def erdf_params(u_min=-4.0, u_max=0.0, u_br=-1.5, d1=0.4, d2=2.5):
+    return agn_erdf_params(float(u_min), float(u_max), float(u_br), float(d1), float(d2))
+
+
 def _declare(lib):
     i32, i64, u32, u64, d = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
     vp, sz = C.c_void_p, C.c_size_t
@@ -64,6 +74,12 @@ def _declare(lib):
     lib.agn_lc_generate_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_int,
                                           vp, vp, vp, vp, sz, vp]
     lib.agn_test_philox.argtypes = [u64, u64, u64, i64, vp, vp]
+    lib.agn_erdf_draw.argtypes = [vp, C.POINTER(agn_erdf_params), i64, u64, u32, vp, vp]
+    lib.agn_batch_plan_create.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_int, vp, vp, vp,
+                                          C.c_int, C.c_int, vp, sz, vp, C.POINTER(vp)]
+    lib.agn_batch_plan_launch.argtypes = [vp, vp]
+    lib.agn_batch_plan_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    lib.agn_batch_plan_destroy.argtypes = [vp]
     lib.agn_ctx_set_profiling.argtypes = [vp, C.c_int]
     lib.agn_ctx_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(d), C.POINTER(i64), C.c_int]
     lib.agn_ctx_kernel_names.argtypes = []
@@ -71,7 +87,8 @@ def _declare(lib):
     for f in ("agn_ctx_create", "agn_ctx_destroy", "agn_supported_n", "agn_spectrum_workspace_size",
               "agn_workspace_size", "agn_batch_workspace_size", "agn_psd_spectrum",
               "agn_lc_iterate", "agn_lc_generate", "agn_lc_generate_batch", "agn_test_philox",
-              "agn_ctx_set_profiling", "agn_ctx_kernel_time"):
+              "agn_ctx_set_profiling", "agn_ctx_kernel_time", "agn_erdf_draw", "agn_batch_plan_create",
+              "agn_batch_plan_launch", "agn_batch_plan_info", "agn_batch_plan_destroy"):
         getattr(lib, f).restype = C.c_int
 
 
@@ -211,6 +228,70 @@ def agn_lc_generate_batch(ctx: Context, n, offset, params, dt, iters, seed, curv
         curve_id.ctypes.data_as(vp), _ptr(erdf), float(tol), int(prec), _ptr(x_out),
         _ptr(delta_out), _ptr(iters_done), _ptr(ws),
         0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, ctx.device)))
+
+
+AGN_PLAN_GRAPH = 1
+AGN_PLAN_AUTOTUNE = 2
+
+
+class BatchPlan:
+    """Owns an agn_batch_plan and keeps the tensors it points to alive."""
+
+    def __init__(self, ctx, handle, keep):
+        self.ctx = ctx
+        self.handle = handle
+        self._keep = keep
+
+    def info(self):
+        b, g, u = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().agn_batch_plan_info(self.handle, C.byref(b), C.byref(g), C.byref(u)))
+        return {"branches": b.value, "groups": g.value, "graph": bool(u.value)}
+
+    def close(self):
+        if self.handle:
+            _check(lib().agn_batch_plan_destroy(self.handle))
+            self.handle = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def agn_batch_plan_create(ctx: Context, n, offset, params, dt, iters, seed, curve_id, erdf, tol, prec,
+                          x_out, delta_out=None, iters_done=None, flags=0, branches=0, ws=None, stream=None):
+    """Arguments of agn_lc_generate_batch plus flags (AGN_PLAN_GRAPH,
+    AGN_PLAN_AUTOTUNE) and branches; returns a BatchPlan."""
+    nc = len(n)
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    offset = np.ascontiguousarray(offset, dtype=np.int64)
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    iters = np.ascontiguousarray(iters, dtype=np.int32)
+    seed = np.ascontiguousarray(seed, dtype=np.uint64)
+    curve_id = np.ascontiguousarray(curve_id, dtype=np.uint32)
+    parr = (agn_psd_params * nc)(*params)
+    vp = C.c_void_p
+    out = vp()
+    _check(lib().agn_batch_plan_create(
+        ctx.handle, nc, n.ctypes.data_as(vp), offset.ctypes.data_as(vp), C.cast(parr, vp),
+        dt.ctypes.data_as(vp), iters.ctypes.data_as(vp), seed.ctypes.data_as(vp),
+        curve_id.ctypes.data_as(vp), _ptr(erdf), float(tol), int(prec), _ptr(x_out),
+        _ptr(delta_out), _ptr(iters_done), int(flags), int(branches), _ptr(ws),
+        0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, ctx.device), C.byref(out)))
+    return BatchPlan(ctx, out, (erdf, x_out, delta_out, iters_done, ws))
+
+
+def agn_batch_plan_launch(plan: BatchPlan, stream=None):
+    if not plan.handle:
+        raise AgnError(int(-1), "plan is closed")
+    _check(lib().agn_batch_plan_launch(plan.handle, _stream(stream, plan.ctx.device)))
+
+
+def agn_erdf_draw(ctx: Context, params, n, seed, curve_id, out, stream=None):
+    _check(lib().agn_erdf_draw(ctx.handle, C.byref(params), int(n), int(seed), int(curve_id), _ptr(out),
+                               _stream(stream, ctx.device)))
 
 
 def agn_test_philox(key0, key1, ctr0, n_blocks, out, stream=None, device=0):

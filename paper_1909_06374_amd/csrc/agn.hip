@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -18,6 +19,7 @@
 #include "../../include/agn.h"
 #include "common.hpp"
 #include "big_path.hpp"
+#include "erdf.hpp"
 #include "lds_iterate.hpp"
 #include "philox.hpp"
 #include "spectrum.hpp"
@@ -134,20 +136,21 @@ static size_t curve_ws(int64_t n, agn_precision prec) {
 }
 
 // Per-curve workspace of the multi-pass path.
+static int64_t big_npart(int64_t n) { return n / 2048 + 1; }
+
 static size_t big_curve_ws(int64_t n, agn_precision prec) {
     const size_t pb = prec_bytes(prec);
     const size_t region = (size_t)n * 12;  // max of (iteration key + value) and (64-bit key + value)
     const int64_t ntiles = n / BIG_TILE;
     size_t b = 0;
     b += align256((size_t)n * 8);           // s64
-    b += align256((size_t)n * pb);          // sT
-    b += align256((size_t)n * 8);           // L
+    b += 2 * align256((size_t)n * 8);       // X0, X1
     b += 2 * align256((size_t)n * 4);       // rankA, rankB
     b += 2 * align256(region);              // sortA, sortB
     b += align256((size_t)ntiles * 256 * 4);  // hist
     b += align256(256 * 4);                 // dstart
-    b += align256((size_t)ntiles * 8);      // dpart
-    b += align256((size_t)ntiles * 4);      // cpart
+    b += align256((size_t)big_npart(n) * 8);  // dpart
+    b += align256((size_t)big_npart(n) * 4);  // cpart
     b += align256(16);                      // state
     b += align256((size_t)(n / 2 + 1) * pb);  // amp
     b += spectrum_ws(n);
@@ -185,11 +188,12 @@ struct agn_ctx {
     std::vector<void*> tw64_mem;
     std::vector<StageSlot> ring;
     size_t ring_next = 0;
+    std::map<std::string, int> tuned;  // batch signature -> chain count chosen by the autotuner
 };
 
 static const char* KERNEL_NAMES =
     "spectrum_partial,spectrum_norm,spectrum_amp,lds_prep,lds_iterate,big_prep,fft_pass,fold,"
-    "sort_hist,sort_scan,sort_scatter,delta,big_output";
+    "sort_hist,sort_scan,sort_scatter,delta,big_output,erdf_draw,batch_graph";
 
 // Kernel timing: events recorded on the launch stream around each launch.
 struct ProfScope {
@@ -335,9 +339,9 @@ extern "C" int agn_ctx_kernel_time(agn_ctx* ctx, const char* name, double* total
     *launches = cnt;
     if (reset) {
         for (auto& r : ctx->prof_recs) {
-            hipEventSynchronize(r.b);
-            hipEventDestroy(r.a);
-            hipEventDestroy(r.b);
+            (void)hipEventSynchronize(r.b);
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
         }
         ctx->prof_recs.clear();
     }
@@ -346,19 +350,19 @@ extern "C" int agn_ctx_kernel_time(agn_ctx* ctx, const char* name, double* total
 
 extern "C" int agn_ctx_destroy(agn_ctx* ctx) {
     if (!ctx) return AGN_OK;
-    hipSetDevice(ctx->device);
+    (void)hipSetDevice(ctx->device);
     for (auto& r : ctx->prof_recs) {
-        hipEventSynchronize(r.b);
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
+        (void)hipEventSynchronize(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
     }
     for (auto& s : ctx->ring) {
-        if (s.used && s.ev) hipEventSynchronize(s.ev);
-        if (s.ev) hipEventDestroy(s.ev);
-        if (s.host) hipHostFree(s.host);
+        if (s.used && s.ev) (void)hipEventSynchronize(s.ev);
+        if (s.ev) (void)hipEventDestroy(s.ev);
+        if (s.host) (void)hipHostFree(s.host);
     }
-    for (auto& kv : ctx->tw) hipFree(kv.second);
-    for (void* p : ctx->tw64_mem) hipFree(p);
+    for (auto& kv : ctx->tw) (void)hipFree(kv.second);
+    for (void* p : ctx->tw64_mem) (void)hipFree(p);
     delete ctx;
     return AGN_OK;
 }
@@ -546,7 +550,7 @@ template <typename T>
 static void launch_fft_pass(agn_ctx* ctx, const BigCurve* d, int nc, const FftPass& P, const TwTable& tb,
                             hipStream_t st) {
     const size_t lds = (size_t)(P.R * FFT_COLS + 1 + ((P.R * FFT_COLS + 1) >> (sizeof(T) == 4 ? 5 : 4))) *
-                           sizeof(cplx<T>) + 16 + (size_t)P.R * sizeof(cplx<T>);
+                           sizeof(cplx<T>) + 16 + (size_t)P.R * sizeof(cplx<T>) + 8 * 8 + 8 * 4;
     dim3 grid((unsigned)(P.M / P.R / FFT_COLS), (unsigned)nc);
     ProfScope ps(ctx, "fft_pass", st);
     if (P.inverse)
@@ -570,30 +574,33 @@ static void launch_sort_pass(agn_ctx* ctx, const BigCurve* d, int nc, int64_t nt
     }
     {
         ProfScope ps(ctx, "sort_scatter", st);
-        hipLaunchKernelGGL((k_sort_scatter<K, T>), gt, dim3(BIG_THREADS), 0, st, d, P, ntiles);
+        hipLaunchKernelGGL((k_sort_scatter<K>), gt, dim3(BIG_THREADS), 0, st, d, P, ntiles);
     }
 }
 
-// All curves of one length on the multi-pass path.
-template <typename T>
-static int run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, int32_t max_iters,
-                         hipStream_t st) {
-    typedef typename key_of<T>::type K;
-    const agn_precision prec = sizeof(T) == 4 ? AGN_FP32 : AGN_FP64;
-    const int64_t M = n / 2, ntiles = n / BIG_TILE;
-    TwTable tb;
-    int rc = get_tw64(ctx, n, &tb);
+// Checks the multi-pass FFT plan of length n and resolves its twiddle table.
+static int big_group_setup(agn_ctx* ctx, int64_t n, agn_precision prec, TwTable* tb, std::vector<int>* rad) {
+    const int64_t M = n / 2;
+    int rc = get_tw64(ctx, n, tb);
     if (rc) return rc;
-    const std::vector<int> rad = big_radices(M, prec);
-    if (rad.empty()) return fail(AGN_EUNSUPPORTED_N, "internal: no FFT plan for n=%lld", (long long)n);
-    {
-        int64_t ns = 1;
-        for (int r : rad) {
-            if ((M / r) % FFT_COLS != 0 || r > 512 || (ns > 1 && ns % FFT_COLS != 0))
-                return fail(AGN_EUNSUPPORTED_N, "internal: no FFT plan for n=%lld", (long long)n);
-            ns *= r;
-        }
+    *rad = big_radices(M, prec);
+    if (rad->empty()) return fail(AGN_EUNSUPPORTED_N, "internal: no FFT plan for n=%lld", (long long)n);
+    int64_t ns = 1;
+    for (int r : *rad) {
+        if ((M / r) % FFT_COLS != 0 || r > 512 || (ns > 1 && ns % FFT_COLS != 0) || (ns == 1 && r < 64))
+            return fail(AGN_EUNSUPPORTED_N, "internal: no FFT plan for n=%lld", (long long)n);
+        ns *= r;
     }
+    return AGN_OK;
+}
+
+// All curves of one length on the multi-pass path (plan checked by
+// big_group_setup).  ctx may be NULL (no kernel timing, e.g. under capture).
+template <typename T>
+static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, int32_t max_iters,
+                          const TwTable& tb, const std::vector<int>& rad, hipStream_t st) {
+    typedef typename key_of<T>::type K;
+    const int64_t M = n / 2, ntiles = n / BIG_TILE;
     const dim3 gt((unsigned)ntiles, (unsigned)nc);
     hipLaunchKernelGGL(k_big_init, dim3((unsigned)nc), dim3(64), 0, st, d);
     {
@@ -611,18 +618,26 @@ static int run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, int
     }
     hipLaunchKernelGGL(k_big_after_prep, dim3((unsigned)nc), dim3(64), 0, st, d);
     const int npass_sort = (int)sizeof(K);
+    const int np = (int)rad.size();
+    const int64_t npart0 = M / rad[0] / FFT_COLS;  // blocks of the first FFT pass
     for (int it = 0; it < max_iters; ++it) {
-        const int cur = it & 1;
-        int sel = 0;  // region written by the next FFT pass
-        const int np = (int)rad.size();
+        const int cur = it & 1;  // x_it lives in X0 (even) or X1 (odd)
+        int sel = 0;             // region written by the next FFT pass
         int64_t Ns = 1;
         for (int p = 0; p < np; ++p) {
             FftPass P;
             memset(&P, 0, sizeof(P));
             P.M = M; P.R = rad[p]; P.nthreads = rad[p] * FFT_COLS / 16; P.Ns = Ns;
-            P.in_mode = p == 0 ? 1 : 0; P.out_mode = 0; P.inverse = 0; P.rank_sel = cur;
+            P.in_mode = p == 0 ? 1 : 0; P.out_mode = 0; P.inverse = 0;
+            P.x_sel = cur; P.with_delta = (p == 0 && it > 0) ? 1 : 0;
             P.src_sel = 1 - sel; P.dst_sel = sel; P.sub = make_plan(rad[p]);
             launch_fft_pass<T>(ctx, d, nc, P, tb, st);
+            if (p == 0 && it > 0) {
+                // delta of iteration it-1 (x_it against x_{it-1}); may stop the curve
+                ProfScope ps(ctx, "delta", st);
+                hipLaunchKernelGGL(k_big_delta_final, dim3((unsigned)nc), dim3(BIG_THREADS), 0, st, d, it - 1,
+                                   npart0);
+            }
             Ns *= rad[p];
             sel = 1 - sel;
         }
@@ -636,7 +651,7 @@ static int run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, int
             FftPass P;
             memset(&P, 0, sizeof(P));
             P.M = M; P.R = rad[p]; P.nthreads = rad[p] * FFT_COLS / 16; P.Ns = Ns;
-            P.in_mode = 0; P.out_mode = (p == np - 1) ? 1 : 0; P.inverse = 1; P.rank_sel = cur;
+            P.in_mode = 0; P.out_mode = (p == np - 1) ? 1 : 0; P.inverse = 1;
             P.src_sel = 1 - sel; P.dst_sel = sel; P.sub = make_plan(rad[p]);
             launch_fft_pass<T>(ctx, d, nc, P, tb, st);
             Ns *= rad[p];
@@ -654,23 +669,63 @@ static int run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, int
             launch_sort_pass<K, T>(ctx, d, nc, ntiles, P, st);
             src = 1 - src;
         }
-        {
-            ProfScope ps(ctx, "delta", st);
-            hipLaunchKernelGGL(k_big_delta, gt, dim3(BIG_THREADS), 0, st, d, 1 - cur);
-            hipLaunchKernelGGL(k_big_delta_final, dim3((unsigned)nc), dim3(BIG_THREADS), 0, st, d, it, ntiles);
-        }
+    }
+    {
+        // delta of the last iteration for curves that ran all of them
+        ProfScope ps(ctx, "delta", st);
+        hipLaunchKernelGGL(k_big_delta_last, gt, dim3(BIG_THREADS), 0, st, d, max_iters & 1);
+        hipLaunchKernelGGL(k_big_delta_final, dim3((unsigned)nc), dim3(BIG_THREADS), 0, st, d, max_iters - 1,
+                           ntiles);
     }
     {
         ProfScope ps(ctx, "big_output", st);
         hipLaunchKernelGGL(k_big_output, gt, dim3(BIG_THREADS), 0, st, d);
     }
-    HIPCHK(hipGetLastError());
-    return AGN_OK;
 }
 
-static int run_batch(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_precision prec,
-                     void* ws, size_t ws_bytes, hipStream_t st) {
+// A batch prepared for launch: descriptors resident in the workspace, one
+// launch group per curve length, twiddle tables resolved.  Enqueueing it is
+// pure kernel launches (no allocation, copy or host synchronisation), so it
+// can be replayed and captured into a HIP graph.
+struct LdsGroup {
+    int first, count, E, nt;
+    int64_t n;
+    size_t pl, il;
+};
+struct BigGroup {
+    int first, count;
+    int64_t n;
+    int32_t max_it;
+    TwTable tb;
+    std::vector<int> rad;
+};
+
+struct agn_batch_plan {
+    agn_ctx* ctx = nullptr;
+    agn_precision prec = AGN_FP32;
+    LcDesc* d_lc = nullptr;
+    SpecDesc* d_sp = nullptr;
+    BigCurve* d_bg = nullptr;
+    int nsp = 0;
+    int64_t nchunks = 0;
+    std::vector<LdsGroup> lds;
+    std::vector<BigGroup> big;
+    std::vector<double> lds_cost, big_cost;  // relative run time of each group
+    int branches = 1;                         // concurrent launch chains
+    int flags = 0;
+    std::vector<hipStream_t> aux;             // chains 1..branches-1 (default priority)
+    std::vector<hipEvent_t> ev;               // fork + one join event per chain
+    hipStream_t cap = nullptr;                // private stream graphs are captured on
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_branches = 0;                   // chain count the graph was captured with
+};
+
+static int build_plan(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_precision prec,
+                      void* ws, size_t ws_bytes, hipStream_t st, agn_batch_plan& pl) {
     const int32_t nc = (int32_t)rq.size();
+    pl.ctx = ctx;
+    pl.prec = prec;
     if (nc == 0) return AGN_OK;
     size_t need = header_ws(nc);
     for (auto& r : rq) need += curve_ws(r.n, prec);
@@ -741,16 +796,16 @@ static int run_batch(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_pr
             d.tol = tol;
             d.x0 = r.x0;
             d.s64 = (double*)(base + off); off += align256((size_t)n * 8);
-            d.sT = (void*)(base + off); off += align256((size_t)n * pb);
-            d.L = (double*)(base + off); off += align256((size_t)n * 8);
+            d.X0 = (double*)(base + off); off += align256((size_t)n * 8);
+            d.X1 = (double*)(base + off); off += align256((size_t)n * 8);
             d.rankA = (uint32_t*)(base + off); off += align256((size_t)n * 4);
             d.rankB = (uint32_t*)(base + off); off += align256((size_t)n * 4);
             d.sortA = base + off; off += align256((size_t)n * 12);
             d.sortB = base + off; off += align256((size_t)n * 12);
             d.hist = (uint32_t*)(base + off); off += align256((size_t)ntiles * 256 * 4);
             d.dstart = (uint32_t*)(base + off); off += align256(256 * 4);
-            d.dpart = (double*)(base + off); off += align256((size_t)ntiles * 8);
-            d.cpart = (uint32_t*)(base + off); off += align256((size_t)ntiles * 4);
+            d.dpart = (double*)(base + off); off += align256((size_t)big_npart(n) * 8);
+            d.cpart = (uint32_t*)(base + off); off += align256((size_t)big_npart(n) * 4);
             d.state = (int32_t*)(base + off); off += align256(16);
             amp_ws = (void*)(base + off); off += align256((size_t)(M + 1) * pb);
             partial = (double*)(base + off); off += align256((size_t)spec_chunks(n) * 8);
@@ -793,40 +848,136 @@ static int run_batch(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_pr
         int rc = stage_upload(ctx, ws, hdr.data(), hdr.size(), st);
         if (rc) return rc;
     }
-    if (!sp.empty()) {
-        launch_spectrum(ctx, d_sp, (int)sp.size(), chunk0, st);
-        HIPCHK(hipGetLastError());
-    }
+    pl.d_lc = d_lc;
+    pl.d_sp = d_sp;
+    pl.d_bg = d_bg;
+    pl.nsp = (int)sp.size();
+    pl.nchunks = chunk0;
     // LDS path: one prep + iterate launch per distinct length.
     int i = 0;
     while (i < n_lds) {
         int j = i;
         while (j < n_lds && lc[j].n == lc[i].n) ++j;
-        const int64_t n = lc[i].n;
-        const int E = lds_ipt(n) / 2;
-        const int nt = (int)(n / lds_ipt(n));
-        const size_t pl = lds_prep_bytes(n), il = lds_iter_bytes(n, prec);
-        if (pl > ctx->lds_max || il > ctx->lds_max)
+        LdsGroup g;
+        g.first = i;
+        g.count = j - i;
+        g.n = lc[i].n;
+        g.E = lds_ipt(g.n) / 2;
+        g.nt = (int)(g.n / lds_ipt(g.n));
+        g.pl = lds_prep_bytes(g.n);
+        g.il = lds_iter_bytes(g.n, prec);
+        if (g.pl > ctx->lds_max || g.il > ctx->lds_max)
             return fail(AGN_EUNSUPPORTED_N, "n=%lld needs %zu bytes of LDS per workgroup; the device allows %zu",
-                        (long long)n, std::max(pl, il), ctx->lds_max);
-        int rc = (prec == AGN_FP32) ? launch_lds_E<float>(ctx, E, d_lc + i, j - i, nt, pl, il, st)
-                                    : launch_lds_E<double>(ctx, E, d_lc + i, j - i, nt, pl, il, st);
-        if (rc) return rc;
-        HIPCHK(hipGetLastError());
+                        (long long)g.n, std::max(g.pl, g.il), ctx->lds_max);
+        int32_t max_it = 0;
+        for (int k = i; k < j; ++k) max_it = std::max(max_it, lc[k].iters);
+        pl.lds.push_back(g);
+        pl.lds_cost.push_back((double)g.count * (double)g.n * (1.0 + max_it));
         i = j;
     }
     // Multi-pass path: one launch sequence per distinct length.
     i = n_lds;
     while (i < nc) {
         int j = i;
-        int32_t max_it = 0;
-        while (j < nc && bg[j].n == bg[i].n) { max_it = std::max(max_it, bg[j].iters); ++j; }
-        int rc = (prec == AGN_FP32) ? run_big_group<float>(ctx, d_bg + i, j - i, bg[i].n, max_it, st)
-                                    : run_big_group<double>(ctx, d_bg + i, j - i, bg[i].n, max_it, st);
+        BigGroup g;
+        g.max_it = 0;
+        while (j < nc && bg[j].n == bg[i].n) { g.max_it = std::max(g.max_it, bg[j].iters); ++j; }
+        g.first = i;
+        g.count = j - i;
+        g.n = bg[i].n;
+        int rc = big_group_setup(ctx, g.n, prec, &g.tb, &g.rad);
         if (rc) return rc;
+        // per sample-iteration the multi-pass path takes about 3x the LDS path
+        pl.big_cost.push_back(3.0 * (double)g.count * (double)g.n * (1.0 + g.max_it));
+        pl.big.push_back(std::move(g));
         i = j;
     }
     return AGN_OK;
+}
+
+static void enqueue_group(const agn_batch_plan& pl, agn_ctx* pctx, bool is_big, int k, hipStream_t st) {
+    if (!is_big) {
+        const LdsGroup& g = pl.lds[k];
+        if (pl.prec == AGN_FP32) launch_lds_E<float>(pctx, g.E, pl.d_lc + g.first, g.count, g.nt, g.pl, g.il, st);
+        else launch_lds_E<double>(pctx, g.E, pl.d_lc + g.first, g.count, g.nt, g.pl, g.il, st);
+    } else {
+        const BigGroup& g = pl.big[k];
+        if (pl.prec == AGN_FP32) run_big_group<float>(pctx, pl.d_bg + g.first, g.count, g.n, g.max_it, g.tb, g.rad, st);
+        else run_big_group<double>(pctx, pl.d_bg + g.first, g.count, g.n, g.max_it, g.tb, g.rad, st);
+    }
+}
+
+// Launches the plan's kernels on st; with more than one chain the groups are
+// dealt to the chains longest first (each to the least loaded chain) and the
+// chains fork from and join back into st.  pctx NULL: no kernel timing.
+static int enqueue_plan(agn_batch_plan& pl, agn_ctx* pctx, int branches, hipStream_t st) {
+    if (pl.nsp > 0) launch_spectrum(pctx, pl.d_sp, pl.nsp, pl.nchunks, st);
+    const int ng = (int)(pl.lds.size() + pl.big.size());
+    branches = std::max(1, std::min(branches, ng));
+    if (branches == 1) {
+        for (int k = 0; k < (int)pl.lds.size(); ++k) enqueue_group(pl, pctx, false, k, st);
+        for (int k = 0; k < (int)pl.big.size(); ++k) enqueue_group(pl, pctx, true, k, st);
+        HIPCHK(hipGetLastError());
+        return AGN_OK;
+    }
+    while ((int)pl.aux.size() < branches - 1) {
+        hipStream_t s = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        pl.aux.push_back(s);
+    }
+    while ((int)pl.ev.size() < branches) {
+        hipEvent_t e = nullptr;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        pl.ev.push_back(e);
+    }
+    std::vector<std::pair<double, int>> order;  // (cost, group id; big groups offset by nlds)
+    const int nl = (int)pl.lds.size();
+    for (int k = 0; k < nl; ++k) order.push_back({pl.lds_cost[k], k});
+    for (int k = 0; k < (int)pl.big.size(); ++k) order.push_back({pl.big_cost[k], nl + k});
+    std::stable_sort(order.begin(), order.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+        return a.first > b.first;
+    });
+    std::vector<double> load(branches, 0.0);
+    std::vector<std::vector<int>> chain(branches);
+    for (auto& o : order) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[b] += o.first;
+        chain[b].push_back(o.second);
+    }
+    HIPCHK(hipEventRecord(pl.ev[0], st));
+    for (int b = 1; b < branches; ++b) HIPCHK(hipStreamWaitEvent(pl.aux[b - 1], pl.ev[0], 0));
+    for (int b = 0; b < branches; ++b) {
+        hipStream_t s = b == 0 ? st : pl.aux[b - 1];
+        for (int g : chain[b]) enqueue_group(pl, pctx, g >= nl, g >= nl ? g - nl : g, s);
+    }
+    HIPCHK(hipGetLastError());
+    for (int b = 1; b < branches; ++b) {
+        HIPCHK(hipEventRecord(pl.ev[b], pl.aux[b - 1]));
+        HIPCHK(hipStreamWaitEvent(st, pl.ev[b], 0));
+    }
+    return AGN_OK;
+}
+
+static void destroy_plan_resources(agn_batch_plan& pl) {
+    if (pl.exec) (void)hipGraphExecDestroy(pl.exec);
+    if (pl.graph) (void)hipGraphDestroy(pl.graph);
+    pl.exec = nullptr;
+    pl.graph = nullptr;
+    for (hipStream_t s : pl.aux) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); }
+    for (hipEvent_t e : pl.ev) (void)hipEventDestroy(e);
+    if (pl.cap) (void)hipStreamDestroy(pl.cap);
+    pl.aux.clear();
+    pl.ev.clear();
+    pl.cap = nullptr;
+}
+
+static int run_batch(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_precision prec,
+                     void* ws, size_t ws_bytes, hipStream_t st) {
+    if (rq.empty()) return AGN_OK;
+    agn_batch_plan pl;
+    int rc = build_plan(ctx, rq, tol, prec, ws, ws_bytes, st, pl);
+    if (rc) return rc;
+    return enqueue_plan(pl, ctx, 1, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -898,13 +1049,10 @@ extern "C" int agn_lc_generate(agn_ctx* ctx, const agn_psd_params* p, const doub
     return run_batch(ctx, rq, tol, prec, ws, ws_bytes, (hipStream_t)stream);
 }
 
-extern "C" int agn_lc_generate_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n,
-                                     const int64_t* offset, const agn_psd_params* p, const double* dt,
-                                     const int32_t* iters, const uint64_t* seed,
-                                     const uint32_t* curve_id, const double* erdf, double tol,
-                                     agn_precision prec, double* x_out, double* delta_out,
-                                     int32_t* iters_done, void* ws, size_t ws_bytes, void* stream) {
-    if (!ctx) return fail(AGN_EINVAL, "ctx is NULL");
+static int batch_requests(int32_t n_curves, const int64_t* n, const int64_t* offset, const agn_psd_params* p,
+                          const double* dt, const int32_t* iters, const uint64_t* seed, const uint32_t* curve_id,
+                          const double* erdf, double tol, agn_precision prec, double* x_out, double* delta_out,
+                          int32_t* iters_done, std::vector<CurveReq>& rq) {
     if (n_curves < 0) return fail(AGN_EINVAL, "n_curves < 0");
     if (n_curves == 0) return AGN_OK;
     if (!n || !offset || !p || !dt || !iters || !seed || !curve_id || !erdf || !x_out)
@@ -925,7 +1073,7 @@ extern "C" int agn_lc_generate_batch(agn_ctx* ctx, int32_t n_curves, const int64
     std::sort(spans.begin(), spans.end());
     for (size_t i = 1; i < spans.size(); ++i)
         if (spans[i].first < spans[i - 1].second) return fail(AGN_EINVAL, "curves overlap in erdf/x_out");
-    std::vector<CurveReq> rq(n_curves);
+    rq.resize(n_curves);
     for (int32_t c = 0; c < n_curves; ++c) {
         CurveReq& r = rq[c];
         memset(&r, 0, sizeof(r));
@@ -936,7 +1084,198 @@ extern "C" int agn_lc_generate_batch(agn_ctx* ctx, int32_t n_curves, const int64
         r.delta_out = delta_out ? delta_out + (size_t)c * max_it : nullptr;
         r.iters_done = iters_done ? iters_done + c : nullptr;
     }
+    return AGN_OK;
+}
+
+extern "C" int agn_lc_generate_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n,
+                                     const int64_t* offset, const agn_psd_params* p, const double* dt,
+                                     const int32_t* iters, const uint64_t* seed,
+                                     const uint32_t* curve_id, const double* erdf, double tol,
+                                     agn_precision prec, double* x_out, double* delta_out,
+                                     int32_t* iters_done, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx) return fail(AGN_EINVAL, "ctx is NULL");
+    std::vector<CurveReq> rq;
+    int rc = batch_requests(n_curves, n, offset, p, dt, iters, seed, curve_id, erdf, tol, prec, x_out, delta_out,
+                            iters_done, rq);
+    if (rc) return rc;
     return run_batch(ctx, rq, tol, prec, ws, ws_bytes, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// batch plans: build once, launch many times (optionally as a HIP graph)
+// ---------------------------------------------------------------------------
+static std::string plan_signature(const agn_batch_plan& pl) {
+    std::string sig = pl.prec == AGN_FP32 ? "f32" : "f64";
+    char buf[96];
+    for (const auto& g : pl.lds) {
+        snprintf(buf, sizeof(buf), "|L%lld:%d", (long long)g.n, g.count);
+        sig += buf;
+    }
+    for (const auto& g : pl.big) {
+        snprintf(buf, sizeof(buf), "|B%lld:%d", (long long)g.n, g.count);
+        sig += buf;
+    }
+    return sig;
+}
+
+// Times each candidate chain count on a copy of the batch with at most two
+// iterations per curve (same workspace, so the real plan is built after it)
+// and returns the fastest.  Synchronises st.
+static int autotune_branches(agn_ctx* ctx, std::vector<CurveReq> rq, double tol, agn_precision prec, void* ws,
+                             size_t ws_bytes, hipStream_t st, int* best) {
+    for (auto& r : rq) {
+        r.iters = std::min(r.iters, 2);
+        r.delta_out = nullptr;  // the real plan's delta rows are laid out for its own iteration count
+    }
+    agn_batch_plan tp;
+    int rc = build_plan(ctx, rq, tol, prec, ws, ws_bytes, st, tp);
+    if (rc) { destroy_plan_resources(tp); return rc; }
+    const int ng = (int)(tp.lds.size() + tp.big.size());
+    const int cand[3] = {1, 2, 4};
+    hipEvent_t a = nullptr, b = nullptr;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    float best_ms = 0.f;
+    *best = 1;
+    rc = AGN_OK;
+    for (int ci = 0; ci < 3 && rc == AGN_OK; ++ci) {
+        if (cand[ci] > 1 && cand[ci] > ng) break;
+        float m = 0.f;
+        for (int rep = 0; rep < 3 && rc == AGN_OK; ++rep) {  // first run warms up
+            if (hipEventRecord(a, st) != hipSuccess) { rc = fail(AGN_EDEVICE, "event record failed"); break; }
+            rc = enqueue_plan(tp, nullptr, cand[ci], st);
+            if (rc) break;
+            if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+                rc = fail(AGN_EDEVICE, "event wait failed");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, a, b);
+            if (rep == 1 || (rep == 2 && ms < m)) m = ms;
+        }
+        if (rc == AGN_OK && (ci == 0 || m < best_ms)) { best_ms = m; *best = cand[ci]; }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    destroy_plan_resources(tp);
+    return rc;
+}
+
+extern "C" int agn_batch_plan_create(agn_ctx* ctx, int32_t n_curves, const int64_t* n, const int64_t* offset,
+                                     const agn_psd_params* p, const double* dt, const int32_t* iters,
+                                     const uint64_t* seed, const uint32_t* curve_id, const double* erdf,
+                                     double tol, agn_precision prec, double* x_out, double* delta_out,
+                                     int32_t* iters_done, int flags, int branches, void* ws, size_t ws_bytes,
+                                     void* stream, agn_batch_plan** out) {
+    if (!ctx || !out) return fail(AGN_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (flags & ~(AGN_PLAN_GRAPH | AGN_PLAN_AUTOTUNE)) return fail(AGN_EINVAL, "unknown plan flags 0x%x", flags);
+    if (branches < 0 || branches > 8) return fail(AGN_EINVAL, "branches must be 0..8");
+    std::vector<CurveReq> rq;
+    int rc = batch_requests(n_curves, n, offset, p, dt, iters, seed, curve_id, erdf, tol, prec, x_out, delta_out,
+                            iters_done, rq);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    std::unique_ptr<agn_batch_plan> pl(new agn_batch_plan());
+    pl->flags = flags;
+    if ((rc = build_plan(ctx, rq, tol, prec, ws, ws_bytes, st, *pl))) { destroy_plan_resources(*pl); return rc; }
+    int nb = branches > 0 ? branches : 1;
+    if ((flags & AGN_PLAN_AUTOTUNE) && !rq.empty()) {
+        const std::string sig = plan_signature(*pl);
+        bool hit = false;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            auto it = ctx->tuned.find(sig);
+            if (it != ctx->tuned.end()) { nb = it->second; hit = true; }
+        }
+        if (!hit) {
+            if ((rc = autotune_branches(ctx, rq, tol, prec, ws, ws_bytes, st, &nb))) {
+                destroy_plan_resources(*pl);
+                return rc;
+            }
+            // the tuning runs overwrote the descriptors: build the real plan again
+            destroy_plan_resources(*pl);
+            pl.reset(new agn_batch_plan());
+            pl->flags = flags;
+            if ((rc = build_plan(ctx, rq, tol, prec, ws, ws_bytes, st, *pl))) {
+                destroy_plan_resources(*pl);
+                return rc;
+            }
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->tuned[sig] = nb;
+        }
+    }
+    pl->branches = nb;
+    *out = pl.release();
+    return AGN_OK;
+}
+
+extern "C" int agn_batch_plan_launch(agn_batch_plan* pl, void* stream) {
+    if (!pl) return fail(AGN_EINVAL, "plan is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    agn_ctx* ctx = pl->ctx;
+    HIPCHK(hipSetDevice(ctx->device));
+    if (!(pl->flags & AGN_PLAN_GRAPH)) return enqueue_plan(*pl, ctx, pl->branches, st);
+    if (!pl->exec || pl->graph_branches != pl->branches) {
+        if (pl->exec) { (void)hipGraphExecDestroy(pl->exec); pl->exec = nullptr; }
+        if (pl->graph) { (void)hipGraphDestroy(pl->graph); pl->graph = nullptr; }
+        if (!pl->cap) HIPCHK(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_plan(*pl, nullptr, pl->branches, pl->cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(pl->cap, &g);
+        if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+        if (e != hipSuccess) return fail(AGN_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        pl->graph = g;
+        HIPCHK(hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0));
+        pl->graph_branches = pl->branches;
+    }
+    {
+        ProfScope ps(ctx, "batch_graph", st);
+        HIPCHK(hipGraphLaunch(pl->exec, st));
+    }
+    return AGN_OK;
+}
+
+extern "C" int agn_batch_plan_info(const agn_batch_plan* pl, int32_t* branches, int32_t* groups,
+                                   int32_t* uses_graph) {
+    if (!pl) return fail(AGN_EINVAL, "plan is NULL");
+    if (branches) *branches = pl->branches;
+    if (groups) *groups = (int32_t)(pl->lds.size() + pl->big.size());
+    if (uses_graph) *uses_graph = (pl->flags & AGN_PLAN_GRAPH) ? 1 : 0;
+    return AGN_OK;
+}
+
+extern "C" int agn_batch_plan_destroy(agn_batch_plan* pl) {
+    if (!pl) return AGN_OK;
+    (void)hipSetDevice(pl->ctx ? pl->ctx->device : 0);
+    destroy_plan_resources(*pl);
+    delete pl;
+    return AGN_OK;
+}
+
+extern "C" int agn_erdf_draw(agn_ctx* ctx, const agn_erdf_params* p, int64_t n, uint64_t seed,
+                             uint32_t curve_id, double* out, void* stream) {
+    if (!ctx || !p || (n > 0 && !out)) return fail(AGN_EINVAL, "NULL argument");
+    if (n < 0) return fail(AGN_EINVAL, "n < 0");
+    if (!(p->u_min < p->u_br && p->u_br < p->u_max) || p->d1 == 0.0 || p->d2 == 0.0 ||
+        !std::isfinite(p->u_min) || !std::isfinite(p->u_max) || !std::isfinite(p->d1) || !std::isfinite(p->d2))
+        return fail(AGN_EINVAL, "invalid PDF parameters");
+    if (n == 0) return AGN_OK;
+    HIPCHK(hipSetDevice(ctx->device));
+    const double ln10 = std::log(10.0);
+    ErdfDraw P;
+    P.u_min = p->u_min; P.u_max = p->u_max; P.u_br = p->u_br; P.d1 = p->d1; P.d2 = p->d2;
+    P.a1 = std::pow(10.0, p->d1 * (p->u_br - p->u_min));
+    P.m1 = (P.a1 - 1.0) / (p->d1 * ln10);
+    P.m2 = (1.0 - std::pow(10.0, -p->d2 * (p->u_max - p->u_br))) / (p->d2 * ln10);
+    P.n = n; P.seed = seed; P.curve_id = curve_id; P.out = out;
+    {
+        ProfScope ps(ctx, "erdf_draw", (hipStream_t)stream);
+        hipLaunchKernelGGL(k_erdf_draw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, P);
+    }
+    HIPCHK(hipGetLastError());
+    return AGN_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -2,15 +2,17 @@
 // longer than one workgroup's LDS (up to 2^27 samples): every step is a
 // separate pass over HBM, batched over all curves of one length.
 //
-// Per iteration:
-//   FFT passes   x[n] = s[rank[n]] gathered on the fly -> ... -> X (half spectrum
-//                of length M = N/2 as a complex FFT of z[m] = x[2m] + i x[2m+1])
+// Per iteration i (x_i is kept in time order, FP64, two buffers):
+//   FFT passes   the first pass reads x_i and x_{i-1} in time order, adds the
+//                Eq. 4 terms log10(x_i / x_{i-1})^2 of the previous iteration to
+//                per-block partials, and feeds z[m] = x[2m] + i x[2m+1]
 //   fold pass    real-spectrum fold, modulus replacement, unfold (pairs k, M-k)
 //   IFFT passes  ... -> y, written as order-preserving integer keys
 //   sort passes  LSD radix sort of (key, sample index), 8-bit digits: per tile
-//                histogram -> per-curve scan -> stable scatter; the last pass
-//                writes rank[sample] = sorted position directly
-//   delta pass   Eq. 4 partial sums per tile, then one block per curve
+//                histogram -> per-curve scan -> stable scatter staged through
+//                LDS in digit order, so global writes are contiguous runs; the
+//                last pass writes x_{i+1}[sample] = s[sorted position] into the
+//                other series buffer (the sorted values are read contiguously)
 //
 // FFT pass (self-sorting Stockham step with a large radix R): butterfly j of
 // M/R reads z[j + r M/R], r < R, multiplies by W_{Ns R}^{(j mod Ns) r}, takes a
@@ -39,17 +41,17 @@ struct BigCurve {
     double tol;
     const void* amp;       // T[M + 1]
     const double* x0;      // [N] draw order
-    double* s64;           // [N]
-    void* sT;              // T[N]
-    double* L;             // [N]
-    uint32_t* rankA;       // [N] ranks after an even number of iterations
-    uint32_t* rankB;       // [N] ranks after an odd number
-    unsigned char* sortA;  // N * (sizeof(K) + 4) bytes: keys, then 32-bit values
+    double* s64;           // [N] sorted draw
+    double* X0;            // [N] x_i for even i (time order)
+    double* X1;            // [N] x_i for odd i
+    uint32_t* rankA;       // [N] ranks of x_i, even i (kept only if rank_out)
+    uint32_t* rankB;       // [N] ranks of x_i, odd i
+    unsigned char* sortA;  // N * 12 bytes: keys, then 32-bit values
     unsigned char* sortB;
     uint32_t* hist;        // 256 * ntiles digit counts, scanned in place
     uint32_t* dstart;      // 256 digit starts
-    double* dpart;         // [ntiles] delta partial sums
-    uint32_t* cpart;       // [ntiles] changed-sample counts
+    double* dpart;         // [npart] delta partial sums
+    uint32_t* cpart;       // [npart] changed-sample counts
     int32_t* state;        // [0] valid, [1] active, [2] iterations done
     double* x_out;
     double* delta_out;     // [iters] or null
@@ -79,10 +81,11 @@ struct FftPass {
     int32_t R;           // radix of this pass (<= 512)
     int32_t nthreads;    // R * FFT_COLS / E
     int64_t Ns;          // product of the previous radices
-    int32_t in_mode;     // 0: complex buffer, 1: gather x = sT[rank]
+    int32_t in_mode;     // 0: complex buffer, 1: series x_i (FP64, time order)
     int32_t out_mode;    // 0: complex buffer, 1: keys of y (real view)
     int32_t inverse;
-    int32_t rank_sel;    // in_mode 1: 0 = rankA, 1 = rankB
+    int32_t x_sel;       // in_mode 1: x_i in X0 (0) or X1 (1)
+    int32_t with_delta;  // in_mode 1: add Eq. 4 terms of x_i against x_{i-1}
     int32_t src_sel;     // 0: sortA, 1: sortB (complex input)
     int32_t dst_sel;     // 0: sortA, 1: sortB (complex or key output)
     FftPlan sub;         // radices of the in-LDS length-R DFT
@@ -97,6 +100,7 @@ template <typename T, int RR, int BMAX, bool INV>
 AGN_DEV void col_pass(cplx<T>* buf, const cplx<T>* wr, int R, int Ns, int tid, int nt) {
     const int nb = (R / RR) * FFT_COLS;  // butterflies
     const int RB = R / RR;
+    const bool pow2 = (Ns & (Ns - 1)) == 0;
     cplx<T> v[BMAX][RR];
     cplx<T> w[BMAX][RR];
     tid = opaque(tid);
@@ -108,11 +112,12 @@ AGN_DEV void col_pass(cplx<T>* buf, const cplx<T>* wr, int R, int Ns, int tid, i
 #pragma unroll
             for (int r = 0; r < RR; ++r) v[b][r] = buf[tpad<T>((j + r * RB) * FFT_COLS + c)];
             if (Ns > 1) {
-                const int jm = j % Ns;
+                const int jm = pow2 ? (j & (Ns - 1)) : (j % Ns);
                 const int step = R / (Ns * RR);
+                // jm * r * step < Ns * RR * R / (Ns * RR) = R
 #pragma unroll
                 for (int r = 1; r < RR; ++r) {
-                    cplx<T> t = wr[(jm * r * step) % R];
+                    cplx<T> t = wr[jm * r * step];
                     w[b][r] = INV ? cconj(t) : t;
                 }
             }
@@ -124,7 +129,7 @@ AGN_DEV void col_pass(cplx<T>* buf, const cplx<T>* wr, int R, int Ns, int tid, i
         const int q = tid + b * nt;
         if (q < nb) {
             const int j = q / FFT_COLS, c = q % FFT_COLS;
-            const int jm = j % Ns;
+            const int jm = pow2 ? (j & (Ns - 1)) : (j % Ns);
             if (Ns > 1) {
 #pragma unroll
                 for (int r = 1; r < RR; ++r) v[b][r] = cmul(v[b][r], w[b][r]);
@@ -169,32 +174,74 @@ __global__ __launch_bounds__(512) void k_fft_pass(const BigCurve* __restrict__ c
     const int64_t j0m = (Ns > 1) ? (j0 % Ns) : 0;
     cplx<T>* buf = (cplx<T>*)smem;
     cplx<T>* wr = (cplx<T>*)(smem + (size_t)tpad<T>(R * FFT_COLS + 1) * sizeof(cplx<T>) + 16);
+    double* red = (double*)(wr + R);         // 8 doubles
+    uint32_t* redc = (uint32_t*)(red + 8);   // 8 words
+
 
     // R-th roots for the in-LDS passes: W_R^u = W_N^{u N / R}.
     for (int u = tid; u < R; u += nt) wr[u] = to_T<T>(tw64(tb, (int64_t)u * (N / R)));
 
     // Load R rows of FFT_COLS consecutive butterflies; apply inter-pass twiddles.
     const cplx<T>* src = (const cplx<T>*)(P.src_sel ? d.sortB : d.sortA);
-    const uint32_t* rk = P.rank_sel ? d.rankB : d.rankA;
-    const T* sT = (const T*)d.sT;
-    for (int e = tid; e < R * FFT_COLS; e += nt) {
-        const int r = e / FFT_COLS, c = e % FFT_COLS;
-        const int64_t m = j0 + c + (int64_t)r * MR;
-        cplx<T> v;
-        if (P.in_mode == 1) {
-            const uint2 rr = *(const uint2*)(rk + 2 * m);
-            v = cmk(sT[rr.x], sT[rr.y]);
-        } else {
-            v = src[m];
+    const double* xc = P.x_sel ? d.X1 : d.X0;
+    const double* xp = P.x_sel ? d.X0 : d.X1;
+    double acc = 0.0;
+    uint32_t chg = 0;
+    // E elements per thread, loaded in two unrolled halves so that the data
+    // and twiddle-table loads of a half are all in flight together.
+    static_assert(E % 2 == 0, "E must be even");
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        cplx<T> v[E / 2];
+        cplx<double> tw[E / 2];
+#pragma unroll
+        for (int u = 0; u < E / 2; ++u) {
+            const int e = tid + (h * (E / 2) + u) * nt;
+            const int r = e / FFT_COLS, c = e % FFT_COLS;
+            const int64_t m = j0 + c + (int64_t)r * MR;
+            if (P.in_mode == 1) {
+                const double2 a = *(const double2*)(xc + 2 * m);
+                if (P.with_delta) {
+                    const double2 b = *(const double2*)(xp + 2 * m);
+                    if (a.x != b.x) { const double l = log10(a.x / b.x); acc += l * l; ++chg; }
+                    if (a.y != b.y) { const double l = log10(a.y / b.y); acc += l * l; ++chg; }
+                }
+                v[u] = cmk((T)a.x, (T)a.y);
+            } else {
+                v[u] = src[m];
+            }
+            if (Ns > 1 && r > 0) tw[u] = tw64(tb, (j0m + c) * r * (N / (Ns * R)));
         }
-        if (Ns > 1 && r > 0) {
-            const int64_t jm = j0m + c;
-            const int64_t t = jm * r * (N / (Ns * R));
-            cplx<T> w = to_T<T>(tw64(tb, t));
-            if (INV) w = cconj(w);
-            v = cmul(v, w);
+#pragma unroll
+        for (int u = 0; u < E / 2; ++u) {
+            const int e = tid + (h * (E / 2) + u) * nt;
+            const int r = e / FFT_COLS;
+            cplx<T> x = v[u];
+            if (Ns > 1 && r > 0) {
+                cplx<T> w = to_T<T>(tw[u]);
+                if (INV) w = cconj(w);
+                x = cmul(x, w);
+            }
+            buf[tpad<T>(e)] = x;
         }
-        buf[tpad<T>(e)] = v;
+    }
+    if (P.in_mode == 1 && P.with_delta) {
+        // per-block Eq. 4 partials, fixed reduction order (blocks are >= 64 threads)
+        const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+        for (int s2 = 32; s2 >= 1; s2 >>= 1) {
+            acc += __shfl_xor(acc, s2, 64);
+            chg += __shfl_xor(chg, s2, 64);
+        }
+        if (lane == 0) { red[wave] = acc; redc[wave] = chg; }
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            uint32_t cc = 0;
+            for (int w = 0; w < nt / 64; ++w) { t += red[w]; cc += redc[w]; }
+            d.dpart[blockIdx.x] = t;
+            d.cpart[blockIdx.x] = cc;
+        }
     }
     __syncthreads();
     col_fft<T, E, INV>(buf, wr, R, P.sub, tid, nt);
@@ -273,7 +320,7 @@ struct SortPass {
     int32_t first;     // 1: values are implicit (sample index)
     int32_t src_sel;   // 0: sortA, 1: sortB
     int32_t mode;      // SORT_MODE_*
-    int32_t rank_sel;  // MODE_RANK / PREP: 0 = rankA, 1 = rankB
+    int32_t rank_sel;  // MODE_RANK: x_{i+1} and its ranks go to X1/rankB (1) or X0/rankA (0)
 };
 
 // grid: (ntiles, curves), block 256.  hist[d * ntiles + tile] = count of digit d.
@@ -349,11 +396,19 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sort_scan_digits(const BigCurve
 }
 
 // grid: (ntiles, curves), block 256.  Stable scatter of one 8-bit digit.
-template <typename K, typename T>
+// The tile is first rearranged in LDS into digit order; then thread q takes
+// tile positions q, q + 256, ... so that consecutive threads write consecutive
+// global positions inside each digit's run.
+template <typename K>
 __global__ __launch_bounds__(BIG_THREADS) void k_sort_scatter(const BigCurve* __restrict__ cv, SortPass P,
                                                               int64_t ntiles) {
     __shared__ uint32_t wcnt[4][256];   // per-wave running digit counters
     __shared__ uint32_t wpre[4][256];   // exclusive prefix over waves
+    __shared__ uint32_t tstart[256];    // digit start inside the tile
+    __shared__ uint32_t gbase[256];     // global start of the tile's digit run
+    __shared__ uint32_t wtot[4];        // per-wave digit-count totals
+    __shared__ K skey[BIG_TILE];
+    __shared__ uint32_t sval[BIG_TILE];
     const BigCurve& d = cv[blockIdx.y];
     if (d.state[1] == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -395,45 +450,64 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sort_scatter(const BigCurve* __
         loc[i] = cur + below;
     }
     __syncthreads();
-    // exclusive prefix of the per-wave counts, per digit (4 waves)
     {
-        const int q = tid;  // digit
-        const uint32_t c0 = wcnt[0][q], c1 = wcnt[1][q], c2 = wcnt[2][q];
+        // per digit: prefix over waves, tile total; then exclusive scan over digits
+        const int q = tid;
+        const uint32_t c0 = wcnt[0][q], c1 = wcnt[1][q], c2 = wcnt[2][q], c3 = wcnt[3][q];
         wpre[0][q] = 0;
         wpre[1][q] = c0;
         wpre[2][q] = c0 + c1;
         wpre[3][q] = c0 + c1 + c2;
+        const uint32_t tot = c0 + c1 + c2 + c3;
+        uint32_t inc = tot;
+#pragma unroll
+        for (int s2 = 1; s2 < 64; s2 <<= 1) {
+            const uint32_t o = __shfl_up(inc, s2, 64);
+            if (lane >= s2) inc += o;
+        }
+        if (lane == 63) wtot[wave] = inc;
+        __syncthreads();
+        uint32_t pre = 0;
+        for (int w = 0; w < wave; ++w) pre += wtot[w];
+        const uint32_t ts = pre + inc - tot;
+        tstart[q] = ts;
+        gbase[q] = d.dstart[q] + d.hist[(int64_t)q * ntiles + tile];
     }
     __syncthreads();
-    const uint32_t* hist = d.hist;
-    const uint32_t* dstart = d.dstart;
-    const T* sT = (const T*)d.sT;
-    uint32_t* rnk = P.rank_sel ? d.rankB : d.rankA;
-    unsigned char* dstb = P.src_sel ? d.sortA : d.sortB;
-    K* dkeys = (K*)dstb;
-    uint32_t* dvals = (uint32_t*)(dstb + (size_t)n * sizeof(K));
 #pragma unroll
     for (int i = 0; i < BIG_IPT; ++i) {
         const uint32_t dg = (uint32_t)(key[i] >> P.shift) & 255u;
-        const uint32_t dest = dstart[dg] + hist[(int64_t)dg * ntiles + tile] + wpre[wave][dg] + loc[i];
+        const uint32_t pl = tstart[dg] + wpre[wave][dg] + loc[i];
+        skey[pl] = key[i];
+        sval[pl] = val[i];
+    }
+    __syncthreads();
+    unsigned char* dstb = P.src_sel ? d.sortA : d.sortB;
+    K* dkeys = (K*)dstb;
+    uint32_t* dvals = (uint32_t*)(dstb + (size_t)n * sizeof(K));
+    uint32_t* rnk = P.rank_sel ? d.rankB : d.rankA;
+    double* xn = P.rank_sel ? d.X1 : d.X0;
+#pragma unroll 4
+    for (int q = tid; q < BIG_TILE; q += BIG_THREADS) {
+        const K k = skey[q];
+        const uint32_t v = sval[q];
+        const uint32_t dg = (uint32_t)(k >> P.shift) & 255u;
+        const uint32_t dest = gbase[dg] + (uint32_t)q - tstart[dg];
         if (P.mode == SORT_MODE_MOVE) {
-            dkeys[dest] = key[i];
-            dvals[dest] = val[i];
+            dkeys[dest] = k;
+            dvals[dest] = v;
         } else if (P.mode == SORT_MODE_RANK) {
-            rnk[val[i]] = dest;
+            xn[v] = d.s64[dest];
+            if (d.rank_out) rnk[v] = dest;
         } else {
-            const double x = d.x0[val[i]];
-            d.s64[dest] = x;
-            ((T*)d.sT)[dest] = (T)x;
-            d.L[dest] = log10(x);
-            rnk[val[i]] = dest;
+            d.s64[dest] = d.x0[v];
+            rnk[v] = dest;
         }
     }
-    (void)sT;
 }
 
-// Order-preserving keys of the draw and its validity (prep, once per call).
-// grid: (ntiles, curves), block 256.
+// Order-preserving keys of the draw, its validity, and x_0 = draw (prep, once
+// per call).  grid: (ntiles, curves), block 256.
 __global__ __launch_bounds__(BIG_THREADS) void k_big_prep_keys(const BigCurve* __restrict__ cv) {
     const BigCurve& d = cv[blockIdx.y];
     const int64_t base = (int64_t)blockIdx.x * BIG_TILE;
@@ -444,11 +518,12 @@ __global__ __launch_bounds__(BIG_THREADS) void k_big_prep_keys(const BigCurve* _
         const double x = d.x0[p];
         bad |= !(x > 0.0 && x <= 1.7976931348623157e308);
         keys[p] = ord_key(x);
+        d.X0[p] = x;
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) atomicAnd(&d.state[0], 0);
 }
 
-// State init: valid = 1, active = (iters > 0), done = 0.  grid: (curves), block 64.
+// State init: valid = 1, active = 1, done = 0.  grid: (curves), block 64.
 __global__ void k_big_init(const BigCurve* __restrict__ cv) {
     const BigCurve& d = cv[blockIdx.x];
     if (threadIdx.x == 0) {
@@ -466,31 +541,32 @@ __global__ void k_big_after_prep(const BigCurve* __restrict__ cv) {
     }
 }
 
-// Eq. 4 partial sums per tile.  grid: (ntiles, curves), block 256.
-__global__ __launch_bounds__(BIG_THREADS) void k_big_delta(const BigCurve* __restrict__ cv, int new_sel) {
+// Eq. 4 partials of the last iteration (x_sel holds x_last, the other buffer
+// x_{last-1}); only for curves still active.  grid: (ntiles, curves), block 256.
+__global__ __launch_bounds__(BIG_THREADS) void k_big_delta_last(const BigCurve* __restrict__ cv, int x_sel) {
     __shared__ double shd[4];
     __shared__ uint32_t shc[4];
     const BigCurve& d = cv[blockIdx.y];
     if (d.state[1] == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t* rn = new_sel ? d.rankB : d.rankA;
-    const uint32_t* ro = new_sel ? d.rankA : d.rankB;
+    const double* xc = x_sel ? d.X1 : d.X0;
+    const double* xp = x_sel ? d.X0 : d.X1;
     const int64_t base = (int64_t)blockIdx.x * BIG_TILE;
     double acc = 0.0;
     uint32_t chg = 0;
     for (int i = 0; i < BIG_IPT; ++i) {
         const int64_t p = base + i * BIG_THREADS + tid;
-        const uint32_t a = rn[p], b = ro[p];
+        const double a = xc[p], b = xp[p];
         if (a != b) {
-            const double dl = d.L[a] - d.L[b];
-            acc += dl * dl;
-            chg += (d.s64[a] != d.s64[b]) ? 1u : 0u;
+            const double l = log10(a / b);
+            acc += l * l;
+            ++chg;
         }
     }
 #pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) {
-        acc += __shfl_xor(acc, s, 64);
-        chg += __shfl_xor(chg, s, 64);
+    for (int s2 = 32; s2 >= 1; s2 >>= 1) {
+        acc += __shfl_xor(acc, s2, 64);
+        chg += __shfl_xor(chg, s2, 64);
     }
     if (lane == 0) { shd[wave] = acc; shc[wave] = chg; }
     __syncthreads();
@@ -500,9 +576,10 @@ __global__ __launch_bounds__(BIG_THREADS) void k_big_delta(const BigCurve* __res
     }
 }
 
-// One block per curve: delta_i, iteration count, stopping rule.
+// One block per curve: delta of iteration `it` from `npart` partials,
+// iteration count, stopping rule.
 __global__ __launch_bounds__(BIG_THREADS) void k_big_delta_final(const BigCurve* __restrict__ cv, int it,
-                                                                 int64_t ntiles) {
+                                                                 int64_t npart) {
     __shared__ double shd[4];
     __shared__ uint32_t shc[4];
     const BigCurve& d = cv[blockIdx.x];
@@ -510,14 +587,14 @@ __global__ __launch_bounds__(BIG_THREADS) void k_big_delta_final(const BigCurve*
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double acc = 0.0;
     uint32_t chg = 0;
-    for (int64_t t = tid; t < ntiles; t += BIG_THREADS) {
+    for (int64_t t = tid; t < npart; t += BIG_THREADS) {
         acc += d.dpart[t];
         chg += d.cpart[t];
     }
 #pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) {
-        acc += __shfl_xor(acc, s, 64);
-        chg += __shfl_xor(chg, s, 64);
+    for (int s2 = 32; s2 >= 1; s2 >>= 1) {
+        acc += __shfl_xor(acc, s2, 64);
+        chg += __shfl_xor(chg, s2, 64);
     }
     if (lane == 0) { shd[wave] = acc; shc[wave] = chg; }
     __syncthreads();
@@ -532,18 +609,18 @@ __global__ __launch_bounds__(BIG_THREADS) void k_big_delta_final(const BigCurve*
     }
 }
 
-// x_out = s64[rank], rank_out, iters_done, zero-fill of unused delta entries.
+// x_out = x_done, rank_out, iters_done, zero-fill of unused delta entries.
 // grid: (ntiles, curves), block 256.
 __global__ __launch_bounds__(BIG_THREADS) void k_big_output(const BigCurve* __restrict__ cv) {
     const BigCurve& d = cv[blockIdx.y];
     const int done = d.state[2];
+    const double* x = (done & 1) ? d.X1 : d.X0;
     const uint32_t* r = (done & 1) ? d.rankB : d.rankA;
     const int64_t base = (int64_t)blockIdx.x * BIG_TILE;
     for (int i = 0; i < BIG_IPT; ++i) {
         const int64_t p = base + i * BIG_THREADS + threadIdx.x;
-        const uint32_t k = r[p];
-        d.x_out[p] = d.s64[k];
-        if (d.rank_out) d.rank_out[p] = k;
+        d.x_out[p] = x[p];
+        if (d.rank_out) d.rank_out[p] = r[p];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (d.iters_done) *d.iters_done = d.state[0] ? done : -1;

@@ -261,3 +261,24 @@ def test_repeat_is_bit_identical(gpu_ctx):
     a = run_iterate(gpu_ctx, amp, x0, 20, 1)
     b = run_iterate(gpu_ctx, amp, x0, 20, 1)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("n", [1, 1000, 2**20])
+def test_erdf_draw_matches_oracle(gpu_ctx, n):
+    """PDF draw on the device vs the oracle's inverse CDF of the same Philox
+    uniforms.  Above the break the log argument 1 - (t - m1) d2 ln10 falls to
+    10^(-d2 (u_max - u_br)) = 1.8e-4 while its terms are of order 1, so one
+    ulp of difference in forming it (fused or separate multiply-add, device
+    vs host log10) moves u by up to 2^-52 * 5.6e3 / (d2 ln10) = 2.2e-13; the
+    bound on |u_gpu - u_ref| is 1e-11 (about 50 such ulps)."""
+    m = agn()
+    out = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda:0")
+    m.agn_erdf_draw(gpu_ctx, m.erdf_params(), n, 77, 3, out)
+    got = host(out)
+    ref = oracle.erdf_bpl(oracle.erdf_params(), n, 77, 3)
+    assert np.all(got > 0)
+    du = np.abs(np.log10(got) - np.log10(ref))
+    assert du.max() <= 1e-11, du.max()
+    assert np.median(du) <= 4e-15
+    with pytest.raises(m.AgnError):
+        m.agn_erdf_draw(gpu_ctx, m.erdf_params(u_min=0.0, u_max=-4.0), n, 77, 3, out)
