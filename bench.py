@@ -27,6 +27,15 @@ METRIC = "light-curve samples/s through full iteration (FP32 batched vs FP64 pla
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
 LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
+FP32_PEAK_TFLOPS = 157.3        # FP32 vector, packed FMA
+
+
+def lds_flops_per_sample_iter(n):
+    """FP32 flops per sample-iteration of the LDS-resident kernel counted
+    algorithmically: two complex FFTs of length N/2 at 5 (N/2) log2(N/2) flops
+    each, plus about 40 flops per Hermitian pair for the fold, the modulus
+    replacement and the unfold (20 per real sample)."""
+    return 5.0 * math.log2(n // 2) + 20.0
 
 
 def lds_bytes_per_sample_iter(n, prec_bytes):
@@ -55,12 +64,13 @@ def lds_bytes_per_sample_iter(n, prec_bytes):
 
 def hbm_bytes_per_sample(kernel, prec_bytes):
     """Algorithmic HBM bytes per real sample for one launch of a multi-pass
-    kernel (average over the launches of one iteration).  FFT pass: read and
-    write the complex buffer (2 x prec bytes per sample each way).  Sort
-    scatter (8-bit LSD, key of prec bytes + 32-bit index): read key and index,
-    write both.  Histogram: read the key."""
+    kernel.  FFT pass: read and write the N/2-point complex buffer (prec bytes
+    per real sample each way; the first forward pass reads more, so this is a
+    lower bound for the average launch).  Sort scatter (8-bit LSD, key of prec
+    bytes + 32-bit index): read key and index, write both.  Histogram: read
+    the key."""
     if kernel == "fft_pass":
-        return 4 * prec_bytes
+        return 2 * prec_bytes
     if kernel == "sort_scatter":
         return 2 * (prec_bytes + 4)
     if kernel == "sort_hist":
@@ -78,6 +88,7 @@ def main():
     ap.add_argument("--workload", default="ptf_batch",
                     choices=["ptf_batch", "single_curve", "lsst_long", "lsst_long_fp64", "uneven_batch", "serving"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the FP32-vs-FP64 accuracy report")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -174,12 +185,17 @@ def main():
     dom_ms = kt[dom][0] / max(kt[dom][1], 1)
     pb = 4 if prec == agn.AGN_FP32 else 8
     if dom == "lds_iterate":
+        # issue/barrier-bound: FP32 flops of the FFTs + replacement against the
+        # vector peak; the LDS-traffic view alongside
+        fl = lds_flops_per_sample_iter(n)
+        achieved = fl * samples * iters / (dom_ms / 1000.0) / 1e12
         per = lds_bytes_per_sample_iter(n, pb)
-        lds_bytes = per * samples * iters
-        achieved = lds_bytes / (dom_ms / 1000.0) / 1e9
-        roof = {"bound": "lds", "kernel": dom, "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBS, 1),
-                "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_sample_iter": per, "avg_launch_ms": round(dom_ms, 4)}
+        lds_gbs = per * samples * iters / (dom_ms / 1000.0) / 1e9
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "flops_per_sample_iter": fl, "avg_launch_ms": round(dom_ms, 4),
+                "lds_view": {"achieved_gbs": round(lds_gbs, 1), "peak_gbs": round(LDS_PEAK_GBS, 1),
+                             "frac": round(lds_gbs / LDS_PEAK_GBS, 4), "bytes_per_sample_iter": per}}
     else:
         per = hbm_bytes_per_sample(dom, pb)
         achieved = per * samples / (dom_ms / 1000.0) / 1e9
@@ -198,6 +214,10 @@ def main():
         "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]},
         "roofline": roof,
     }
+
+    if args.workload == "ptf_batch" and prec == agn.AGN_FP32 and not args.no_accuracy:
+        out["accuracy_vs_fp64"] = fp32_accuracy(agn, np, torch, ctx, x, ns, offs, params, dt_days, iters,
+                                                seeds, ids, erdf_t, k=8)
 
     if not args.no_cpu_baseline:
         import oracle
@@ -224,6 +244,69 @@ def main():
                                    "sample": f"first {k} curve(s) of the workload, all {iters} iterations, "
                                              f"single-threaded FP64 oracle ({el:.1f} s)"}
     print(json.dumps(out))
+
+
+def log_binned_periodogram(np, x, dex=0.1):
+    """Eq. A2 periodogram P_j = 2/N^2 |X_j|^2, j = 1..N/2, averaged in bins of
+    `dex` in log10 frequency starting at the first Fourier frequency."""
+    n = len(x)
+    P = 2.0 / n**2 * np.abs(np.fft.rfft(x)[1:]) ** 2
+    lj = np.log10(np.arange(1, n // 2 + 1))
+    b = np.floor(lj / dex + 1e-9).astype(int)
+    sums = np.bincount(b, weights=P)
+    cnt = np.bincount(b)
+    keep = cnt > 0
+    return sums[keep] / cnt[keep]
+
+
+def fp32_accuracy(agn, np, torch, ctx, x32_all, ns, offs, params, dt_days, iters, seeds, ids, erdf_t, k):
+    """FP32 form against the FP64 path (bit-identical to the oracle) on the
+    first k curves: value multiset, end-to-end and one-step rank agreement,
+    |rank difference| quantiles, log-binned periodogram difference."""
+    dev = "cuda:0"
+    ns_k, offs_k = ns[:k], offs[:k]
+    tot = int(sum(ns_k))
+    x64 = torch.empty(tot, dtype=torch.float64, device=dev)
+    ws = torch.empty(agn.agn_batch_workspace_size(ns_k, agn.AGN_FP64), dtype=torch.uint8, device=dev)
+    agn.agn_lc_generate_batch(ctx, ns_k, offs_k, params[:k], [dt_days] * k, [iters] * k, seeds[:k], ids[:k],
+                              erdf_t[:tot], -1.0, agn.AGN_FP64, x64, None, None, ws)
+    torch.cuda.synchronize()
+    a64 = x64.cpu().numpy()
+    a32 = x32_all[:tot].cpu().numpy()
+    multiset, e2e, one, drank, pdiff = True, [], [], [], []
+    for c in range(k):
+        n, o = ns_k[c], offs_k[c]
+        u32, u64 = a32[o:o + n], a64[o:o + n]
+        s = np.sort(u64)
+        multiset &= bool(np.array_equal(np.sort(u32), s))
+        e2e.append(np.mean(u32 == u64))
+        r32 = np.searchsorted(s, u32)
+        r64 = np.searchsorted(s, u64)
+        drank.append(np.abs(r32.astype(np.int64) - r64))
+        p32, p64 = log_binned_periodogram(np, u32), log_binned_periodogram(np, u64)
+        pdiff.append(np.abs(p32 / p64 - 1.0))
+        # one step from the same input (the FP64 result) in both precisions
+        ranks = []
+        for prec in (agn.AGN_FP32, agn.AGN_FP64):
+            el = torch.float32 if prec == agn.AGN_FP32 else torch.float64
+            amp = torch.empty(n // 2 + 1, dtype=el, device=dev)
+            sws = torch.empty(agn.agn_spectrum_workspace_size(n), dtype=torch.uint8, device=dev)
+            agn.agn_psd_spectrum(ctx, params[c], n, dt_days, seeds[c], ids[c], prec, amp, sws)
+            iws = torch.empty(agn.agn_workspace_size(n, prec), dtype=torch.uint8, device=dev)
+            xo = torch.empty(n, dtype=torch.float64, device=dev)
+            rk = torch.empty(n, dtype=torch.int32, device=dev)
+            agn.agn_lc_iterate(ctx, amp, x64[o:o + n], n, 1, -1.0, prec, xo, None, None, rk, iws)
+            torch.cuda.synchronize()
+            ranks.append(rk.cpu().numpy())
+        one.append(np.mean(ranks[0] == ranks[1]))
+    dr = np.concatenate(drank)
+    pd = np.concatenate(pdiff)
+    return {"curves": k, "reference": "FP64 GPU path (bit-identical to the FP64 oracle)",
+            "value_multiset_exact": multiset,
+            "one_step_rank_agreement": round(float(np.mean(one)), 6),
+            "end_to_end_agreement": round(float(np.mean(e2e)), 6),
+            "abs_rank_diff_p50_p99_max": [int(np.percentile(dr, 50)), int(np.percentile(dr, 99)), int(dr.max())],
+            "log_binned_periodogram_rel_diff_median_max": [float(np.median(pd)), float(pd.max())]}
 
 
 def run_uneven(args, agn, synth, np, torch):

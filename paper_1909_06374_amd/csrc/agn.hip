@@ -546,17 +546,40 @@ static std::vector<int> big_radices(int64_t M, agn_precision prec) {
     return {};
 }
 
+// Tile of one FFT workgroup: R x cols complex values = 64 KB.
+static int fft_tile(agn_precision prec) { return prec == AGN_FP32 ? 8192 : 4096; }
+
+// Butterflies per workgroup of a pass: the largest power of two <= 64 with
+// R * cols within the tile and dividing M / R (0 if none >= 16).
+static int fft_cols(int64_t M, int R, agn_precision prec) {
+    for (int c = FFT_COLS_MAX; c >= FFT_COLS_MIN; c >>= 1)
+        if ((int64_t)R * c <= fft_tile(prec) && (M / R) % c == 0) return c;
+    return 0;
+}
+
+template <typename T, bool INV, int C>
+static void launch_fft_pass_c(const BigCurve* d, int nc, const FftPass& P, const TwTable& tb, size_t lds,
+                              hipStream_t st) {
+    dim3 grid((unsigned)(P.M / P.R / C), (unsigned)nc);
+    hipLaunchKernelGGL((k_fft_pass<T, 16, INV, C>), grid, dim3(P.nthreads), lds, st, d, P, tb);
+}
+
 template <typename T>
 static void launch_fft_pass(agn_ctx* ctx, const BigCurve* d, int nc, const FftPass& P, const TwTable& tb,
                             hipStream_t st) {
-    const size_t lds = (size_t)(P.R * FFT_COLS + 1 + ((P.R * FFT_COLS + 1) >> (sizeof(T) == 4 ? 5 : 4))) *
-                           sizeof(cplx<T>) + 16 + (size_t)P.R * sizeof(cplx<T>) + 8 * 8 + 8 * 4;
-    dim3 grid((unsigned)(P.M / P.R / FFT_COLS), (unsigned)nc);
+    const int C = P.cols;
+    const size_t lds = (size_t)(P.R * C + 1 + ((P.R * C + 1) >> (sizeof(T) == 4 ? 5 : 4))) * sizeof(cplx<T>) +
+                       16 + (size_t)P.R * sizeof(cplx<T>) + 8 * 8 + 8 * 4;
     ProfScope ps(ctx, "fft_pass", st);
-    if (P.inverse)
-        hipLaunchKernelGGL((k_fft_pass<T, 16, true>), grid, dim3(P.nthreads), lds, st, d, P, tb);
-    else
-        hipLaunchKernelGGL((k_fft_pass<T, 16, false>), grid, dim3(P.nthreads), lds, st, d, P, tb);
+    if (P.inverse) {
+        if (C == 64) launch_fft_pass_c<T, true, 64>(d, nc, P, tb, lds, st);
+        else if (C == 32) launch_fft_pass_c<T, true, 32>(d, nc, P, tb, lds, st);
+        else launch_fft_pass_c<T, true, 16>(d, nc, P, tb, lds, st);
+    } else {
+        if (C == 64) launch_fft_pass_c<T, false, 64>(d, nc, P, tb, lds, st);
+        else if (C == 32) launch_fft_pass_c<T, false, 32>(d, nc, P, tb, lds, st);
+        else launch_fft_pass_c<T, false, 16>(d, nc, P, tb, lds, st);
+    }
 }
 
 template <typename K, typename T>
@@ -587,7 +610,8 @@ static int big_group_setup(agn_ctx* ctx, int64_t n, agn_precision prec, TwTable*
     if (rad->empty()) return fail(AGN_EUNSUPPORTED_N, "internal: no FFT plan for n=%lld", (long long)n);
     int64_t ns = 1;
     for (int r : *rad) {
-        if ((M / r) % FFT_COLS != 0 || r > 512 || (ns > 1 && ns % FFT_COLS != 0) || (ns == 1 && r < 64))
+        const int c = fft_cols(M, r, prec);
+        if (c == 0 || r > 512 || (ns > 1 && ns % c != 0) || (ns == 1 && r < 64) || r < 16)
             return fail(AGN_EUNSUPPORTED_N, "internal: no FFT plan for n=%lld", (long long)n);
         ns *= r;
     }
@@ -619,7 +643,9 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
     hipLaunchKernelGGL(k_big_after_prep, dim3((unsigned)nc), dim3(64), 0, st, d);
     const int npass_sort = (int)sizeof(K);
     const int np = (int)rad.size();
-    const int64_t npart0 = M / rad[0] / FFT_COLS;  // blocks of the first FFT pass
+    const int prec_bits = sizeof(T) == 4 ? 1 : 0;
+    const agn_precision prec = prec_bits ? AGN_FP32 : AGN_FP64;
+    const int64_t npart0 = M / rad[0] / fft_cols(M, rad[0], prec);  // blocks of the first FFT pass
     for (int it = 0; it < max_iters; ++it) {
         const int cur = it & 1;  // x_it lives in X0 (even) or X1 (odd)
         int sel = 0;             // region written by the next FFT pass
@@ -627,7 +653,8 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
         for (int p = 0; p < np; ++p) {
             FftPass P;
             memset(&P, 0, sizeof(P));
-            P.M = M; P.R = rad[p]; P.nthreads = rad[p] * FFT_COLS / 16; P.Ns = Ns;
+            P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], prec); P.nthreads = rad[p] * P.cols / 16;
+            P.Ns = Ns;
             P.in_mode = p == 0 ? 1 : 0; P.out_mode = 0; P.inverse = 0;
             P.x_sel = cur; P.with_delta = (p == 0 && it > 0) ? 1 : 0;
             P.src_sel = 1 - sel; P.dst_sel = sel; P.sub = make_plan(rad[p]);
@@ -650,7 +677,8 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
         for (int p = 0; p < np; ++p) {
             FftPass P;
             memset(&P, 0, sizeof(P));
-            P.M = M; P.R = rad[p]; P.nthreads = rad[p] * FFT_COLS / 16; P.Ns = Ns;
+            P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], prec); P.nthreads = rad[p] * P.cols / 16;
+            P.Ns = Ns;
             P.in_mode = 0; P.out_mode = (p == np - 1) ? 1 : 0; P.inverse = 1;
             P.src_sel = 1 - sel; P.dst_sel = sel; P.sub = make_plan(rad[p]);
             launch_fft_pass<T>(ctx, d, nc, P, tb, st);
@@ -782,7 +810,7 @@ static int build_plan(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_p
             d.iters_done = r.iters_done;
             d.rank_out = r.rank_out;
             const void* tw = nullptr;
-            int rc = get_twiddles(ctx, n, prec, &tw);
+            int rc = get_twiddles(ctx, n, AGN_FP64, &tw);
             if (rc) return rc;
             d.tw = tw;
             d.plan = make_plan(M);

@@ -17,11 +17,12 @@
 // FFT pass (self-sorting Stockham step with a large radix R): butterfly j of
 // M/R reads z[j + r M/R], r < R, multiplies by W_{Ns R}^{(j mod Ns) r}, takes a
 // length-R DFT and writes output q to z[(j - j mod Ns) R + j mod Ns + q Ns].  A
-// workgroup takes 16 consecutive butterflies (16-element, 128-byte rows for
-// FP32) into LDS and runs the 16 length-R DFTs there as small Stockham passes.
+// workgroup takes C consecutive butterflies (C = 16..64 so that the tile of
+// R x C values is 64 KB; C-element rows of 128-512 bytes) into LDS and runs the
+// C length-R DFTs there as small Stockham passes.
 // Inter-pass twiddles W_N^t are generated in double precision from a two-level
-// table (W_N^{t_hi B} W_N^{t_lo}, B = 4096) and rounded once to the working
-// precision.
+// table (W_N^{t_hi B} W_N^{t_lo}, B = 4096), stepped along a thread's column by
+// FP64 products, and rounded once to the working precision.
 #pragma once
 #include "common.hpp"
 #include "lds_fft.hpp"
@@ -31,7 +32,8 @@ namespace agn {
 constexpr int BIG_TILE = 4096;       // sort / delta tile (256 threads x 16)
 constexpr int BIG_THREADS = 256;
 constexpr int BIG_IPT = 16;
-constexpr int FFT_COLS = 16;         // butterflies per FFT workgroup
+constexpr int FFT_COLS_MIN = 16;     // fewest butterflies per FFT workgroup
+constexpr int FFT_COLS_MAX = 64;     // most butterflies per FFT workgroup
 constexpr int TW_LO_BITS = 12;       // two-level twiddle split
 
 struct BigCurve {
@@ -79,7 +81,8 @@ AGN_DEV cplx<double> tw64(const TwTable& tb, int64_t t) {
 struct FftPass {
     int64_t M;           // complex length
     int32_t R;           // radix of this pass (<= 512)
-    int32_t nthreads;    // R * FFT_COLS / E
+    int32_t nthreads;    // R * cols / E
+    int32_t cols;        // butterflies per workgroup (power of two, 16..64)
     int64_t Ns;          // product of the previous radices
     int32_t in_mode;     // 0: complex buffer, 1: series x_i (FP64, time order)
     int32_t out_mode;    // 0: complex buffer, 1: keys of y (real view)
@@ -94,11 +97,11 @@ struct FftPass {
 template <typename T>
 AGN_DEV int tpad(int e) { return e + (e >> (sizeof(T) == 4 ? 5 : 4)); }
 
-// In-LDS Stockham pass over FFT_COLS independent columns: element (r, c) at
-// tpad(r * FFT_COLS + c).  Sub-twiddles come from the LDS table of R-th roots.
-template <typename T, int RR, int BMAX, bool INV>
+// In-LDS Stockham pass over C independent columns: element (r, c) at
+// tpad(r * C + c).  Sub-twiddles come from the LDS table of R-th roots.
+template <typename T, int RR, int BMAX, bool INV, int C>
 AGN_DEV void col_pass(cplx<T>* buf, const cplx<T>* wr, int R, int Ns, int tid, int nt) {
-    const int nb = (R / RR) * FFT_COLS;  // butterflies
+    const int nb = (R / RR) * C;  // butterflies
     const int RB = R / RR;
     const bool pow2 = (Ns & (Ns - 1)) == 0;
     cplx<T> v[BMAX][RR];
@@ -108,9 +111,9 @@ AGN_DEV void col_pass(cplx<T>* buf, const cplx<T>* wr, int R, int Ns, int tid, i
     for (int b = 0; b < BMAX; ++b) {
         const int q = tid + b * nt;
         if (q < nb) {
-            const int j = q / FFT_COLS, c = q % FFT_COLS;
+            const int j = q / C, c = q % C;
 #pragma unroll
-            for (int r = 0; r < RR; ++r) v[b][r] = buf[tpad<T>((j + r * RB) * FFT_COLS + c)];
+            for (int r = 0; r < RR; ++r) v[b][r] = buf[tpad<T>((j + r * RB) * C + c)];
             if (Ns > 1) {
                 const int jm = pow2 ? (j & (Ns - 1)) : (j % Ns);
                 const int step = R / (Ns * RR);
@@ -128,7 +131,7 @@ AGN_DEV void col_pass(cplx<T>* buf, const cplx<T>* wr, int R, int Ns, int tid, i
     for (int b = 0; b < BMAX; ++b) {
         const int q = tid + b * nt;
         if (q < nb) {
-            const int j = q / FFT_COLS, c = q % FFT_COLS;
+            const int j = q / C, c = q % C;
             const int jm = pow2 ? (j & (Ns - 1)) : (j % Ns);
             if (Ns > 1) {
 #pragma unroll
@@ -137,21 +140,21 @@ AGN_DEV void col_pass(cplx<T>* buf, const cplx<T>* wr, int R, int Ns, int tid, i
             dftR<T, RR, INV>(v[b]);
             const int d = (j - jm) * RR + jm;
 #pragma unroll
-            for (int r = 0; r < RR; ++r) buf[tpad<T>((d + r * Ns) * FFT_COLS + c)] = v[b][r];
+            for (int r = 0; r < RR; ++r) buf[tpad<T>((d + r * Ns) * C + c)] = v[b][r];
         }
     }
     __syncthreads();
 }
 
-template <typename T, int E, bool INV>
+template <typename T, int E, bool INV, int C>
 AGN_DEV void col_fft(cplx<T>* buf, const cplx<T>* wr, int R, const FftPlan& plan, int tid, int nt) {
     int Ns = 1;
     for (int p = 0; p < plan.npass; ++p) {
         const int RR = plan.radix[p];
-        if (RR == 8) col_pass<T, 8, (E + 7) / 8, INV>(buf, wr, R, Ns, tid, nt);
-        else if (RR == 4) col_pass<T, 4, (E + 3) / 4, INV>(buf, wr, R, Ns, tid, nt);
-        else if (RR == 3) col_pass<T, 3, (E + 2) / 3, INV>(buf, wr, R, Ns, tid, nt);
-        else col_pass<T, 2, (E + 1) / 2, INV>(buf, wr, R, Ns, tid, nt);
+        if (RR == 8) col_pass<T, 8, (E + 7) / 8, INV, C>(buf, wr, R, Ns, tid, nt);
+        else if (RR == 4) col_pass<T, 4, (E + 3) / 4, INV, C>(buf, wr, R, Ns, tid, nt);
+        else if (RR == 3) col_pass<T, 3, (E + 2) / 3, INV, C>(buf, wr, R, Ns, tid, nt);
+        else col_pass<T, 2, (E + 1) / 2, INV, C>(buf, wr, R, Ns, tid, nt);
         Ns *= RR;
     }
 }
@@ -159,8 +162,9 @@ AGN_DEV void col_fft(cplx<T>* buf, const cplx<T>* wr, int R, const FftPlan& plan
 template <typename T>
 AGN_DEV cplx<T> to_T(cplx<double> a) { return cmk((T)a.re, (T)a.im); }
 
-// grid: (M / R / FFT_COLS, curves), block: P.nthreads (E = R * FFT_COLS / nthreads).
-template <typename T, int E, bool INV>
+// grid: (M / R / C, curves), block: P.nthreads (E = R * C / nthreads, nthreads a
+// multiple of C, so each thread stays in one column c = tid mod C).
+template <typename T, int E, bool INV, int C>
 __global__ __launch_bounds__(512) void k_fft_pass(const BigCurve* __restrict__ cv, FftPass P, TwTable tb) {
     typedef typename key_of<T>::type K;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -169,11 +173,11 @@ __global__ __launch_bounds__(512) void k_fft_pass(const BigCurve* __restrict__ c
     const int tid = threadIdx.x, nt = blockDim.x;
     const int R = P.R;
     const int64_t M = P.M, N = 2 * M, MR = M / R, Ns = P.Ns;
-    const int64_t j0 = (int64_t)blockIdx.x * FFT_COLS;
-    // Ns is 1 or a multiple of FFT_COLS, so (j0 + c) mod Ns = j0m + c.
+    const int64_t j0 = (int64_t)blockIdx.x * C;
+    // Ns is 1 or a multiple of C, so (j0 + c) mod Ns = j0m + c.
     const int64_t j0m = (Ns > 1) ? (j0 % Ns) : 0;
     cplx<T>* buf = (cplx<T>*)smem;
-    cplx<T>* wr = (cplx<T>*)(smem + (size_t)tpad<T>(R * FFT_COLS + 1) * sizeof(cplx<T>) + 16);
+    cplx<T>* wr = (cplx<T>*)(smem + (size_t)tpad<T>(R * C + 1) * sizeof(cplx<T>) + 16);
     double* red = (double*)(wr + R);         // 8 doubles
     uint32_t* redc = (uint32_t*)(red + 8);   // 8 words
 
@@ -181,24 +185,34 @@ __global__ __launch_bounds__(512) void k_fft_pass(const BigCurve* __restrict__ c
     // R-th roots for the in-LDS passes: W_R^u = W_N^{u N / R}.
     for (int u = tid; u < R; u += nt) wr[u] = to_T<T>(tw64(tb, (int64_t)u * (N / R)));
 
-    // Load R rows of FFT_COLS consecutive butterflies; apply inter-pass twiddles.
+    // Load R rows of C consecutive butterflies; apply inter-pass twiddles.
+    // Element e = tid + k nt sits in column c = tid mod C and row
+    // r_k = tid / C + k (nt / C); its twiddle W_N^{b r_k}, b = (j0m + c) N / (Ns R),
+    // is W_N^{b r_0} (W_N^{b nt / C})^k, formed by FP64 products (at most
+    // E - 1 of them, a few ulp of FP64) and rounded once to T.
     const cplx<T>* src = (const cplx<T>*)(P.src_sel ? d.sortB : d.sortA);
     const double* xc = P.x_sel ? d.X1 : d.X0;
     const double* xp = P.x_sel ? d.X0 : d.X1;
     double acc = 0.0;
     uint32_t chg = 0;
+    const int c_t = tid % C, r_t = tid / C, dr = nt / C;
+    const bool twid = Ns > 1;
+    cplx<double> wk = cmk(1.0, 0.0), wstep = cmk(1.0, 0.0);
+    if (twid) {
+        const int64_t b = (j0m + c_t) * (N / (Ns * R));
+        wk = tw64(tb, b * r_t);
+        wstep = tw64(tb, b * dr);
+    }
     // E elements per thread, loaded in two unrolled halves so that the data
-    // and twiddle-table loads of a half are all in flight together.
+    // loads of a half are all in flight together.
     static_assert(E % 2 == 0, "E must be even");
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         cplx<T> v[E / 2];
-        cplx<double> tw[E / 2];
 #pragma unroll
         for (int u = 0; u < E / 2; ++u) {
-            const int e = tid + (h * (E / 2) + u) * nt;
-            const int r = e / FFT_COLS, c = e % FFT_COLS;
-            const int64_t m = j0 + c + (int64_t)r * MR;
+            const int r = r_t + (h * (E / 2) + u) * dr;
+            const int64_t m = j0 + c_t + (int64_t)r * MR;
             if (P.in_mode == 1) {
                 const double2 a = *(const double2*)(xc + 2 * m);
                 if (P.with_delta) {
@@ -210,17 +224,16 @@ __global__ __launch_bounds__(512) void k_fft_pass(const BigCurve* __restrict__ c
             } else {
                 v[u] = src[m];
             }
-            if (Ns > 1 && r > 0) tw[u] = tw64(tb, (j0m + c) * r * (N / (Ns * R)));
         }
 #pragma unroll
         for (int u = 0; u < E / 2; ++u) {
             const int e = tid + (h * (E / 2) + u) * nt;
-            const int r = e / FFT_COLS;
             cplx<T> x = v[u];
-            if (Ns > 1 && r > 0) {
-                cplx<T> w = to_T<T>(tw[u]);
+            if (twid) {
+                cplx<T> w = to_T<T>(wk);
                 if (INV) w = cconj(w);
                 x = cmul(x, w);
+                wk = cmul(wk, wstep);
             }
             buf[tpad<T>(e)] = x;
         }
@@ -244,28 +257,28 @@ __global__ __launch_bounds__(512) void k_fft_pass(const BigCurve* __restrict__ c
         }
     }
     __syncthreads();
-    col_fft<T, E, INV>(buf, wr, R, P.sub, tid, nt);
+    col_fft<T, E, INV, C>(buf, wr, R, P.sub, tid, nt);
 
     // Write outputs: butterfly j = j0 + c, output q goes to (j - jm) R + jm + q Ns.
     if (P.out_mode == 1) {
         K* keys = (K*)(P.dst_sel ? d.sortB : d.sortA);
-        for (int e = tid; e < R * FFT_COLS; e += nt) {
+        for (int e = tid; e < R * C; e += nt) {
             int q, c;
-            if (Ns == 1) { c = e / R; q = e % R; } else { q = e / FFT_COLS; c = e % FFT_COLS; }
+            if (Ns == 1) { c = e / R; q = e % R; } else { q = e / C; c = e % C; }
             const int64_t jm = (Ns > 1) ? j0m + c : 0;
             const int64_t m = (j0 + c - jm) * R + jm + (int64_t)q * Ns;
-            const cplx<T> v = buf[tpad<T>(q * FFT_COLS + c)];
+            const cplx<T> v = buf[tpad<T>(q * C + c)];
             keys[2 * m] = ord_key(v.re);
             keys[2 * m + 1] = ord_key(v.im);
         }
     } else {
         cplx<T>* dst = (cplx<T>*)(P.dst_sel ? d.sortB : d.sortA);
-        for (int e = tid; e < R * FFT_COLS; e += nt) {
+        for (int e = tid; e < R * C; e += nt) {
             int q, c;
-            if (Ns == 1) { c = e / R; q = e % R; } else { q = e / FFT_COLS; c = e % FFT_COLS; }
+            if (Ns == 1) { c = e / R; q = e % R; } else { q = e / C; c = e % C; }
             const int64_t jm = (Ns > 1) ? j0m + c : 0;
             const int64_t m = (j0 + c - jm) * R + jm + (int64_t)q * Ns;
-            dst[m] = buf[tpad<T>(q * FFT_COLS + c)];
+            dst[m] = buf[tpad<T>(q * C + c)];
         }
     }
 }

@@ -10,9 +10,8 @@
 // its butterflies' inputs into registers, meets the workgroup barrier and then
 // writes in place: one LDS buffer of M values (plus padding) suffices.
 //
-// Twiddles come from a table of W_N^t = exp(-2 pi i t / N), t = 0..N/2, for the
-// real length N = 2M (computed in double on the host, rounded once to T);
-// W_M^u = W_N^{2u}.
+// Twiddles W_N^t = exp(-2 pi i t / N) for the real length N = 2M come from a
+// two-level double-precision table in LDS (W_M^u = W_N^{2u}).
 #pragma once
 #include "common.hpp"
 
@@ -34,17 +33,34 @@ AGN_DEV int rpad(int p) { return 2 * cpad<T>(p >> 1) + (p & 1); }
 template <typename T>
 __host__ __device__ inline int cpad_size(int m) { return m + (m >> (sizeof(T) == 4 ? 5 : 4)) + 1; }
 
-// W_N^t for 0 <= t < N from the half table (t <= N/2); inverse = conjugate.
+// Twiddles W_N^t, 0 <= t < N, from a two-level table held in LDS:
+// W_N^t = hi[t >> bits] * lo[t & (2^bits - 1)] with lo[u] = W_N^u and
+// hi[v] = W_N^{v 2^bits}, both in double precision; the product is formed in
+// double precision and rounded once to T.  Inverse = conjugate.
+struct TwLds {
+    const cplx<double>* lo;
+    const cplx<double>* hi;
+    int bits;
+};
+
+// bits of the low level for a length-N table (2^bits >= sqrt(N))
+__host__ __device__ inline int tw_lds_bits(int N) {
+    int lg = 0;
+    while ((1 << lg) < N) ++lg;
+    return (lg + 1) / 2;
+}
+// entries of the two levels together
+__host__ __device__ inline int tw_lds_entries(int N) {
+    const int b = tw_lds_bits(N);
+    return (1 << b) + (N + (1 << b) - 1) / (1 << b);
+}
+
 template <typename T, bool INV>
-AGN_DEV cplx<T> twiddle(const cplx<T>* __restrict__ tw, int t, int halfN) {
-    cplx<T> w;
-    if (t <= halfN) {
-        w = tw[t];
-    } else {
-        cplx<T> u = tw[t - halfN];
-        w = cmk(-u.re, -u.im);
-    }
-    return INV ? cconj(w) : w;
+AGN_DEV cplx<T> twiddle(const TwLds& tl, int t) {
+    const cplx<double> a = tl.hi[t >> tl.bits];
+    const cplx<double> b = tl.lo[t & ((1 << tl.bits) - 1)];
+    const cplx<double> w = cmul(a, b);
+    return cmk((T)w.re, (T)(INV ? -w.im : w.im));
 }
 
 // ---- small DFTs in registers; forward uses exp(-2 pi i / R) ----------------
@@ -120,10 +136,9 @@ AGN_DEV void dftR(cplx<T>* v) {
 // One Stockham pass.  The M/R butterflies are dealt round-robin to the nt
 // threads (at most BMAX per thread); all threads meet both barriers.  The
 // twiddles depend only on the butterfly index, so they are fetched before the
-// barrier, overlapping their latency with the LDS reads.
+// barrier.
 template <typename T, int R, int BMAX, bool INV>
-AGN_DEV void lds_pass(cplx<T>* buf, int M, int Ns, int tid, int nt,
-                      const cplx<T>* __restrict__ tw, int halfN) {
+AGN_DEV void lds_pass(cplx<T>* buf, int M, int Ns, int tid, int nt, const TwLds& tw) {
     cplx<T> v[BMAX][R];
     cplx<T> w[BMAX][R];
     tid = opaque(tid);
@@ -139,7 +154,7 @@ AGN_DEV void lds_pass(cplx<T>* buf, int M, int Ns, int tid, int nt,
             if (Ns > 1) {
                 const int jm = pow2 ? (j & (Ns - 1)) : (j % Ns);
 #pragma unroll
-                for (int r = 1; r < R; ++r) w[b][r] = twiddle<T, INV>(tw, jm * r * tstep, halfN);
+                for (int r = 1; r < R; ++r) w[b][r] = twiddle<T, INV>(tw, jm * r * tstep);
             }
         }
     }
@@ -164,15 +179,14 @@ AGN_DEV void lds_pass(cplx<T>* buf, int M, int Ns, int tid, int nt,
 
 // Full transform; E = M / nt complex values per thread (compile-time bound).
 template <typename T, int E, bool INV>
-AGN_DEV void lds_fft(cplx<T>* buf, int M, const FftPlan& plan, int tid, int nt,
-                     const cplx<T>* __restrict__ tw, int halfN) {
+AGN_DEV void lds_fft(cplx<T>* buf, int M, const FftPlan& plan, int tid, int nt, const TwLds& tw) {
     int Ns = 1;
     for (int p = 0; p < plan.npass; ++p) {
         const int R = plan.radix[p];
-        if (R == 8) lds_pass<T, 8, (E + 7) / 8, INV>(buf, M, Ns, tid, nt, tw, halfN);
-        else if (R == 4) lds_pass<T, 4, (E + 3) / 4, INV>(buf, M, Ns, tid, nt, tw, halfN);
-        else if (R == 3) lds_pass<T, 3, (E + 2) / 3, INV>(buf, M, Ns, tid, nt, tw, halfN);
-        else lds_pass<T, 2, (E + 1) / 2, INV>(buf, M, Ns, tid, nt, tw, halfN);
+        if (R == 8) lds_pass<T, 8, (E + 7) / 8, INV>(buf, M, Ns, tid, nt, tw);
+        else if (R == 4) lds_pass<T, 4, (E + 3) / 4, INV>(buf, M, Ns, tid, nt, tw);
+        else if (R == 3) lds_pass<T, 3, (E + 2) / 3, INV>(buf, M, Ns, tid, nt, tw);
+        else lds_pass<T, 2, (E + 1) / 2, INV>(buf, M, Ns, tid, nt, tw);
         Ns *= R;
     }
 }
@@ -195,15 +209,15 @@ AGN_DEV cplx<T> replace_modulus(cplx<T> X, T a) {
 //   Z'_k    = A + i conj(W_N^k) B,       Z'_{M-k} = conj(A) + i W_N^k conj(B)
 //   A       = Y_k + conj Y_{M-k},        B = Y_k - conj Y_{M-k}
 template <typename T>
-AGN_DEV void lds_fold_replace(cplx<T>* Z, int M, const T* __restrict__ amp,
-                              const cplx<T>* __restrict__ tw, int tid, int nthreads) {
+AGN_DEV void lds_fold_replace(cplx<T>* Z, int M, const T* __restrict__ amp, const TwLds& tw, int tid,
+                              int nthreads) {
     const int half = M / 2;
     for (int k = tid; k <= half; k += nthreads) {
         const int mk = (k == 0) ? 0 : M - k;
         const cplx<T> zk = Z[cpad<T>(k)], zm = Z[cpad<T>(mk)];
         const cplx<T> Ev = cmk((zk.re + zm.re) * (T)0.5, (zk.im - zm.im) * (T)0.5);
         const cplx<T> Ov = cmk((zk.im + zm.im) * (T)0.5, (zm.re - zk.re) * (T)0.5);
-        const cplx<T> w = tw[k];
+        const cplx<T> w = twiddle<T, false>(tw, k);
         const cplx<T> wO = cmul(w, Ov);
         if (k == 0) {
             const T xn = Ev.re - wO.re;  // X_M, real for real input

@@ -36,14 +36,14 @@ struct LcDesc {
     double* delta_out;     // [iters] or null
     int32_t* iters_done;   // [1] or null
     uint32_t* rank_out;    // [N] or null
-    const void* tw;        // cplx<T>[N/2 + 1], W_N^t
+    const void* tw;        // cplx<double>[N/2 + 1], W_N^t
     FftPlan plan;          // radices of the length-N/2 complex FFT
 };
 
 // LDS bytes of the iteration kernel (host and device agree on this layout).
 template <typename T>
 __host__ __device__ inline size_t lds_iter_layout(int N, int nt, size_t* ibuf_off, size_t* rank_off,
-                                                   size_t* scratch_off) {
+                                                   size_t* scratch_off, size_t* tw_off = nullptr) {
     typedef typename key_of<T>::type K;
     size_t work = sort_keys_bytes<K>(N);
     const size_t fft = (size_t)cpad_size<T>(N / 2) * sizeof(cplx<T>);
@@ -54,10 +54,12 @@ __host__ __device__ inline size_t lds_iter_layout(int N, int nt, size_t* ibuf_of
     const size_t ib = work;
     const size_t rk = ib + ((sort_ibuf_bytes(N) + 15) & ~(size_t)15);
     const size_t sc = rk + (((size_t)N * 2 + 15) & ~(size_t)15);
+    const size_t tw = sc + 128 * 4 + 64 * 8;
     if (ibuf_off) *ibuf_off = ib;
     if (rank_off) *rank_off = rk;
     if (scratch_off) *scratch_off = sc;
-    return sc + 128 * 4 + 64 * 8;
+    if (tw_off) *tw_off = tw;
+    return tw + (size_t)tw_lds_entries(N) * sizeof(cplx<double>);
 }
 
 __host__ __device__ inline size_t lds_prep_layout(int N, int nt, size_t* scratch_off) {
@@ -152,8 +154,8 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
         return;
     }
 
-    size_t ib_off, rk_off, sc_off;
-    lds_iter_layout<T>(N, nt, &ib_off, &rk_off, &sc_off);
+    size_t ib_off, rk_off, sc_off, tw_off;
+    lds_iter_layout<T>(N, nt, &ib_off, &rk_off, &sc_off, &tw_off);
     cplx<T>* Zc = (cplx<T>*)smem;
     T* Zf = (T*)smem;
     uint16_t* ibuf = (uint16_t*)(smem + ib_off);
@@ -165,8 +167,31 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
     const T* __restrict__ sT = (const T*)d.sT;
     const double* __restrict__ s64 = d.s64;
     const double* __restrict__ L = d.L;
-    const cplx<T>* __restrict__ tw = (const cplx<T>*)d.tw;
-    const FftPlan plan = d.plan;
+    // two-level twiddle table (double) in LDS, from the half table W_N^t, t <= N/2
+    TwLds tw;
+    tw.bits = tw_lds_bits(N);
+    {
+        cplx<double>* lo = (cplx<double>*)(smem + tw_off);
+        cplx<double>* hi = lo + (1 << tw.bits);
+        const cplx<double>* __restrict__ tg = (const cplx<double>*)d.tw;
+        const int nlo = 1 << tw.bits, nhi = (N + nlo - 1) / nlo;
+        for (int u = tid; u < nlo + nhi; u += nt) {
+            int t = u < nlo ? u : (u - nlo) * nlo;
+            // nlo <= N/2 + 1 entries of the half table exist for every N >= 2
+            cplx<double> w;
+            if (t <= M) {
+                w = tg[t];
+            } else {
+                const cplx<double> v = tg[t - M];  // W_N^{t} = -W_N^{t - N/2}
+                w = cmk(-v.re, -v.im);
+            }
+            if (u < nlo) lo[u] = w;
+            else hi[u - nlo] = w;
+        }
+        tw.lo = lo;
+        tw.hi = hi;
+    }
+    const FftPlan& plan = d.plan;  // read in place (uniform loads), not copied to private memory
 
 #pragma unroll 4
     for (int u = 0; u < IPT; ++u) {
@@ -180,9 +205,9 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
     int done = 0;
 #pragma unroll 1
     for (int it = 0; it < d.iters; ++it) {
-        lds_fft<T, E, false>(Zc, M, plan, tid, nt, tw, M);
+        lds_fft<T, E, false>(Zc, M, plan, tid, nt, tw);
         lds_fold_replace<T>(Zc, M, amp, tw, tid, nt);
-        lds_fft<T, E, true>(Zc, M, plan, tid, nt, tw, M);
+        lds_fft<T, E, true>(Zc, M, plan, tid, nt, tw);
 
         {
             K key[IPT];
@@ -197,9 +222,13 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
             block_radix_sort<K, IPT, true>(key, idx2, smem, ibuf, scratch);
         }
 
+        // x_i[t] = s[k]; Eq. 4 terms from the log10 table.  The exact
+        // fixed-point test (values equal, not only ranks) matters only to the
+        // stopping rule, so the sorted draw is read only when tol >= 0.
         double acc = 0.0;
         uint32_t chg = 0;
         const int tpost = opaque(tid);
+        const bool stop_rule = d.tol >= 0.0;
 #pragma unroll 4
         for (int u = 0; u < IPT; ++u) {
             const uint32_t k = (uint32_t)(u * nt + tpost);
@@ -209,16 +238,18 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
             if (ro != k) {
                 const double dl = L[k] - L[ro];
                 acc += dl * dl;
-                chg += (s64[k] != s64[ro]) ? 1u : 0u;
+                if (stop_rule) chg += (s64[k] != s64[ro]) ? 1u : 0u;
             }
             Zf[rpad<T>(t)] = sT[k];
         }
         acc = block_sum<double>(acc, dscratch);
-        chg = block_sum<uint32_t>(chg, scratch + 64);
         const double delta = sqrt(acc / (double)N);
         if (tid == 0 && d.delta_out) d.delta_out[it] = delta;
         done = it + 1;
-        if (d.tol >= 0.0 && (chg == 0u || (d.tol > 0.0 && delta <= d.tol))) break;
+        if (stop_rule) {
+            chg = block_sum<uint32_t>(chg, scratch + 64);
+            if (chg == 0u || (d.tol > 0.0 && delta <= d.tol)) break;
+        }
     }
     __syncthreads();
 #pragma unroll 4

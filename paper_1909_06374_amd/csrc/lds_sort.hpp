@@ -19,7 +19,10 @@
 namespace agn {
 
 // Exclusive scan of one uint32 per thread over the block (fixed order).
-AGN_DEV uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= nw + 1 words */,
+// One barrier: every wave publishes its total, then every thread adds the
+// totals of the waves before its own.  The caller must not overwrite
+// scratch[0 .. nw) until every thread has returned (a later barrier).
+AGN_DEV uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= nw words */,
                                       uint32_t* total) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nw = (nt + 63) >> 6;
@@ -32,20 +35,14 @@ AGN_DEV uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= nw + 1
     const int last = (nt - (wave << 6) < 64) ? (nt - (wave << 6) - 1) : 63;
     if (lane == last) scratch[wave] = inc;
     __syncthreads();
-    if (tid == 0) {
-        uint32_t run = 0;
-        for (int w = 0; w < nw; ++w) {
-            uint32_t t = scratch[w];
-            scratch[w] = run;
-            run += t;
-        }
-        scratch[nw] = run;
+    uint32_t pre = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+        const uint32_t t = scratch[w];
+        pre += (w < wave) ? t : 0u;
+        tot += t;
     }
-    __syncthreads();
-    uint32_t r = scratch[wave] + inc - v;
-    if (total) *total = scratch[nw];
-    __syncthreads();
-    return r;
+    if (total) *total = tot;
+    return pre + inc - v;
 }
 
 constexpr int SORT_RB = 5;
