@@ -30,6 +30,41 @@ LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
 FP32_PEAK_TFLOPS = 157.3        # FP32 vector, packed FMA
 
 
+def source_hash():
+    """md5 (first 8 hex digits) of the HIP sources, in file-name order."""
+    import glob
+    import hashlib
+    h = hashlib.md5()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1909_06374_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:8]
+
+
+def recorded_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the rocprofv3 counter runs
+    recorded in profiles/traffic.txt (FETCH_SIZE and WRITE_SIZE per dispatch,
+    scaled by the copy calibration), or None if none is recorded or the HIP
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv, rows = {}, {}
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if not line:
+            continue
+        parts = line.split()
+        if len(parts) == 3 and parts[1] == "=":
+            kv[parts[0]] = parts[2]
+        elif len(parts) == 4:
+            rows[(parts[0], parts[1])] = (float(parts[2]), float(parts[3]))
+    if kv.get("sources") != source_hash() or (workload, kernel) not in rows:
+        return None
+    f, w = rows[(workload, kernel)]
+    return (f * float(kv["fetch_scale"]) + w * float(kv["write_scale"])) * 1024.0
+
+
 def lds_flops_per_sample_iter(n):
     """FP32 flops per sample-iteration of the LDS-resident kernel counted
     algorithmically: two complex FFTs of length N/2 at 5 (N/2) log2(N/2) flops
@@ -192,7 +227,8 @@ def main():
         per = lds_bytes_per_sample_iter(n, pb)
         lds_gbs = per * samples * iters / (dom_ms / 1000.0) / 1e9
         roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                "traffic": recorded_traffic(args.workload, dom),
                 "flops_per_sample_iter": fl, "avg_launch_ms": round(dom_ms, 4),
                 "lds_view": {"achieved_gbs": round(lds_gbs, 1), "peak_gbs": round(LDS_PEAK_GBS, 1),
                              "frac": round(lds_gbs / LDS_PEAK_GBS, 4), "bytes_per_sample_iter": per}}
@@ -200,7 +236,8 @@ def main():
         per = hbm_bytes_per_sample(dom, pb)
         achieved = per * samples / (dom_ms / 1000.0) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": recorded_traffic(args.workload, dom),
                 "bytes_per_sample_per_launch": per, "avg_launch_ms": round(dom_ms, 4)}
 
     out = {

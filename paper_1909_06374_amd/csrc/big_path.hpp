@@ -29,9 +29,12 @@
 
 namespace agn {
 
-constexpr int BIG_TILE = 4096;       // sort / delta tile (256 threads x 16)
-constexpr int BIG_THREADS = 256;
-constexpr int BIG_IPT = 16;
+constexpr int BIG_TILE = 8192;       // sort / delta tile
+constexpr int BIG_THREADS = 256;     // block of the streaming kernels (BIG_IPT elements each)
+constexpr int BIG_IPT = BIG_TILE / BIG_THREADS;
+constexpr int SCAT_THREADS = 512;    // block of the scatter kernel (SCAT_IPT keys each)
+constexpr int SCAT_IPT = BIG_TILE / SCAT_THREADS;
+constexpr int SCAT_WAVES = SCAT_THREADS / 64;
 constexpr int FFT_COLS_MIN = 16;     // fewest butterflies per FFT workgroup
 constexpr int FFT_COLS_MAX = 64;     // most butterflies per FFT workgroup
 constexpr int TW_LO_BITS = 12;       // two-level twiddle split
@@ -337,23 +340,30 @@ struct SortPass {
 };
 
 // grid: (ntiles, curves), block 256.  hist[d * ntiles + tile] = count of digit d.
+// All loads of a thread are issued before its counting; each wave counts into
+// its own LDS histogram (fewer colliding atomics when few digits dominate).
 template <typename K>
 __global__ __launch_bounds__(BIG_THREADS) void k_sort_hist(const BigCurve* __restrict__ cv, SortPass P,
                                                            int64_t ntiles) {
-    __shared__ uint32_t h[256];
+    __shared__ uint32_t h[BIG_THREADS / 64][256];
     const BigCurve& d = cv[blockIdx.y];
     if (d.state[1] == 0) return;
-    const int tid = threadIdx.x;
-    h[tid] = 0;
-    __syncthreads();
+    const int tid = threadIdx.x, wave = tid >> 6;
     const K* keys = (const K*)(P.src_sel ? d.sortB : d.sortA);
     const int64_t base = (int64_t)blockIdx.x * BIG_TILE;
-    for (int i = 0; i < BIG_IPT; ++i) {
-        const K k = keys[base + i * BIG_THREADS + tid];
-        atomicAdd(&h[(uint32_t)(k >> P.shift) & 255u], 1u);
-    }
+    K k[BIG_IPT];
+#pragma unroll
+    for (int i = 0; i < BIG_IPT; ++i) k[i] = keys[base + i * BIG_THREADS + tid];
+#pragma unroll
+    for (int w = 0; w < BIG_THREADS / 64; ++w) h[w][tid] = 0;
     __syncthreads();
-    d.hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
+#pragma unroll
+    for (int i = 0; i < BIG_IPT; ++i) atomicAdd(&h[wave][(uint32_t)(k[i] >> P.shift) & 255u], 1u);
+    __syncthreads();
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < BIG_THREADS / 64; ++w) c += h[w][tid];
+    d.hist[(int64_t)tid * ntiles + blockIdx.x] = c;
 }
 
 // grid: (256, curves), block 256: exclusive scan of one digit's tile counts,
@@ -408,46 +418,49 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sort_scan_digits(const BigCurve
     d.dstart[tid] = wpre + inc - v;
 }
 
-// grid: (ntiles, curves), block 256.  Stable scatter of one 8-bit digit.
-// The tile is first rearranged in LDS into digit order; then thread q takes
-// tile positions q, q + 256, ... so that consecutive threads write consecutive
-// global positions inside each digit's run.
+// grid: (ntiles, curves), block SCAT_THREADS.  Stable scatter of one 8-bit
+// digit.  Each wave ranks its 64 x SCAT_IPT keys with ballots and per-wave
+// running digit counters; the tile is then rearranged in LDS into digit order,
+// and thread q takes tile positions q, q + SCAT_THREADS, ... so that
+// consecutive threads write consecutive global positions inside each digit's
+// run (8192-key tiles: runs of 32 keys on average).
 template <typename K>
-__global__ __launch_bounds__(BIG_THREADS) void k_sort_scatter(const BigCurve* __restrict__ cv, SortPass P,
-                                                              int64_t ntiles) {
-    __shared__ uint32_t wcnt[4][256];   // per-wave running digit counters
-    __shared__ uint32_t wpre[4][256];   // exclusive prefix over waves
-    __shared__ uint32_t tstart[256];    // digit start inside the tile
-    __shared__ uint32_t gbase[256];     // global start of the tile's digit run
-    __shared__ uint32_t wtot[4];        // per-wave digit-count totals
+__global__ __launch_bounds__(SCAT_THREADS) void k_sort_scatter(const BigCurve* __restrict__ cv, SortPass P,
+                                                               int64_t ntiles) {
+    __shared__ uint16_t wcnt[SCAT_WAVES][256];  // per-wave running digit counters (<= 64 * SCAT_IPT)
+    __shared__ uint16_t wpre[SCAT_WAVES][256];  // exclusive prefix over waves
+    __shared__ uint32_t tstart[256];            // digit start inside the tile
+    __shared__ uint32_t gbase[256];             // global start of the tile's digit run
+    __shared__ uint32_t wtot[4];                // digit-scan totals of the first four waves
     __shared__ K skey[BIG_TILE];
     __shared__ uint32_t sval[BIG_TILE];
+    static_assert(64 * SCAT_IPT * (SCAT_WAVES - 1) < 65536, "wave prefix must fit 16 bits");
     const BigCurve& d = cv[blockIdx.y];
     if (d.state[1] == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n = d.n;
     const int64_t tile = blockIdx.x;
-    const int64_t base = tile * BIG_TILE + (int64_t)wave * 64 * BIG_IPT;
+    const int64_t base = tile * BIG_TILE + (int64_t)wave * 64 * SCAT_IPT;
     const unsigned char* srcb = P.src_sel ? d.sortB : d.sortA;
     const K* skeys = (const K*)srcb;
     const uint32_t* svals = (const uint32_t*)(srcb + (size_t)n * sizeof(K));
 
-    for (int q = lane; q < 256; q += 64) wcnt[wave][q] = 0u;
+    for (int q = lane; q < 256; q += 64) wcnt[wave][q] = 0;
     __syncthreads();
 
-    K key[BIG_IPT];
-    uint32_t val[BIG_IPT];
-    uint32_t loc[BIG_IPT];
+    K key[SCAT_IPT];
+    uint32_t val[SCAT_IPT];
+    uint32_t loc[SCAT_IPT];
 #pragma unroll
-    for (int i = 0; i < BIG_IPT; ++i) {
+    for (int i = 0; i < SCAT_IPT; ++i) {
         const int64_t p = base + i * 64 + lane;
         key[i] = skeys[p];
         val[i] = P.first ? (uint32_t)p : svals[p];
     }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    volatile uint32_t* vc = wcnt[wave];
+    volatile uint16_t* vc = wcnt[wave];
 #pragma unroll
-    for (int i = 0; i < BIG_IPT; ++i) {
+    for (int i = 0; i < SCAT_IPT; ++i) {
         const uint32_t dg = (uint32_t)(key[i] >> P.shift) & 255u;
         uint64_t peers = ~0ull;
 #pragma unroll
@@ -458,37 +471,42 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sort_scatter(const BigCurve* __
         const uint32_t below = (uint32_t)__popcll(peers & lt);
         const uint32_t cur = vc[dg];
         __builtin_amdgcn_wave_barrier();
-        if (below == 0) vc[dg] = cur + (uint32_t)__popcll(peers);
+        if (below == 0) vc[dg] = (uint16_t)(cur + (uint32_t)__popcll(peers));
         __builtin_amdgcn_wave_barrier();
         loc[i] = cur + below;
     }
     __syncthreads();
-    {
-        // per digit: prefix over waves, tile total; then exclusive scan over digits
+    // per digit (threads 0..255): prefix over waves, tile total, scan over digits
+    uint32_t tot = 0, inc = 0;
+    if (tid < 256) {
         const int q = tid;
-        const uint32_t c0 = wcnt[0][q], c1 = wcnt[1][q], c2 = wcnt[2][q], c3 = wcnt[3][q];
-        wpre[0][q] = 0;
-        wpre[1][q] = c0;
-        wpre[2][q] = c0 + c1;
-        wpre[3][q] = c0 + c1 + c2;
-        const uint32_t tot = c0 + c1 + c2 + c3;
-        uint32_t inc = tot;
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < SCAT_WAVES; ++w) {
+            const uint32_t c = wcnt[w][q];
+            wpre[w][q] = (uint16_t)run;
+            run += c;
+        }
+        tot = run;
+        inc = tot;
 #pragma unroll
         for (int s2 = 1; s2 < 64; s2 <<= 1) {
             const uint32_t o = __shfl_up(inc, s2, 64);
             if (lane >= s2) inc += o;
         }
         if (lane == 63) wtot[wave] = inc;
-        __syncthreads();
+    }
+    __syncthreads();
+    if (tid < 256) {
+        const int q = tid;
         uint32_t pre = 0;
         for (int w = 0; w < wave; ++w) pre += wtot[w];
-        const uint32_t ts = pre + inc - tot;
-        tstart[q] = ts;
+        tstart[q] = pre + inc - tot;
         gbase[q] = d.dstart[q] + d.hist[(int64_t)q * ntiles + tile];
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < BIG_IPT; ++i) {
+    for (int i = 0; i < SCAT_IPT; ++i) {
         const uint32_t dg = (uint32_t)(key[i] >> P.shift) & 255u;
         const uint32_t pl = tstart[dg] + wpre[wave][dg] + loc[i];
         skey[pl] = key[i];
@@ -501,7 +519,7 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sort_scatter(const BigCurve* __
     uint32_t* rnk = P.rank_sel ? d.rankB : d.rankA;
     double* xn = P.rank_sel ? d.X1 : d.X0;
 #pragma unroll 4
-    for (int q = tid; q < BIG_TILE; q += BIG_THREADS) {
+    for (int q = tid; q < BIG_TILE; q += SCAT_THREADS) {
         const K k = skey[q];
         const uint32_t v = sval[q];
         const uint32_t dg = (uint32_t)(k >> P.shift) & 255u;

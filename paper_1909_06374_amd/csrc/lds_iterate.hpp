@@ -225,22 +225,42 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
         // x_i[t] = s[k]; Eq. 4 terms from the log10 table.  The exact
         // fixed-point test (values equal, not only ranks) matters only to the
         // stopping rule, so the sorted draw is read only when tol >= 0.
+        // Groups of G positions; in each, all LDS lookups first, then all
+        // table loads (issued together), then the updates.  A sample whose
+        // rank did not change adds an exact zero.
         double acc = 0.0;
         uint32_t chg = 0;
         const int tpost = opaque(tid);
         const bool stop_rule = d.tol >= 0.0;
-#pragma unroll 4
-        for (int u = 0; u < IPT; ++u) {
-            const uint32_t k = (uint32_t)(u * nt + tpost);
-            const uint32_t t = ibuf[hpad(k)];
-            const uint32_t ro = rank16[t];
-            rank16[t] = (uint16_t)k;
-            if (ro != k) {
-                const double dl = L[k] - L[ro];
-                acc += dl * dl;
-                if (stop_rule) chg += (s64[k] != s64[ro]) ? 1u : 0u;
+        constexpr int HALF = (IPT % 4 == 0) ? 4 : 2;  // positions per group
+#pragma unroll
+        for (int h = 0; h < IPT / HALF; ++h) {
+            uint32_t tr[HALF];
+            double lk[HALF], lr[HALF];
+            T sv[HALF];
+#pragma unroll
+            for (int u = 0; u < HALF; ++u) {
+                const uint32_t k = (uint32_t)((h * HALF + u) * nt + tpost);
+                const uint32_t t = ibuf[hpad(k)];
+                tr[u] = t | ((uint32_t)rank16[t] << 16);
             }
-            Zf[rpad<T>(t)] = sT[k];
+#pragma unroll
+            for (int u = 0; u < HALF; ++u) {
+                const uint32_t k = (uint32_t)((h * HALF + u) * nt + tpost);
+                lk[u] = L[k];
+                lr[u] = L[tr[u] >> 16];
+                sv[u] = sT[k];
+            }
+#pragma unroll
+            for (int u = 0; u < HALF; ++u) {
+                const uint32_t k = (uint32_t)((h * HALF + u) * nt + tpost);
+                const uint32_t t = tr[u] & 0xFFFFu, ro = tr[u] >> 16;
+                rank16[t] = (uint16_t)k;
+                const double dl = lk[u] - lr[u];
+                acc += dl * dl;
+                if (stop_rule && ro != k) chg += (s64[k] != s64[ro]) ? 1u : 0u;
+                Zf[rpad<T>(t)] = sv[u];
+            }
         }
         acc = block_sum<double>(acc, dscratch);
         const double delta = sqrt(acc / (double)N);
