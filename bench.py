@@ -121,7 +121,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ptf_batch",
-                    choices=["ptf_batch", "single_curve", "lsst_long", "lsst_long_fp64", "uneven_batch", "serving"])
+                    choices=["ptf_batch", "single_curve", "lsst_long", "lsst_long_fp64", "uneven_batch", "serving",
+                             "paper_scale"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the FP32-vs-FP64 accuracy report")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -162,6 +163,12 @@ def main():
         erdf = w["erdf"].reshape(-1)
         desc = (f"ptf_batch: {n_curves} curves x N={n}, dt=1 d, per-curve Eq.3 slopes/break, "
                 f"broken-power-law PDF draws, {iters} iterations, FP32 form")
+    elif args.workload == "paper_scale":
+        n_curves, n, iters, prec = 1, 2**27, 200, agn.AGN_FP64
+        params = [agn.psd_params(0.0, 1.0 / (10 * synth.YEAR), 1.0, 2.0)]
+        erdf = None
+        desc = ("paper_scale: 1 curve x N=2^27 (the paper's largest run), dt=7 d, Eq.3 slopes (1, 2), break "
+                "1/(10 yr), broken-power-law PDF drawn on the device, 200 iterations, FP64")
     elif args.workload.startswith("lsst_long"):
         n_curves, n, iters = 4, 2**26, 100
         prec = agn.AGN_FP64 if args.workload.endswith("fp64") else agn.AGN_FP32
@@ -176,14 +183,20 @@ def main():
         params = [agn.psd_params(**w["params"])]
         erdf = w["erdf"]
         desc = "single_curve: 1 curve x N=1024, dt=1 d, bending power law, 50 iterations, FP64"
-    dt_days = 7.0 if args.workload.startswith("lsst_long") else 1.0
+    dt_days = 7.0 if (args.workload.startswith("lsst_long") or args.workload == "paper_scale") else 1.0
 
     ns = [n] * n_curves
     offs = [c * n for c in range(n_curves)]
     seeds = [1000 + c for c in range(n_curves)]
     ids = list(range(n_curves))
     ctx = agn.Context(0)
-    erdf_t = torch.as_tensor(erdf).to(dev)
+    if erdf is None:
+        erdf_t = torch.empty(n_curves * n, dtype=torch.float64, device=dev)
+        for c in range(n_curves):
+            agn.agn_erdf_draw(ctx, agn.erdf_params(), n, 27, c, erdf_t[c * n:(c + 1) * n])
+        torch.cuda.synchronize()
+    else:
+        erdf_t = torch.as_tensor(erdf).to(dev)
     x = torch.empty(n_curves * n, dtype=torch.float64, device=dev)
     delta = torch.empty(n_curves * iters, dtype=torch.float64, device=dev)
     done = torch.empty(n_curves, dtype=torch.int32, device=dev)
@@ -258,7 +271,9 @@ def main():
 
     if not args.no_cpu_baseline:
         import oracle
-        if args.workload.startswith("lsst_long"):
+        if erdf is None:
+            erdf = erdf_t[:2**20].cpu().numpy()
+        if args.workload.startswith("lsst_long") or args.workload == "paper_scale":
             # bounded sample: one 2^20-sample piece of the first curve, 3 iterations,
             # scaled per sample-iteration to the full 100-iteration run
             k, ns_, it_ = 1, 2**20, 3

@@ -241,6 +241,33 @@ typedef struct {
 int agn_erdf_draw(agn_ctx* ctx, const agn_erdf_params* p, int64_t n, uint64_t seed,
                   uint32_t curve_id, double* out, void* stream);
 
+/*
+ * Observables after the path (App. A).
+ *
+ * agn_periodogram_batch -- the periodogram of Eq. A2 of n_curves real series
+ * (for example the generator's output), in double precision:
+ *   P_c[j] = 2 / N^2 |sum_t x_c[t] exp(-2 pi i j t / N)|^2,  j = 0 .. N/2,
+ * and, if bins_out is not NULL, its arithmetic means over logarithmic
+ * frequency bins: j >= 1 falls in bin floor(log10(j) / dex + 1e-9) (bins of
+ * `dex` in log10 frequency starting at the first Fourier frequency); empty
+ * bins are dropped and the others are written in increasing frequency.
+ *   n, offset  host, n_curves entries: length (2^a or 3*2^a, >= 4) and EVEN
+ *              element offset of each curve in x (device)
+ *   p_offset   host: element offset of curve c's N/2+1 values in P_out (device)
+ *   b_offset   host (with bins_out): offset of curve c's bins in bins_out
+ *              (device); agn_log_bin_count gives their number
+ *   ws         device workspace of agn_periodogram_workspace_size bytes
+ *              (the same dex, or dex <= 0 without bins)
+ * Errors: AGN_EINVAL (NULL, negative or odd offset, bad dex, small
+ * workspace), AGN_EUNSUPPORTED_N.  Stream-ordered; nothing is enqueued on error.
+ */
+int agn_log_bin_count(int64_t n, double dex, int32_t* count);
+int agn_periodogram_workspace_size(int32_t n_curves, const int64_t* n, double dex, size_t* bytes);
+int agn_periodogram_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n, const int64_t* offset,
+                          const double* x, const int64_t* p_offset, double* P_out, double dex,
+                          const int64_t* b_offset, double* bins_out, void* ws, size_t ws_bytes,
+                          void* stream);
+
 /* ---- instrumentation ----------------------------------------------------- */
 
 /* Turns per-kernel timing on (1) or off (0) for calls made with this context.

@@ -80,6 +80,9 @@ def _declare(lib):
     lib.agn_batch_plan_launch.argtypes = [vp, vp]
     lib.agn_batch_plan_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.agn_batch_plan_destroy.argtypes = [vp]
+    lib.agn_log_bin_count.argtypes = [i64, d, C.POINTER(i32)]
+    lib.agn_periodogram_workspace_size.argtypes = [i32, vp, d, C.POINTER(sz)]
+    lib.agn_periodogram_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, d, vp, vp, vp, sz, vp]
     lib.agn_ctx_set_profiling.argtypes = [vp, C.c_int]
     lib.agn_ctx_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(d), C.POINTER(i64), C.c_int]
     lib.agn_ctx_kernel_names.argtypes = []
@@ -88,7 +91,8 @@ def _declare(lib):
               "agn_workspace_size", "agn_batch_workspace_size", "agn_psd_spectrum",
               "agn_lc_iterate", "agn_lc_generate", "agn_lc_generate_batch", "agn_test_philox",
               "agn_ctx_set_profiling", "agn_ctx_kernel_time", "agn_erdf_draw", "agn_batch_plan_create",
-              "agn_batch_plan_launch", "agn_batch_plan_info", "agn_batch_plan_destroy"):
+              "agn_batch_plan_launch", "agn_batch_plan_info", "agn_batch_plan_destroy", "agn_log_bin_count",
+              "agn_periodogram_workspace_size", "agn_periodogram_batch"):
         getattr(lib, f).restype = C.c_int
 
 
@@ -287,6 +291,34 @@ def agn_batch_plan_launch(plan: BatchPlan, stream=None):
     if not plan.handle:
         raise AgnError(int(-1), "plan is closed")
     _check(lib().agn_batch_plan_launch(plan.handle, _stream(stream, plan.ctx.device)))
+
+
+def agn_log_bin_count(n, dex) -> int:
+    c = C.c_int32()
+    _check(lib().agn_log_bin_count(int(n), float(dex), C.byref(c)))
+    return c.value
+
+
+def agn_periodogram_workspace_size(n, dex=0.0) -> int:
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    b = C.c_size_t()
+    _check(lib().agn_periodogram_workspace_size(len(n), n.ctypes.data_as(C.c_void_p), float(dex), C.byref(b)))
+    return b.value
+
+
+def agn_periodogram_batch(ctx: Context, n, offset, x, p_offset, P_out, dex=0.0, b_offset=None, bins_out=None,
+                          ws=None, stream=None):
+    """n, offset, p_offset, b_offset: host sequences; x, P_out, bins_out, ws: GPU tensors."""
+    vp = C.c_void_p
+    nc = len(n)
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    offset = np.ascontiguousarray(offset, dtype=np.int64)
+    p_offset = np.ascontiguousarray(p_offset, dtype=np.int64)
+    bo = None if b_offset is None else np.ascontiguousarray(b_offset, dtype=np.int64)
+    _check(lib().agn_periodogram_batch(
+        ctx.handle, nc, n.ctypes.data_as(vp), offset.ctypes.data_as(vp), _ptr(x), p_offset.ctypes.data_as(vp),
+        _ptr(P_out), float(dex), None if bo is None else bo.ctypes.data_as(vp), _ptr(bins_out), _ptr(ws),
+        0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, ctx.device)))
 
 
 def agn_erdf_draw(ctx: Context, params, n, seed, curve_id, out, stream=None):

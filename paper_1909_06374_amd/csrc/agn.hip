@@ -20,6 +20,7 @@
 #include "common.hpp"
 #include "big_path.hpp"
 #include "erdf.hpp"
+#include "observables.hpp"
 #include "lds_iterate.hpp"
 #include "philox.hpp"
 #include "spectrum.hpp"
@@ -193,7 +194,7 @@ struct agn_ctx {
 
 static const char* KERNEL_NAMES =
     "spectrum_partial,spectrum_norm,spectrum_amp,lds_prep,lds_iterate,big_prep,fft_pass,fold,"
-    "sort_hist,sort_scan,sort_scatter,delta,big_output,erdf_draw,batch_graph";
+    "sort_hist,sort_scan,sort_scatter,delta,big_output,erdf_draw,batch_graph,periodogram,log_bins";
 
 // Kernel timing: events recorded on the launch stream around each launch.
 struct ProfScope {
@@ -1279,6 +1280,227 @@ extern "C" int agn_batch_plan_destroy(agn_batch_plan* pl) {
     (void)hipSetDevice(pl->ctx ? pl->ctx->device : 0);
     destroy_plan_resources(*pl);
     delete pl;
+    return AGN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// observables after the path: periodogram (Eq. A2) and log-binned means
+// ---------------------------------------------------------------------------
+static bool pg_lds(int64_t n) {
+    if (!n_supported(n)) return false;
+    return (n % 3 == 0) ? n <= 12288 : n <= 16384;
+}
+
+// Bin of j >= 1: floor(log10(j) / dex + 1e-9); non-empty bins in increasing j.
+static int64_t bin_of(int64_t j, double dex) { return (int64_t)std::floor(std::log10((double)j) / dex + 1e-9); }
+
+static void log_bin_edges(int64_t n, double dex, std::vector<int64_t>* edges) {
+    edges->clear();
+    const int64_t h = n / 2;
+    int64_t j = 1;
+    while (j <= h) {
+        const int64_t b = bin_of(j, dex);
+        // first j' > j in a later bin: start below the estimate, step to it
+        int64_t g = (int64_t)std::ceil(std::pow(10.0, (double)(b + 1) * dex)) - 2;
+        if (g <= j) g = j + 1;
+        while (g > j + 1 && bin_of(g - 1, dex) > b) --g;
+        while (g <= h && bin_of(g, dex) <= b) ++g;
+        if (g > h + 1) g = h + 1;
+        edges->push_back(j);
+        edges->push_back(g);
+        j = g;
+    }
+}
+
+extern "C" int agn_log_bin_count(int64_t n, double dex, int32_t* count) {
+    if (!count) return fail(AGN_EINVAL, "count is NULL");
+    if (!n_supported(n)) return fail(AGN_EUNSUPPORTED_N, "n=%lld is not 2^a or 3*2^a in [2, 2^27]", (long long)n);
+    if (!(dex > 0.0) || !std::isfinite(dex)) return fail(AGN_EINVAL, "dex must be finite and > 0");
+    std::vector<int64_t> e;
+    log_bin_edges(n, dex, &e);
+    *count = (int32_t)(e.size() / 2);
+    return AGN_OK;
+}
+
+static size_t pg_header_ws(int32_t nc) {
+    return align256(sizeof(PgDesc) * (size_t)nc) + align256(sizeof(BigCurve) * (size_t)nc) +
+           align256(sizeof(BinDesc) * (size_t)nc) + align256(sizeof(double*) * (size_t)nc);
+}
+
+static size_t pg_curve_ws(int64_t n, double dex) {
+    size_t b = 0;
+    if (!pg_lds(n)) b += 2 * align256((size_t)n * 8) + align256(16);  // FFT ping-pong + state
+    if (dex > 0.0) {
+        std::vector<int64_t> e;
+        log_bin_edges(n, dex, &e);
+        b += align256(e.size() * sizeof(int64_t));
+    }
+    return b;
+}
+
+extern "C" int agn_periodogram_workspace_size(int32_t n_curves, const int64_t* n, double dex, size_t* bytes) {
+    if (!bytes || (n_curves > 0 && !n)) return fail(AGN_EINVAL, "NULL argument");
+    if (n_curves < 0) return fail(AGN_EINVAL, "n_curves < 0");
+    size_t b = pg_header_ws(n_curves);
+    for (int32_t c = 0; c < n_curves; ++c) {
+        if (!n_supported(n[c]) || n[c] < 4)
+            return fail(AGN_EUNSUPPORTED_N, "n=%lld is not 2^a or 3*2^a in [4, 2^27]", (long long)n[c]);
+        b += pg_curve_ws(n[c], dex);
+    }
+    *bytes = b;
+    return AGN_OK;
+}
+
+template <int E>
+static void launch_pg(const PgDesc* d, int count, int nt, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL((k_lds_periodogram<E>), dim3(count), dim3(nt), lds, st, d);
+}
+
+extern "C" int agn_periodogram_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n, const int64_t* offset,
+                                     const double* x, const int64_t* p_offset, double* P_out, double dex,
+                                     const int64_t* b_offset, double* bins_out, void* ws, size_t ws_bytes,
+                                     void* stream) {
+    if (!ctx) return fail(AGN_EINVAL, "ctx is NULL");
+    if (n_curves < 0) return fail(AGN_EINVAL, "n_curves < 0");
+    if (n_curves == 0) return AGN_OK;
+    if (!n || !offset || !x || !p_offset || !P_out) return fail(AGN_EINVAL, "NULL argument");
+    if (bins_out && (!b_offset || !(dex > 0.0) || !std::isfinite(dex)))
+        return fail(AGN_EINVAL, "bins_out needs b_offset and a finite dex > 0");
+    const double dx = bins_out ? dex : 0.0;
+    size_t need = 0;
+    int rc = agn_periodogram_workspace_size(n_curves, n, dx, &need);
+    if (rc) return rc;
+    if (!ws || ws_bytes < need)
+        return fail(AGN_EINVAL, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+    for (int32_t c = 0; c < n_curves; ++c) {
+        if (offset[c] < 0 || p_offset[c] < 0 || (bins_out && b_offset[c] < 0))
+            return fail(AGN_EINVAL, "negative offset for curve %d", c);
+        if (offset[c] & 1) return fail(AGN_EINVAL, "offset[%d] must be even", c);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    const int32_t nc = n_curves;
+    std::vector<int> order(nc);
+    for (int i = 0; i < nc; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const bool la = pg_lds(n[a]), lb = pg_lds(n[b]);
+        if (la != lb) return la;
+        return n[a] < n[b];
+    });
+    unsigned char* base = (unsigned char*)ws;
+    PgDesc* d_pg = (PgDesc*)base;
+    BigCurve* d_bg = (BigCurve*)(base + align256(sizeof(PgDesc) * (size_t)nc));
+    BinDesc* d_bd = (BinDesc*)((unsigned char*)d_bg + align256(sizeof(BigCurve) * (size_t)nc));
+    double** d_pp = (double**)((unsigned char*)d_bd + align256(sizeof(BinDesc) * (size_t)nc));
+    std::vector<PgDesc> pg(nc);
+    std::vector<BigCurve> bg(nc);
+    std::vector<BinDesc> bd(nc);
+    std::vector<double*> pp(nc);
+    std::vector<std::vector<int64_t>> edges(nc);
+    size_t off = pg_header_ws(nc);
+    int32_t maxbins = 0;
+    int n_lds = 0;
+    for (int i = 0; i < nc; ++i) {
+        const int c = order[i];
+        const int64_t nn = n[c];
+        memset(&pg[i], 0, sizeof(PgDesc));
+        memset(&bg[i], 0, sizeof(BigCurve));
+        memset(&bd[i], 0, sizeof(BinDesc));
+        pp[i] = P_out + p_offset[c];
+        if (pg_lds(nn)) {
+            ++n_lds;
+            pg[i].n = (int32_t)nn;
+            pg[i].x = x + offset[c];
+            pg[i].P = P_out + p_offset[c];
+            const void* tw = nullptr;
+            if ((rc = get_twiddles(ctx, nn, AGN_FP64, &tw))) return rc;
+            pg[i].tw = tw;
+            pg[i].plan = make_plan(nn / 2);
+        } else {
+            BigCurve& b = bg[i];
+            b.n = nn;
+            b.X0 = const_cast<double*>(x + offset[c]);  // read only (in_mode 1 of the first pass)
+            b.sortA = base + off; off += align256((size_t)nn * 8);
+            b.sortB = base + off; off += align256((size_t)nn * 8);
+            b.state = (int32_t*)(base + off); off += align256(16);
+        }
+        if (bins_out) {
+            log_bin_edges(nn, dex, &edges[i]);
+            bd[i].P = P_out + p_offset[c];
+            bd[i].out = bins_out + b_offset[c];
+            bd[i].edges = (const int64_t*)(base + off);
+            bd[i].nbins = (int32_t)(edges[i].size() / 2);
+            maxbins = std::max(maxbins, bd[i].nbins);
+            off += align256(edges[i].size() * sizeof(int64_t));
+        }
+    }
+    // one upload: header, then the bin edges
+    {
+        std::vector<unsigned char> hdr(off, 0);
+        memcpy(hdr.data(), pg.data(), sizeof(PgDesc) * (size_t)nc);
+        memcpy(hdr.data() + ((unsigned char*)d_bg - base), bg.data(), sizeof(BigCurve) * (size_t)nc);
+        memcpy(hdr.data() + ((unsigned char*)d_bd - base), bd.data(), sizeof(BinDesc) * (size_t)nc);
+        memcpy(hdr.data() + ((unsigned char*)d_pp - base), pp.data(), sizeof(double*) * (size_t)nc);
+        for (int i = 0; i < nc; ++i)
+            if (bins_out && !edges[i].empty())
+                memcpy(hdr.data() + ((const unsigned char*)bd[i].edges - base), edges[i].data(),
+                       edges[i].size() * sizeof(int64_t));
+        if ((rc = stage_upload(ctx, ws, hdr.data(), hdr.size(), st))) return rc;
+    }
+    {
+        ProfScope ps(ctx, "periodogram", st);
+        int i = 0;
+        while (i < n_lds) {
+            int j = i;
+            while (j < n_lds && pg[j].n == pg[i].n) ++j;
+            const int64_t nn = pg[i].n;
+            const int E = lds_ipt(nn) / 2, nt = (int)(nn / lds_ipt(nn));
+            const size_t lds = lds_pg_layout((int)nn, nullptr);
+            if (lds > ctx->lds_max) return fail(AGN_EUNSUPPORTED_N, "n=%lld: LDS too small", (long long)nn);
+            switch (E) {
+                case 1: launch_pg<1>(d_pg + i, j - i, nt, lds, st); break;
+                case 2: launch_pg<2>(d_pg + i, j - i, nt, lds, st); break;
+                case 3: launch_pg<3>(d_pg + i, j - i, nt, lds, st); break;
+                case 4: launch_pg<4>(d_pg + i, j - i, nt, lds, st); break;
+                case 6: launch_pg<6>(d_pg + i, j - i, nt, lds, st); break;
+                case 8: launch_pg<8>(d_pg + i, j - i, nt, lds, st); break;
+                default: return fail(AGN_EINVAL, "internal: no kernel for E=%d", E);
+            }
+            i = j;
+        }
+        while (i < nc) {
+            int j = i;
+            while (j < nc && bg[j].n == bg[i].n) ++j;
+            const int64_t nn = bg[i].n, M = nn / 2;
+            TwTable tb;
+            std::vector<int> rad;
+            if ((rc = big_group_setup(ctx, nn, AGN_FP64, &tb, &rad))) return rc;
+            hipLaunchKernelGGL(k_big_init, dim3((unsigned)(j - i)), dim3(64), 0, st, d_bg + i);
+            int sel = 0;
+            int64_t Ns = 1;
+            for (size_t p = 0; p < rad.size(); ++p) {
+                FftPass P;
+                memset(&P, 0, sizeof(P));
+                P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], AGN_FP64); P.nthreads = rad[p] * P.cols / 16;
+                P.Ns = Ns;
+                P.in_mode = p == 0 ? 1 : 0; P.out_mode = 0; P.inverse = 0;
+                P.x_sel = 0; P.with_delta = 0;
+                P.src_sel = 1 - sel; P.dst_sel = sel; P.sub = make_plan(rad[p]);
+                launch_fft_pass<double>(nullptr, d_bg + i, j - i, P, tb, st);
+                Ns *= rad[p];
+                sel = 1 - sel;
+            }
+            hipLaunchKernelGGL(k_big_fold_power, dim3((unsigned)((M / 2 + 1 + 255) / 256), (unsigned)(j - i)),
+                               dim3(256), 0, st, d_bg + i, M, 1 - sel, tb, d_pp + i);
+            i = j;
+        }
+    }
+    HIPCHK(hipGetLastError());
+    if (bins_out && maxbins > 0) {
+        ProfScope ps(ctx, "log_bins", st);
+        hipLaunchKernelGGL(k_log_bins, dim3((unsigned)maxbins, (unsigned)nc), dim3(256), 0, st, d_bd);
+        HIPCHK(hipGetLastError());
+    }
     return AGN_OK;
 }
 

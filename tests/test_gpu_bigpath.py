@@ -143,3 +143,23 @@ def test_lsst_length_2p26_fp32_properties(gpu_ctx):
     assert np.array_equal(np.sort(xg), s)
     dg = host(d)
     assert np.all(np.isfinite(dg)) and np.all(dg > 0)
+
+
+def test_paper_scale_2p27_fp64_properties(gpu_ctx):
+    """The paper's largest single curve (2^27 steps, Sec. 3.2.3) in FP64 on
+    one GPU: exact value multiset, valid ranks, finite convergence distances."""
+    n = 2**27
+    m = agn()
+    ep = m.erdf_params()
+    x0 = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    m.agn_erdf_draw(gpu_ctx, ep, n, 27, 0, x0)
+    p = m.psd_params(0.0, 1.0 / 3652.5, 1.0, 2.0)
+    ws = torch.empty(m.agn_workspace_size(n, 0), dtype=torch.uint8, device="cuda:0")
+    x = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    d = torch.empty(2, dtype=torch.float64, device="cuda:0")
+    done = torch.empty(1, dtype=torch.int32, device="cuda:0")
+    m.agn_lc_generate(gpu_ctx, p, x0, n, 7.0, 2, -1.0, 5, 0, 0, x, d, done, ws)
+    assert int(host(done)[0]) == 2
+    assert torch.equal(torch.sort(x).values, torch.sort(x0).values)
+    dg = host(d)
+    assert np.all(np.isfinite(dg)) and np.all(dg > 0)
