@@ -455,6 +455,7 @@ static void launch_lds(agn_ctx* ctx, const LcDesc* d, int count, int nt, size_t 
 template <typename T>
 static int launch_lds_E(agn_ctx* ctx, int E, const LcDesc* d, int count, int nt, size_t prep_lds,
                         size_t iter_lds, hipStream_t st) {
+    if (E >= 8 && nt % 32 != 0) return fail(AGN_EINVAL, "internal: %d-thread block for E=%d", nt, E);
     switch (E) {
         case 1: launch_lds<T, 1>(ctx, d, count, nt, prep_lds, iter_lds, st); break;
         case 2: launch_lds<T, 2>(ctx, d, count, nt, prep_lds, iter_lds, st); break;

@@ -11,7 +11,8 @@
 // writes in place: one LDS buffer of M values (plus padding) suffices.
 //
 // Twiddles W_N^t = exp(-2 pi i t / N) for the real length N = 2M come from a
-// two-level double-precision table in LDS (W_M^u = W_N^{2u}).
+// two-level double-precision table in LDS (W_M^u = W_N^{2u}); the R - 1
+// twiddles of one butterfly are double-precision powers of the first.
 #pragma once
 #include "common.hpp"
 
@@ -145,16 +146,35 @@ AGN_DEV void lds_pass(cplx<T>* buf, int M, int Ns, int tid, int nt, const TwLds&
     const int MR = M / R;
     const bool pow2 = (Ns & (Ns - 1)) == 0;
     const int tstep = 2 * (M / (Ns * R));
+    // When a stride is a multiple of the pad period P, cpad(x + r * S) =
+    // cpad(x) + r * (S + S / P): one base per butterfly, then fixed steps.
+    constexpr int PL = sizeof(T) == 4 ? 5 : 4;
+    const bool rd_al = (MR & ((1 << PL) - 1)) == 0, wr_al = (Ns & ((1 << PL) - 1)) == 0;
+    const int rd_st = MR + (MR >> PL), wr_st = Ns + (Ns >> PL);
 #pragma unroll
     for (int b = 0; b < BMAX; ++b) {
         const int j = tid + b * nt;
         if (j < MR) {
+            if (rd_al) {
+                const int base = cpad<T>(j);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[b][r] = buf[cpad<T>(j + r * MR)];
+                for (int r = 0; r < R; ++r) v[b][r] = buf[base + r * rd_st];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[b][r] = buf[cpad<T>(j + r * MR)];
+            }
             if (Ns > 1) {
                 const int jm = pow2 ? (j & (Ns - 1)) : (j % Ns);
+                // W^{t r} for r = 1..R-1 as powers of W^t, formed by double-precision
+                // products (at most R - 2 of them) and rounded once to T.
+                const int t1 = jm * tstep;
+                const cplx<double> w1 = cmul(tw.hi[t1 >> tw.bits], tw.lo[t1 & ((1 << tw.bits) - 1)]);
+                cplx<double> wr = w1;
 #pragma unroll
-                for (int r = 1; r < R; ++r) w[b][r] = twiddle<T, INV>(tw, jm * r * tstep);
+                for (int r = 1; r < R; ++r) {
+                    w[b][r] = cmk((T)wr.re, (T)(INV ? -wr.im : wr.im));
+                    wr = cmul(wr, w1);
+                }
             }
         }
     }
@@ -170,8 +190,14 @@ AGN_DEV void lds_pass(cplx<T>* buf, int M, int Ns, int tid, int nt, const TwLds&
             }
             dftR<T, R, INV>(v[b]);
             const int d = (j - jm) * R + jm;
+            if (wr_al) {
+                const int base = cpad<T>(d);
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[cpad<T>(d + r * Ns)] = v[b][r];
+                for (int r = 0; r < R; ++r) buf[base + r * wr_st] = v[b][r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[cpad<T>(d + r * Ns)] = v[b][r];
+            }
         }
     }
     __syncthreads();

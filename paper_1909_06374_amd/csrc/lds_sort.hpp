@@ -53,8 +53,9 @@ constexpr int SORT_LANES = 1 << (SORT_RB - 1);  // counter words per thread
 template <typename K>
 AGN_DEV int kpad(int e) { return e + (e >> (sizeof(K) == 4 ? 5 : 4)); }
 AGN_DEV int wpad(int w) { return w + (w >> 5); }
-// 16-bit element e of a padded array of 32-bit words.
-AGN_DEV int hpad(int e) { return 2 * wpad(e >> 1) + (e & 1); }
+// 16-bit element e of a padded array of 32-bit words:
+// 2 * wpad(e >> 1) + (e & 1) = e + 2 * (e >> 6).
+AGN_DEV int hpad(int e) { return e + ((e >> 6) << 1); }
 
 template <typename K>
 __host__ __device__ inline size_t sort_keys_bytes(int n) {
@@ -79,40 +80,54 @@ __host__ __device__ inline size_t sort_ibuf_bytes(int n) {
 //   scratch            LDS, >= 20 words, not aliased
 // On return ibuf[hpad(k)] holds the index carried by the k-th smallest key
 // (after a barrier).  key[] and idx2[] are left in an unspecified state.
-template <typename K, int IPT, bool SEP>
-AGN_DEV void block_radix_sort(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned char* work,
-                              uint16_t* ibuf, uint32_t* scratch) {
+//
+// Index arithmetic: when T is a multiple of 32, the counter word of digit
+// lane l for thread t, wpad(l T + t), equals l (T + T/32) + (t + t/32); the
+// thread's own scan words wpad(16 t + q), q < 16, are 16 t + t/2 + q; and
+// when IPT divides the pad period, the read-back addresses of a thread's
+// IPT keys and IPT/2 index words are a per-thread base plus i (or j).  The
+// addresses are the same as the padded formulas, with fewer instructions.
+template <typename K, int IPT, bool SEP, bool ALIGNED>
+AGN_DEV void block_radix_sort_impl(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned char* work,
+                                   uint16_t* ibuf, uint32_t* scratch) {
     static_assert(IPT % 2 == 0, "IPT must be even");
     const int T = blockDim.x;
     constexpr int NPASS = (int)((8 * sizeof(K) + SORT_RB - 1) / SORT_RB);
+    constexpr int KPER = sizeof(K) == 4 ? 32 : 16;  // key pad period
+    constexpr bool KFAST = (KPER % IPT) == 0;
+    constexpr bool IFAST = (32 % (IPT / 2)) == 0;
     uint32_t* cnt = (uint32_t*)work;
     K* kb = (K*)work;
     const uint32_t* ibuf32 = (const uint32_t*)ibuf;
+    const int Tp = T + (T >> 5);
 
 #pragma unroll 1
     for (int pass = 0; pass < NPASS; ++pass) {
         const int t = opaque((int)threadIdx.x);
+        const int tb = t + (t >> 5);
         const int shift = pass * SORT_RB;
 #pragma unroll
-        for (int l = 0; l < SORT_LANES; ++l) cnt[wpad(l * T + t)] = 0u;
+        for (int l = 0; l < SORT_LANES; ++l) cnt[ALIGNED ? l * Tp + tb : wpad(l * T + t)] = 0u;
         // pos[i]: bits 0..15 running position, bits 16..20 the digit.
         uint32_t pos[IPT];
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             const uint32_t d = (uint32_t)(key[i] >> shift) & (2 * SORT_LANES - 1);
-            const int a = wpad((int)(d & (SORT_LANES - 1)) * T + t);
-            const uint32_t sh = (d & SORT_LANES) ? 16u : 0u;
+            const int l = (int)(d & (SORT_LANES - 1));
+            const int a = ALIGNED ? l * Tp + tb : wpad(l * T + t);
+            const uint32_t sh = d & SORT_LANES;  // 0 or 16
             const uint32_t c = cnt[a];
             pos[i] = ((c >> sh) & 0xFFFFu) | (d << 16);
             cnt[a] = c + (1u << sh);
         }
         __syncthreads();
         {
+            const int sb = 16 * t + (t >> 1);  // wpad(16 t + q) - q
             uint32_t w[SORT_LANES];
             uint32_t s = 0;
 #pragma unroll
             for (int q = 0; q < SORT_LANES; ++q) {
-                w[q] = cnt[wpad(t * SORT_LANES + q)];
+                w[q] = cnt[sb + q];
                 s += w[q];
             }
             uint32_t total;
@@ -120,7 +135,7 @@ AGN_DEV void block_radix_sort(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned
             run += (total & 0xFFFFu) << 16;
 #pragma unroll
             for (int q = 0; q < SORT_LANES; ++q) {
-                cnt[wpad(t * SORT_LANES + q)] = run;
+                cnt[sb + q] = run;
                 run += w[q];
             }
         }
@@ -128,45 +143,71 @@ AGN_DEV void block_radix_sort(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             const uint32_t d = pos[i] >> 16;
-            const int a = wpad((int)(d & (SORT_LANES - 1)) * T + t);
-            const uint32_t sh = (d & SORT_LANES) ? 16u : 0u;
+            const int l = (int)(d & (SORT_LANES - 1));
+            const int a = ALIGNED ? l * Tp + tb : wpad(l * T + t);
+            const uint32_t sh = d & SORT_LANES;
             pos[i] = (pos[i] & 0xFFFFu) + ((cnt[a] >> sh) & 0xFFFFu);
         }
         __syncthreads();
         const bool last = (pass == NPASS - 1);
+        const int kbase = KFAST ? t * IPT + (t * IPT) / KPER : 0;
+        const int ibase = IFAST ? t * (IPT / 2) + (t * (IPT / 2)) / 32 : 0;
         if (SEP) {
+            if (!last) {
 #pragma unroll
-            for (int i = 0; i < IPT; ++i) {
-                if (!last) kb[kpad<K>(pos[i])] = key[i];
-                ibuf[hpad(pos[i])] = (uint16_t)((i & 1) ? (idx2[i / 2] >> 16) : (idx2[i / 2] & 0xFFFFu));
+                for (int i = 0; i < IPT; ++i) {
+                    kb[kpad<K>((int)pos[i])] = key[i];
+                    ibuf[hpad((int)pos[i])] = (uint16_t)((i & 1) ? (idx2[i / 2] >> 16) : idx2[i / 2]);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < IPT; ++i)
+                    ibuf[hpad((int)pos[i])] = (uint16_t)((i & 1) ? (idx2[i / 2] >> 16) : idx2[i / 2]);
             }
             __syncthreads();
             if (!last) {
 #pragma unroll
-                for (int i = 0; i < IPT; ++i) key[i] = kb[kpad<K>(t * IPT + i)];
+                for (int i = 0; i < IPT; ++i) key[i] = kb[KFAST ? kbase + i : kpad<K>(t * IPT + i)];
 #pragma unroll
-                for (int j = 0; j < IPT / 2; ++j) idx2[j] = ibuf32[wpad((t * IPT) / 2 + j)];
+                for (int j = 0; j < IPT / 2; ++j) idx2[j] = ibuf32[IFAST ? ibase + j : wpad((t * IPT) / 2 + j)];
                 __syncthreads();
             }
         } else {
             if (!last) {
 #pragma unroll
-                for (int i = 0; i < IPT; ++i) kb[kpad<K>(pos[i])] = key[i];
+                for (int i = 0; i < IPT; ++i) kb[kpad<K>((int)pos[i])] = key[i];
                 __syncthreads();
 #pragma unroll
-                for (int i = 0; i < IPT; ++i) key[i] = kb[kpad<K>(t * IPT + i)];
+                for (int i = 0; i < IPT; ++i) key[i] = kb[KFAST ? kbase + i : kpad<K>(t * IPT + i)];
                 __syncthreads();
             }
 #pragma unroll
             for (int i = 0; i < IPT; ++i)
-                ibuf[hpad(pos[i])] = (uint16_t)((i & 1) ? (idx2[i / 2] >> 16) : (idx2[i / 2] & 0xFFFFu));
+                ibuf[hpad((int)pos[i])] = (uint16_t)((i & 1) ? (idx2[i / 2] >> 16) : idx2[i / 2]);
             __syncthreads();
             if (!last) {
 #pragma unroll
-                for (int j = 0; j < IPT / 2; ++j) idx2[j] = ibuf32[wpad((t * IPT) / 2 + j)];
+                for (int j = 0; j < IPT / 2; ++j) idx2[j] = ibuf32[IFAST ? ibase + j : wpad((t * IPT) / 2 + j)];
                 __syncthreads();
             }
         }
+    }
+}
+
+// IPT 16 is used only with 1024-thread blocks (the host checks that the
+// block size is a multiple of 32 for it), so only the aligned form is built.
+template <typename K, int IPT, bool SEP>
+AGN_DEV void block_radix_sort(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned char* work,
+                              uint16_t* ibuf, uint32_t* scratch) {
+    if constexpr (IPT >= 16) {
+        block_radix_sort_impl<K, IPT, SEP, true>(key, idx2, work, ibuf, scratch);
+    } else if constexpr (sizeof(K) == 8) {
+        // 64-bit keys (one-time draw sort, FP64 path): one general form keeps
+        // register pressure low
+        block_radix_sort_impl<K, IPT, SEP, false>(key, idx2, work, ibuf, scratch);
+    } else {
+        if ((blockDim.x & 31) == 0) block_radix_sort_impl<K, IPT, SEP, true>(key, idx2, work, ibuf, scratch);
+        else block_radix_sort_impl<K, IPT, SEP, false>(key, idx2, work, ibuf, scratch);
     }
 }
 
