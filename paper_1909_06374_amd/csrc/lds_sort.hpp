@@ -116,9 +116,11 @@ AGN_DEV void block_radix_sort_impl(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], uns
             const int l = (int)(d & (SORT_LANES - 1));
             const int a = ALIGNED ? l * Tp + tb : wpad(l * T + t);
             const uint32_t sh = d & SORT_LANES;  // 0 or 16
-            const uint32_t c = cnt[a];
+            // the counter word is private to this thread: the returned old
+            // value is the count of earlier equal digits; atomics issue back
+            // to back instead of waiting for each read before the next write
+            const uint32_t c = atomicAdd(&cnt[a], 1u << sh);
             pos[i] = ((c >> sh) & 0xFFFFu) | (d << 16);
-            cnt[a] = c + (1u << sh);
         }
         __syncthreads();
         {
