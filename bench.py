@@ -526,6 +526,12 @@ def run_serving(args, agn, np, torch):
     el = t_ev0.elapsed_time(t_ev1) / 1000.0
     fp64 = {"requests": k, "req_per_s": k / el, "samples_per_s": sum(r.n for r in one) / el,
             "sample": f"first {k} requests of the 2000/s stream, FP64, one agn_lc_generate call each"}
+    # the same requests through the server (FP32 form, all queued at time zero)
+    same = [Request(**{**r.__dict__, "arrival": 0.0, "rid": r.rid}) for r in one]
+    st_same = srv.run(same)
+    span_same = max(r.done for r in same)
+    fp64["fp32_served_same_requests_req_per_s"] = st_same.completed / span_same
+    fp64["speedup_fp32_served_vs_fp64_one_at_a_time"] = (st_same.completed / span_same) / (k / el)
     return {
         "metric": METRIC, "value": cap_sps, "unit": "samples/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": 1000.0 / cap_rps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

@@ -18,6 +18,21 @@
 
 namespace agn {
 
+// Inclusive scan of one uint32 per lane across a 64-lane wave with DPP
+// moves: row shifts by 1, 2, 4, 8 (lanes shifted in from outside the row add
+// zero), then the last lane of rows 0 and 2 is added to rows 1 and 3 and the
+// last lane of row 1 to rows 2 and 3.  Lanes only read lower lanes, so a
+// partial wave scans its active lanes correctly.
+AGN_DEV uint32_t wave_inclusive_scan(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);   // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);   // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);   // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);   // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return x;
+}
+
 // Exclusive scan of one uint32 per thread over the block (fixed order).
 // One barrier: every wave publishes its total, then every thread adds the
 // totals of the waves before its own.  The caller must not overwrite
@@ -26,12 +41,7 @@ AGN_DEV uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= nw wor
                                       uint32_t* total) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nw = (nt + 63) >> 6;
-    uint32_t inc = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t o = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += o;
-    }
+    const uint32_t inc = wave_inclusive_scan(v);
     const int last = (nt - (wave << 6) < 64) ? (nt - (wave << 6) - 1) : 63;
     if (lane == last) scratch[wave] = inc;
     __syncthreads();
