@@ -11,6 +11,7 @@ All arrays are numpy float64 / uint32 on the host.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -34,6 +35,21 @@ class ErdfParams(C.Structure):
 
 def erdf_params(u_min=-4.0, u_max=0.0, u_br=-1.5, d1=0.4, d2=2.5):
     return ErdfParams(float(u_min), float(u_max), float(u_br), float(d1), float(d2))
+
+
+class PdfParams(C.Structure):
+    """General PDF of Sec. 2.1 step (ii): kind 0 sharp broken power law, 1 Eq. 1,
+    2 Eq. 2 (log-normal); measure 0 dN/dlog10(lambda), 1 dN/dlambda."""
+    _fields_ = [("kind", C.c_int32), ("measure", C.c_int32), ("u_min", C.c_double),
+                ("u_max", C.c_double), ("u_star", C.c_double), ("d1", C.c_double),
+                ("d2", C.c_double), ("sigma", C.c_double)]
+
+
+def pdf_params(kind, measure=0, u_min=-3.75, u_max=0.5, u_star=math.log10(0.11), d1=0.47, d2=2.53,
+               sigma=0.64):
+    """Defaults: the Eq. 1 parameters of the reference simulation (Table 2)."""
+    return PdfParams(int(kind), int(measure), float(u_min), float(u_max), float(u_star), float(d1),
+                     float(d2), float(sigma))
 
 
 def _load():
@@ -66,6 +82,10 @@ def _load():
     lib.agn_oracle_periodogram.argtypes = [pd, i64, pd]
     lib.agn_oracle_erdf_bpl.argtypes = [C.POINTER(ErdfParams), i64, u64, u32, pd]
     lib.agn_oracle_erdf_bpl.restype = C.c_int
+    lib.agn_oracle_pdf_draw.argtypes = [C.POINTER(PdfParams), i64, u64, u32, pd]
+    lib.agn_oracle_pdf_draw.restype = C.c_int
+    lib.agn_oracle_pdf_draw_at.argtypes = [C.POINTER(PdfParams), u64, u32, C.POINTER(C.c_int64), i64, pd]
+    lib.agn_oracle_pdf_draw_at.restype = C.c_int
     for name in ("psd_spectrum", "dft", "rfft", "irfft", "replace", "argsort",
                  "iterate", "generate", "periodogram"):
         getattr(lib, "agn_oracle_" + name).restype = C.c_int
@@ -196,6 +216,24 @@ def erdf_bpl(params: ErdfParams, n, seed, curve_id=0):
     out = np.full(n, np.nan, dtype=np.float64)
     _chk(_load().agn_oracle_erdf_bpl(C.byref(params), int(n), int(seed), int(curve_id), _pd(out)),
          "erdf_bpl")
+    return out
+
+
+def pdf_draw(params: PdfParams, n, seed, curve_id=0):
+    """Draws 0..n-1 of the general PDF (lambda values)."""
+    out = np.full(n, np.nan, dtype=np.float64)
+    _chk(_load().agn_oracle_pdf_draw(C.byref(params), int(n), int(seed), int(curve_id), _pd(out)),
+         "pdf_draw")
+    return out
+
+
+def pdf_draw_at(params: PdfParams, idx, seed, curve_id=0):
+    """Draws #idx[i] of the general PDF (lambda values)."""
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.full(len(idx), np.nan, dtype=np.float64)
+    _chk(_load().agn_oracle_pdf_draw_at(C.byref(params), int(seed), int(curve_id),
+                                        idx.ctypes.data_as(C.POINTER(C.c_int64)), len(idx), _pd(out)),
+         "pdf_draw_at")
     return out
 
 

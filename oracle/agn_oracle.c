@@ -412,6 +412,141 @@ int agn_oracle_erdf_bpl(const agn_oracle_erdf_params* p, int64_t n, uint64_t see
     return E_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* General PDF draw (Sec. 2.1 step ii; Eq. 1, Eq. 2).                         */
+/* ------------------------------------------------------------------------ */
+static const double LN10 = 2.302585092994045684;
+
+/* Shape of the density in u = log10(lambda), up to a constant. */
+static double pdf_shape_u(const agn_oracle_pdf_params* p, double u)
+{
+    const double x = u - p->u_star;
+    double f;
+    if (p->kind == 0) f = pow(10.0, -(x < 0.0 ? p->d1 : p->d2) * x);
+    else if (p->kind == 1) f = 1.0 / (pow(10.0, p->d1 * x) + pow(10.0, p->d2 * x));
+    else f = exp(-x * x / (2.0 * p->sigma * p->sigma));
+    if (p->measure == 1) f *= pow(10.0, x);  /* dN/du = dN/dlambda * lambda ln10 */
+    return f;
+}
+
+/* 20-point Gauss-Legendre integral of the shape over [a, b]. */
+static double pdf_gl(const agn_oracle_pdf_params* p, double a, double b)
+{
+    static const double xg[10] = {0.0765265211334973338, 0.2277858511416450781, 0.3737060887154195607,
+                                  0.5108670019508270980, 0.6360536807265150254, 0.7463319064601507926,
+                                  0.8391169718222188234, 0.9122344282513259059, 0.9639719272779137912,
+                                  0.9931285991850949248};
+    static const double wg[10] = {0.1527533871307258507, 0.1491729864726037467, 0.1420961093183820514,
+                                  0.1316886384491766269, 0.1181945319615184174, 0.1019301198172404351,
+                                  0.0832767415767047487, 0.0626720483341090636, 0.0406014298003869413,
+                                  0.0176140071391521183};
+    const double c = 0.5 * (a + b), h = 0.5 * (b - a);
+    double s = 0.0;
+    for (int i = 0; i < 10; ++i) s += wg[i] * (pdf_shape_u(p, c - h * xg[i]) + pdf_shape_u(p, c + h * xg[i]));
+    return s * h;
+}
+
+/* Standard normal CDF and its complement. */
+static double phi_lo(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
+
+/* Inverse CDF of one uniform for kinds 0 and 2 (closed form / bisection on erfc). */
+static double pdf_invert_analytic(const agn_oracle_pdf_params* p, double U)
+{
+    if (p->kind == 0) {
+        /* closed form: the density in u is 10^(-e1 (u - u*)) below and 10^(-e2 (u - u*)) above */
+        const double e1 = p->d1 - (p->measure == 1 ? 1.0 : 0.0), e2 = p->d2 - (p->measure == 1 ? 1.0 : 0.0);
+        const double a = p->u_star - p->u_min, b = p->u_max - p->u_star;
+        const double m1 = (e1 == 0.0) ? a : (pow(10.0, e1 * a) - 1.0) / (e1 * LN10);
+        const double m2 = (e2 == 0.0) ? b : (1.0 - pow(10.0, -e2 * b)) / (e2 * LN10);
+        const double t = U * (m1 + m2);
+        double u;
+        if (t < m1) u = (e1 == 0.0) ? p->u_min + t : p->u_star - log10(pow(10.0, e1 * a) - t * e1 * LN10) / e1;
+        else u = (e2 == 0.0) ? p->u_star + (t - m1) : p->u_star - log10(1.0 - (t - m1) * e2 * LN10) / e2;
+        if (u < p->u_min) u = p->u_min;
+        if (u > p->u_max) u = p->u_max;
+        return u;
+    }
+    /* kind 2: normal in u truncated to [u_min, u_max]; for the linear measure the
+     * extra factor 10^(u - u*) completes the square to a mean of u* + sigma^2 ln10 */
+    const double mu = p->u_star + (p->measure == 1 ? p->sigma * p->sigma * LN10 : 0.0);
+    /* a support above the mean is reflected about it, so that the normal CDF is
+     * always taken in its lower half, where it keeps full relative precision;
+     * the reflected draw uses the exact complement 1 - U */
+    const int mirror = 0.5 * (p->u_min + p->u_max) > mu;
+    const double a = mirror ? 2.0 * mu - p->u_max : p->u_min;
+    const double b = mirror ? 2.0 * mu - p->u_min : p->u_max;
+    const double fa = phi_lo((a - mu) / p->sigma), fb = phi_lo((b - mu) / p->sigma);
+    const double target = fa + (mirror ? 1.0 - U : U) * (fb - fa);
+    double lo = a, hi = b;
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * (1.0 + fabs(lo)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (phi_lo((mid - mu) / p->sigma) < target) lo = mid;
+        else hi = mid;
+    }
+    const double v = 0.5 * (lo + hi);
+    return mirror ? 2.0 * mu - v : v;
+}
+
+int agn_oracle_pdf_draw_at(const agn_oracle_pdf_params* p, uint64_t seed, uint32_t curve_id,
+                           const int64_t* idx, int64_t m, double* out)
+{
+    if (!p || m < 0 || (m > 0 && (!idx || !out))) return E_INVAL;
+    if (!(p->u_min < p->u_max) || !isfinite(p->u_min) || !isfinite(p->u_max) || !isfinite(p->u_star))
+        return E_INVAL;
+    if (p->kind < 0 || p->kind > 2 || (p->measure != 0 && p->measure != 1)) return E_INVAL;
+    if (p->kind == 0 && !(p->u_min < p->u_star && p->u_star < p->u_max)) return E_INVAL;
+    if (p->kind != 2 && (!isfinite(p->d1) || !isfinite(p->d2))) return E_INVAL;
+    if (p->kind == 2 && !(p->sigma > 0.0 && isfinite(p->sigma))) return E_INVAL;
+    for (int64_t i = 0; i < m; ++i)
+        if (idx[i] < 0) return E_INVAL;
+    if (p->kind != 1) {
+        for (int64_t i = 0; i < m; ++i)
+            out[i] = pow(10.0, pdf_invert_analytic(p, agn_oracle_uniform(seed, 1, curve_id, (uint64_t)idx[i])));
+        return E_OK;
+    }
+    /* kind 1 (Eq. 1): CDF from Gauss-Legendre panels, summed in extended precision;
+     * the draw is found by search over the panels, then bisection inside one */
+    enum { NP = 2048 };
+    long double* cum = (long double*)malloc(sizeof(long double) * (NP + 1));
+    if (!cum) return E_NOMEM;
+    const double w = (p->u_max - p->u_min) / NP;
+    cum[0] = 0.0L;
+    for (int i = 0; i < NP; ++i) cum[i + 1] = cum[i] + pdf_gl(p, p->u_min + i * w, p->u_min + (i + 1) * w);
+    const long double total = cum[NP];
+    for (int64_t i = 0; i < m; ++i) {
+        const long double target = (long double)agn_oracle_uniform(seed, 1, curve_id, (uint64_t)idx[i]) * total;
+        int lo_i = 0, hi_i = NP;  /* cum[lo_i] <= target < cum[hi_i] */
+        while (hi_i - lo_i > 1) {
+            const int mid = (lo_i + hi_i) / 2;
+            if (cum[mid] <= target) lo_i = mid;
+            else hi_i = mid;
+        }
+        const double a = p->u_min + lo_i * w;
+        const double rest = (double)(target - cum[lo_i]);
+        double lo = a, hi = (lo_i == NP - 1) ? p->u_max : a + w;
+        for (int it = 0; it < 200 && hi - lo > 1e-15 * (1.0 + fabs(lo)); ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (pdf_gl(p, a, mid) < rest) lo = mid;
+            else hi = mid;
+        }
+        out[i] = pow(10.0, 0.5 * (lo + hi));
+    }
+    free(cum);
+    return E_OK;
+}
+
+int agn_oracle_pdf_draw(const agn_oracle_pdf_params* p, int64_t n, uint64_t seed, uint32_t curve_id,
+                        double* out)
+{
+    if (n < 0 || (n > 0 && !out)) return E_INVAL;
+    int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!idx) return E_NOMEM;
+    for (int64_t k = 0; k < n; ++k) idx[k] = k;
+    const int rc = agn_oracle_pdf_draw_at(p, seed, curve_id, idx, n, out);
+    free(idx);
+    return rc;
+}
+
 /* Periodogram, Eq. A2 (Appendix A): P(f_j) = 2 / N^2 |DFT(f_j)|^2, j = 0..N/2. */
 int agn_oracle_periodogram(const double* x, int64_t n, double* P)
 {

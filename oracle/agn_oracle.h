@@ -88,6 +88,32 @@ typedef struct {
 int agn_oracle_erdf_bpl(const agn_oracle_erdf_params* p, int64_t n, uint64_t seed,
                         uint32_t curve_id, double* out);
 
+/* General PDF draw (Sec. 2.1 step ii), u = log10(lambda) in [u_min, u_max]:
+ *   kind 0: sharp broken power law, shape 10^(-d1 (u - u_star)) below u_star and
+ *           10^(-d2 (u - u_star)) above;
+ *   kind 1: Eq. 1, shape 1 / ((lambda/lambda*)^d1 + (lambda/lambda*)^d2);
+ *   kind 2: Eq. 2, shape exp(-(u - u_star)^2 / (2 sigma^2)).
+ * measure 0: the shape is dN/dlog10(lambda); measure 1: the shape is dN/dlambda
+ * (the density in u then carries an extra factor lambda).  Draw k is the exact
+ * inverse CDF (closed form, or bisection on the CDF computed by quadrature) of
+ * uniform #k of Philox stream 1; out[k] = 10^u. */
+typedef struct {
+    int32_t kind;
+    int32_t measure;
+    double u_min;
+    double u_max;
+    double u_star;
+    double d1;
+    double d2;
+    double sigma;
+} agn_oracle_pdf_params;
+
+int agn_oracle_pdf_draw(const agn_oracle_pdf_params* p, int64_t n, uint64_t seed, uint32_t curve_id,
+                        double* out);
+/* The same draws at the m indices idx[0..m-1] only (out[i] is draw #idx[i]). */
+int agn_oracle_pdf_draw_at(const agn_oracle_pdf_params* p, uint64_t seed, uint32_t curve_id,
+                           const int64_t* idx, int64_t m, double* out);
+
 /* Periodogram, Eq. A2: P[j] = 2/n^2 |DFT_j|^2 for j = 0..n/2. */
 int agn_oracle_periodogram(const double* x, int64_t n, double* P);
 

@@ -11,6 +11,7 @@ import pytest
 from scipy import stats
 
 import oracle
+from pdf_reference import quad_cdf as _quad_cdf
 
 
 def numpy_philox_block(key, block):
@@ -143,3 +144,86 @@ def test_erdf_sampler_closed_form_cdf():
     lam_rate = np.log(10.0)
     cdf = lambda x: (1 - np.exp(-lam_rate * (x + 3.0))) / (1 - np.exp(-lam_rate * 3.0))
     assert stats.kstest(u2, cdf).pvalue > 1e-3
+
+
+PDF_CASES = [
+    # Table 2: Eq. 1 with lambda* = 0.11, slopes 0.47 / 2.53, log lambda in [-3.75, 0.5]
+    dict(kind=1, measure=0), dict(kind=1, measure=1),
+    # Eq. 2 with log lambda* = -3.25, sigma = 0.64 on a wide support
+    dict(kind=2, measure=0, u_min=-6.0, u_max=1.0, u_star=-3.25),
+    dict(kind=2, measure=1, u_min=-6.0, u_max=1.0, u_star=-3.25),
+    # support entirely in the upper tail of the normal
+    dict(kind=2, measure=0, u_min=-1.5, u_max=0.5, u_star=-3.25),
+    # sharp broken power law, both measures, and a slope of exactly 1 (flat in u for dN/dlambda)
+    dict(kind=0, measure=0), dict(kind=0, measure=1), dict(kind=0, measure=1, d1=1.0),
+]
+
+
+@pytest.mark.parametrize("case", PDF_CASES)
+def test_pdf_draw_inverts_the_cdf(case):
+    """Draw k is the inverse CDF of uniform #k of stream 1: the CDF from
+    quadrature of the restated density, at the drawn value, returns that uniform."""
+    p = oracle.pdf_params(**case)
+    lam = oracle.pdf_draw(p, 40, seed=5, curve_id=2)
+    u = np.log10(lam)
+    assert np.all((u >= p.u_min) & (u <= p.u_max))
+    F = _quad_cdf(p)
+    for k in range(40):
+        assert abs(F(u[k]) - oracle.uniform(5, 1, 2, k)) < 1e-12, (case, k)
+
+
+def test_pdf_lognormal_matches_scipy_truncnorm():
+    """Eq. 2 is a normal in log10(lambda); read as dN/dlambda its mean moves up
+    by sigma^2 ln 10.  KS against scipy's truncated normal."""
+    for measure, mean in [(0, -3.25), (1, -3.25 + 0.64 ** 2 * math.log(10.0))]:
+        p = oracle.pdf_params(2, measure, u_min=-6.0, u_max=1.0, u_star=-3.25, sigma=0.64)
+        u = np.log10(oracle.pdf_draw(p, 20000, seed=3, curve_id=measure))
+        a, b = (-6.0 - mean) / 0.64, (1.0 - mean) / 0.64
+        assert stats.kstest(u, stats.truncnorm(a, b, loc=mean, scale=0.64).cdf).pvalue > 1e-3
+        assert abs(u.mean() - stats.truncnorm(a, b, loc=mean, scale=0.64).mean()) < 5 * u.std() / math.sqrt(len(u))
+
+
+def test_pdf_eq1_special_cases_in_closed_form():
+    """Eq. 1 with equal slopes d is half a single power law: u has the
+    truncated exponential law, inverted in closed form per uniform.  With
+    d = 1 and the linear measure the density in u is flat."""
+    d, lo, hi = 1.7, -3.0, 0.5
+    p = oracle.pdf_params(1, 0, u_min=lo, u_max=hi, u_star=-1.0, d1=d, d2=d)
+    u = np.log10(oracle.pdf_draw(p, 300, seed=8, curve_id=1))
+    U = np.array([oracle.uniform(8, 1, 1, k) for k in range(300)])
+    expect = lo - np.log10(1.0 - U * (1.0 - 10.0 ** (-d * (hi - lo)))) / d
+    assert np.max(np.abs(u - expect)) < 1e-12
+    q = oracle.pdf_params(1, 1, u_min=lo, u_max=hi, u_star=-1.0, d1=1.0, d2=1.0)
+    u = np.log10(oracle.pdf_draw(q, 300, seed=8, curve_id=1))
+    assert np.max(np.abs(u - (lo + U * (hi - lo)))) < 1e-12
+
+
+def test_pdf_sharp_kind_equals_the_erdf_sampler_and_draw_at():
+    """Kind 0 in dN/dlog10(lambda) is the sharp broken power law of erdf_bpl;
+    draws at chosen indices equal the same draws of the full sequence."""
+    p = oracle.pdf_params(0, 0, u_min=-4.0, u_max=0.0, u_star=-1.5, d1=0.4, d2=2.5)
+    a = oracle.pdf_draw(p, 500, seed=9, curve_id=4)
+    b = oracle.erdf_bpl(oracle.erdf_params(), 500, seed=9, curve_id=4)
+    assert np.max(np.abs(np.log10(a) - np.log10(b))) < 1e-13
+    for case in [dict(kind=1, measure=1), dict(kind=2, measure=0, u_star=-2.0)]:
+        q = oracle.pdf_params(**case)
+        full = oracle.pdf_draw(q, 400, seed=2, curve_id=7)
+        idx = np.array([399, 0, 17, 17, 250])
+        assert np.array_equal(oracle.pdf_draw_at(q, idx, seed=2, curve_id=7), full[idx])
+
+
+def test_pdf_eq1_table2_mass_split():
+    """Table 2's Eq. 1: the fraction of draws below the cut log lambda = -1.2
+    of Table 2 matches the quadrature mass (binomial bound)."""
+    p = oracle.pdf_params(1, 0)
+    u = np.log10(oracle.pdf_draw(p, 20000, seed=1, curve_id=0))
+    m = _quad_cdf(p)(-1.2)
+    assert abs(np.mean(u < -1.2) - m) < 5 * math.sqrt(m * (1 - m) / len(u))
+
+
+def test_pdf_rejects_bad_parameters():
+    bad = [dict(kind=3), dict(kind=0, measure=2), dict(kind=1, u_min=1.0, u_max=0.0),
+           dict(kind=2, sigma=0.0), dict(kind=0, u_star=1.0), dict(kind=1, d1=float("nan"))]
+    for case in bad:
+        with pytest.raises(oracle.OracleError):
+            oracle.pdf_draw(oracle.pdf_params(**case), 4, seed=0)
