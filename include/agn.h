@@ -241,6 +241,42 @@ typedef struct {
 int agn_erdf_draw(agn_ctx* ctx, const agn_erdf_params* p, int64_t n, uint64_t seed,
                   uint32_t curve_id, double* out, void* stream);
 
+/* General PDF of the draw (Sec. 2.1 step (ii), shapes of Sec. 2.1.1), in
+ * u = log10(lambda) on [u_min, u_max], x = u - u_star:
+ *   AGN_PDF_SHARP_BPL  10^(-d1 x) for x < 0, 10^(-d2 x) for x >= 0 (needs
+ *                      u_min < u_star < u_max);
+ *   AGN_PDF_EQ1        Eq. 1: 1 / (10^(d1 x) + 10^(d2 x));
+ *   AGN_PDF_LOGNORMAL  Eq. 2: exp(-x^2 / (2 sigma^2)) (needs sigma > 0).
+ * measure AGN_PDF_PER_LOG reads the shape as dN/dlog10(lambda); measure
+ * AGN_PDF_PER_LINEAR reads it as dN/dlambda (the paper samples in linear
+ * lambda), so that the density in u carries an extra factor 10^x.  Slopes are
+ * limited so that the shape spans under 10^260 over the support. */
+enum { AGN_PDF_SHARP_BPL = 0, AGN_PDF_EQ1 = 1, AGN_PDF_LOGNORMAL = 2 };
+enum { AGN_PDF_PER_LOG = 0, AGN_PDF_PER_LINEAR = 1 };
+typedef struct {
+    int32_t kind;
+    int32_t measure;
+    double u_min;
+    double u_max;
+    double u_star;
+    double d1;      /* slopes (kinds 0 and 1) */
+    double d2;
+    double sigma;   /* dex (kind 2) */
+} agn_pdf_params;
+
+/*
+ * agn_pdf_draw -- n i.i.d. draws lambda = 10^u of the PDF above, draw k the
+ * inverse CDF of uniform #k of Philox stream 1 (key (seed, 1 << 32 |
+ * curve_id); same stream as agn_erdf_draw, which equals kind 0, measure 0).
+ * Kind 0 inverts in closed form, kind 2 with erfcinv, kind 1 on a CDF table
+ * that each block builds in LDS followed by Newton steps on the exact integral.
+ *   p    host parameters; out: device, n doubles, in draw order.
+ * Errors: AGN_EINVAL for NULL pointers, n < 0 or parameters outside the ranges
+ * above (nothing is launched).  Stream-ordered; no allocation.
+ */
+int agn_pdf_draw(agn_ctx* ctx, const agn_pdf_params* p, int64_t n, uint64_t seed, uint32_t curve_id,
+                 double* out, void* stream);
+
 /*
  * Observables after the path (App. A).
  *

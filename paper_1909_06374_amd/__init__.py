@@ -55,6 +55,26 @@ def erdf_params(u_min=-4.0, u_max=0.0, u_br=-1.5, d1=0.4, d2=2.5):
     return agn_erdf_params(float(u_min), float(u_max), float(u_br), float(d1), float(d2))
 
 
+AGN_PDF_SHARP_BPL, AGN_PDF_EQ1, AGN_PDF_LOGNORMAL = 0, 1, 2
+AGN_PDF_PER_LOG, AGN_PDF_PER_LINEAR = 0, 1
+
+
+class agn_pdf_params(C.Structure):
+    """General PDF in u = log10(lambda): kind (sharp BPL / Eq. 1 / Eq. 2), measure
+    (dN/dlog10 lambda or dN/dlambda), u_min, u_max, u_star, d1, d2, sigma."""
+    _fields_ = [("kind", C.c_int32), ("measure", C.c_int32), ("u_min", C.c_double),
+                ("u_max", C.c_double), ("u_star", C.c_double), ("d1", C.c_double),
+                ("d2", C.c_double), ("sigma", C.c_double)]
+
+
+def pdf_params(kind, measure=AGN_PDF_PER_LOG, u_min=-3.75, u_max=0.5, u_star=-0.958607314841775, d1=0.47,
+               d2=2.53, sigma=0.64):
+    """Defaults: the Eq. 1 parameters of the reference simulation (Table 2:
+    lambda* = 0.11, slopes 0.47 / 2.53, log lambda in [-3.75, 0.5])."""
+    return agn_pdf_params(int(kind), int(measure), float(u_min), float(u_max), float(u_star), float(d1),
+                          float(d2), float(sigma))
+
+
 def _declare(lib):
     i32, i64, u32, u64, d = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
     vp, sz = C.c_void_p, C.c_size_t
@@ -75,6 +95,7 @@ def _declare(lib):
                                           vp, vp, vp, vp, sz, vp]
     lib.agn_test_philox.argtypes = [u64, u64, u64, i64, vp, vp]
     lib.agn_erdf_draw.argtypes = [vp, C.POINTER(agn_erdf_params), i64, u64, u32, vp, vp]
+    lib.agn_pdf_draw.argtypes = [vp, C.POINTER(agn_pdf_params), i64, u64, u32, vp, vp]
     lib.agn_batch_plan_create.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_int, vp, vp, vp,
                                           C.c_int, C.c_int, vp, sz, vp, C.POINTER(vp)]
     lib.agn_batch_plan_launch.argtypes = [vp, vp]
@@ -90,7 +111,7 @@ def _declare(lib):
     for f in ("agn_ctx_create", "agn_ctx_destroy", "agn_supported_n", "agn_spectrum_workspace_size",
               "agn_workspace_size", "agn_batch_workspace_size", "agn_psd_spectrum",
               "agn_lc_iterate", "agn_lc_generate", "agn_lc_generate_batch", "agn_test_philox",
-              "agn_ctx_set_profiling", "agn_ctx_kernel_time", "agn_erdf_draw", "agn_batch_plan_create",
+              "agn_ctx_set_profiling", "agn_ctx_kernel_time", "agn_erdf_draw", "agn_pdf_draw", "agn_batch_plan_create",
               "agn_batch_plan_launch", "agn_batch_plan_info", "agn_batch_plan_destroy", "agn_log_bin_count",
               "agn_periodogram_workspace_size", "agn_periodogram_batch"):
         getattr(lib, f).restype = C.c_int
@@ -324,6 +345,11 @@ def agn_periodogram_batch(ctx: Context, n, offset, x, p_offset, P_out, dex=0.0, 
 def agn_erdf_draw(ctx: Context, params, n, seed, curve_id, out, stream=None):
     _check(lib().agn_erdf_draw(ctx.handle, C.byref(params), int(n), int(seed), int(curve_id), _ptr(out),
                                _stream(stream, ctx.device)))
+
+
+def agn_pdf_draw(ctx: Context, params, n, seed, curve_id, out, stream=None):
+    _check(lib().agn_pdf_draw(ctx.handle, C.byref(params), int(n), int(seed), int(curve_id), _ptr(out),
+                              _stream(stream, ctx.device)))
 
 
 def agn_test_philox(key0, key1, ctr0, n_blocks, out, stream=None, device=0):

@@ -1505,6 +1505,24 @@ extern "C" int agn_periodogram_batch(agn_ctx* ctx, int32_t n_curves, const int64
     return AGN_OK;
 }
 
+static int launch_pdf_closed(agn_ctx* ctx, PdfClosed& P, void* stream) {
+    HIPCHK(hipSetDevice(ctx->device));
+    {
+        ProfScope ps(ctx, "erdf_draw", (hipStream_t)stream);
+        hipLaunchKernelGGL(k_pdf_closed, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, P);
+    }
+    HIPCHK(hipGetLastError());
+    return AGN_OK;
+}
+
+static void sharp_bpl_masses(PdfClosed& P, double u_min, double u_max, double u_star, double e1, double e2) {
+    const double ln10 = std::log(10.0);
+    P.kind = 0; P.u_min = u_min; P.u_max = u_max; P.u_star = u_star; P.e1 = e1; P.e2 = e2;
+    P.a1 = std::pow(10.0, e1 * (u_star - u_min));
+    P.m1 = (e1 == 0.0) ? u_star - u_min : (P.a1 - 1.0) / (e1 * ln10);
+    P.m2 = (e2 == 0.0) ? u_max - u_star : (1.0 - std::pow(10.0, -e2 * (u_max - u_star))) / (e2 * ln10);
+}
+
 extern "C" int agn_erdf_draw(agn_ctx* ctx, const agn_erdf_params* p, int64_t n, uint64_t seed,
                              uint32_t curve_id, double* out, void* stream) {
     if (!ctx || !p || (n > 0 && !out)) return fail(AGN_EINVAL, "NULL argument");
@@ -1513,17 +1531,67 @@ extern "C" int agn_erdf_draw(agn_ctx* ctx, const agn_erdf_params* p, int64_t n, 
         !std::isfinite(p->u_min) || !std::isfinite(p->u_max) || !std::isfinite(p->d1) || !std::isfinite(p->d2))
         return fail(AGN_EINVAL, "invalid PDF parameters");
     if (n == 0) return AGN_OK;
-    HIPCHK(hipSetDevice(ctx->device));
-    const double ln10 = std::log(10.0);
-    ErdfDraw P;
-    P.u_min = p->u_min; P.u_max = p->u_max; P.u_br = p->u_br; P.d1 = p->d1; P.d2 = p->d2;
-    P.a1 = std::pow(10.0, p->d1 * (p->u_br - p->u_min));
-    P.m1 = (P.a1 - 1.0) / (p->d1 * ln10);
-    P.m2 = (1.0 - std::pow(10.0, -p->d2 * (p->u_max - p->u_br))) / (p->d2 * ln10);
+    PdfClosed P{};
+    sharp_bpl_masses(P, p->u_min, p->u_max, p->u_br, p->d1, p->d2);
     P.n = n; P.seed = seed; P.curve_id = curve_id; P.out = out;
+    return launch_pdf_closed(ctx, P, stream);
+}
+
+extern "C" int agn_pdf_draw(agn_ctx* ctx, const agn_pdf_params* p, int64_t n, uint64_t seed, uint32_t curve_id,
+                            double* out, void* stream) {
+    if (!ctx || !p || (n > 0 && !out)) return fail(AGN_EINVAL, "NULL argument");
+    if (n < 0) return fail(AGN_EINVAL, "n < 0");
+    if (p->kind < AGN_PDF_SHARP_BPL || p->kind > AGN_PDF_LOGNORMAL) return fail(AGN_EINVAL, "unknown PDF kind");
+    if (p->measure != AGN_PDF_PER_LOG && p->measure != AGN_PDF_PER_LINEAR) return fail(AGN_EINVAL, "unknown measure");
+    if (!std::isfinite(p->u_min) || !std::isfinite(p->u_max) || !std::isfinite(p->u_star) || !(p->u_min < p->u_max))
+        return fail(AGN_EINVAL, "need finite u_min < u_max and u_star");
+    const double ln10 = std::log(10.0);
+    const double shift = (p->measure == AGN_PDF_PER_LINEAR) ? 1.0 : 0.0;
+    if (p->kind == AGN_PDF_SHARP_BPL || p->kind == AGN_PDF_EQ1) {
+        if (!std::isfinite(p->d1) || !std::isfinite(p->d2)) return fail(AGN_EINVAL, "non-finite slopes");
+        // exp(c x) over the support must stay finite and normal
+        const double xm = std::fmax(std::fabs(p->u_min - p->u_star), std::fabs(p->u_max - p->u_star));
+        if (std::fmax(std::fabs(p->d1 - shift), std::fabs(p->d2 - shift)) * ln10 * xm > 600.0)
+            return fail(AGN_EINVAL, "PDF dynamic range over the support exceeds double precision");
+    }
+    if (p->kind == AGN_PDF_SHARP_BPL && !(p->u_min < p->u_star && p->u_star < p->u_max))
+        return fail(AGN_EINVAL, "sharp broken power law needs u_min < u_star < u_max");
+    if (p->kind == AGN_PDF_LOGNORMAL && !(p->sigma > 0.0 && std::isfinite(p->sigma)))
+        return fail(AGN_EINVAL, "log-normal needs sigma > 0");
+    if (n == 0) return AGN_OK;
+    if (p->kind == AGN_PDF_SHARP_BPL) {
+        PdfClosed P{};
+        sharp_bpl_masses(P, p->u_min, p->u_max, p->u_star, p->d1 - shift, p->d2 - shift);
+        P.n = n; P.seed = seed; P.curve_id = curve_id; P.out = out;
+        return launch_pdf_closed(ctx, P, stream);
+    }
+    if (p->kind == AGN_PDF_LOGNORMAL) {
+        PdfClosed P{};
+        P.kind = 2; P.u_min = p->u_min; P.u_max = p->u_max;
+        P.mu = p->u_star + shift * p->sigma * p->sigma * ln10;
+        P.s = p->sigma * std::sqrt(2.0);
+        const double za = (p->u_min - P.mu) / P.s, zb = (p->u_max - P.mu) / P.s;
+        P.c_lo = 0.5 * std::erfc(-za);
+        P.c_hi = 0.5 * std::erfc(zb);
+        // the mass inside, from the tails that keep the difference exact
+        if (za >= 0.0) P.tot = 0.5 * (std::erfc(za) - std::erfc(zb));
+        else if (zb <= 0.0) P.tot = 0.5 * (std::erfc(-zb) - std::erfc(-za));
+        else P.tot = 1.0 - P.c_lo - P.c_hi;
+        if (!(P.tot > 0.0)) return fail(AGN_EINVAL, "log-normal support carries no mass in double precision");
+        P.n = n; P.seed = seed; P.curve_id = curve_id; P.out = out;
+        return launch_pdf_closed(ctx, P, stream);
+    }
+    PdfTable T{};
+    T.u_min = p->u_min; T.u_max = p->u_max; T.u_star = p->u_star;
+    T.c1 = (p->d1 - shift) * ln10; T.c2 = (p->d2 - shift) * ln10;
+    T.h = (p->u_max - p->u_min) / PDF_CELLS;
+    T.n = n; T.seed = seed; T.curve_id = curve_id; T.out = out;
+    const int64_t want = (n + PDF_THREADS * 64 - 1) / (PDF_THREADS * 64);
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, PDF_MAX_BLOCKS));
+    HIPCHK(hipSetDevice(ctx->device));
     {
         ProfScope ps(ctx, "erdf_draw", (hipStream_t)stream);
-        hipLaunchKernelGGL(k_erdf_draw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, P);
+        hipLaunchKernelGGL(k_pdf_eq1, dim3(nb), dim3(PDF_THREADS), 0, (hipStream_t)stream, T);
     }
     HIPCHK(hipGetLastError());
     return AGN_OK;

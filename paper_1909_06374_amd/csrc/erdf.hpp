@@ -1,35 +1,149 @@
 // erdf.hpp -- the PDF draw of Sec. 2.1 step (ii) on the device: N values of
-// L/L_Edd from a sharp broken power law in dN/dlog10(lambda) with the slope
-// convention of Eq. 1 (density 10^(-d1 (u - u_br)) below the break, 10^(-d2
-// (u - u_br)) above, u = log10 lambda in [u_min, u_max]), by its closed-form
-// inverse CDF applied to uniform #k of Philox stream 1.
+// L/L_Edd = 10^u, u = log10 lambda in [u_min, u_max], each the inverse CDF of
+// uniform #k of Philox stream 1.  Three shapes (Sec. 2.1.1):
+//   sharp broken power law (slopes as in Eq. 1, kink at u*): closed form;
+//   log-normal, Eq. 2: a normal in u truncated to the support, inverted with
+//     erfcinv on whichever tail keeps the argument small;
+//   smooth broken power law, Eq. 1: CDF tabulated per block in LDS
+//     (Gauss-Legendre per cell), search over the cells, then Newton inside
+//     the cell on the exact integral.
+// With the dN/dlambda measure the density in u gains a factor 10^(u - u*):
+// the power-law slopes drop by one and the log-normal mean moves up by
+// sigma^2 ln 10; the host folds that into the parameters below.
 #pragma once
 #include "common.hpp"
 #include "philox.hpp"
 
 namespace agn {
 
-struct ErdfDraw {
-    double u_min, u_max, u_br, d1, d2;
-    double m1, m2;         // masses below / above the break (host-computed)
-    double a1;             // 10^(d1 (u_br - u_min))
+// Closed forms (sharp broken power law, log-normal).
+struct PdfClosed {
+    int kind;              // 0 sharp broken power law, 2 log-normal
+    double u_min, u_max;
+    // kind 0: density 10^(-e1 (u - u*)) below u*, 10^(-e2 (u - u*)) above
+    double u_star, e1, e2;
+    double m1, m2;         // masses below / above u*
+    double a1;             // 10^(e1 (u* - u_min))
+    // kind 2: normal of mean mu and standard deviation s / sqrt(2) in u
+    double mu, s;
+    double c_lo, c_hi;     // normal mass below u_min, above u_max
+    double tot;            // normal mass inside the support
     int64_t n;
     uint64_t seed;
     uint32_t curve_id;
     double* out;
 };
 
-__global__ __launch_bounds__(256) void k_erdf_draw(ErdfDraw P) {
+__global__ __launch_bounds__(256) void k_pdf_closed(PdfClosed P) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= P.n) return;
     const double ln10 = 2.30258509299404568402;
     const double U = philox_uniform(P.seed, 1, P.curve_id, (uint64_t)k);
-    const double t = U * (P.m1 + P.m2);
     double u;
-    if (t < P.m1) u = P.u_br - log10(P.a1 - t * P.d1 * ln10) / P.d1;
-    else u = P.u_br - log10(1.0 - (t - P.m1) * P.d2 * ln10) / P.d2;
+    if (P.kind == 0) {
+        const double t = U * (P.m1 + P.m2);
+        if (t < P.m1) u = (P.e1 == 0.0) ? P.u_min + t : P.u_star - log10(P.a1 - t * P.e1 * ln10) / P.e1;
+        else u = (P.e2 == 0.0) ? P.u_star + (t - P.m1) : P.u_star - log10(1.0 - (t - P.m1) * P.e2 * ln10) / P.e2;
+    } else {
+        // mass below the draw, lo; above it, hi = c_hi + (1 - U) tot (1 - U is exact)
+        const double lo = P.c_lo + U * P.tot;
+        double z;
+        if (lo <= 0.5) z = -erfcinv(2.0 * lo);
+        else z = erfcinv(2.0 * (P.c_hi + (1.0 - U) * P.tot));
+        u = P.mu + P.s * z;
+    }
     u = fmin(fmax(u, P.u_min), P.u_max);
     P.out[k] = pow(10.0, u);
+}
+
+// Eq. 1: density 1 / (exp(c1 x) + exp(c2 x)) in x = u - u*, c = slope * ln 10.
+constexpr int PDF_CELLS = 1024;
+constexpr int PDF_THREADS = 256;
+constexpr int PDF_MAX_BLOCKS = 2048;
+
+struct PdfTable {
+    double u_min, u_max, u_star, c1, c2, h;  // h = (u_max - u_min) / PDF_CELLS
+    int64_t n;
+    uint64_t seed;
+    uint32_t curve_id;
+    double* out;
+};
+
+AGN_DEV double eq1_density(const PdfTable& P, double u) {
+    const double x = u - P.u_star;
+    return 1.0 / (exp(P.c1 * x) + exp(P.c2 * x));
+}
+
+// Six-point Gauss-Legendre integral of the density over [a, a + w].
+AGN_DEV double eq1_integral(const PdfTable& P, double a, double w) {
+    const double xn[3] = {0.2386191860831969086, 0.6612093864662645136, 0.9324695142031520279};
+    const double wn[3] = {0.4679139345726910473, 0.3607615730481386076, 0.1713244923791703450};
+    const double c = a + 0.5 * w, hw = 0.5 * w;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) s += wn[j] * (eq1_density(P, c - hw * xn[j]) + eq1_density(P, c + hw * xn[j]));
+    return s * hw;
+}
+
+__global__ __launch_bounds__(PDF_THREADS) void k_pdf_eq1(PdfTable P) {
+    constexpr int CPT = PDF_CELLS / PDF_THREADS;  // cells per thread
+    constexpr int W = PDF_THREADS / 64;
+    __shared__ double cum[PDF_CELLS + 1];         // CDF at the cell edges (unnormalised)
+    __shared__ double fe[PDF_CELLS + 1];          // density at the cell edges
+    __shared__ double wtot[W];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+    // 1. table: every block builds the same one, in the same order of operations
+    double pre[CPT];
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int i = tid * CPT + j;
+        const double a = P.u_min + i * P.h;
+        acc += eq1_integral(P, a, P.h);
+        pre[j] = acc;
+        fe[i] = eq1_density(P, a);
+    }
+    if (tid == 0) fe[PDF_CELLS] = eq1_density(P, P.u_max);
+    double inc = acc;  // wave inclusive scan of the per-thread sums
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const double o = __shfl_up(inc, s, 64);
+        if (lane >= s) inc += o;
+    }
+    if (lane == 63) wtot[wv] = inc;
+    __syncthreads();
+    double base = inc - acc;
+    for (int v = 0; v < wv; ++v) base += wtot[v];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) cum[tid * CPT + j + 1] = base + pre[j];
+    if (tid == 0) cum[0] = 0.0;
+    __syncthreads();
+    const double total = cum[PDF_CELLS];
+
+    // 2. draws, grid-stride
+    for (int64_t k = (int64_t)blockIdx.x * PDF_THREADS + tid; k < P.n; k += (int64_t)gridDim.x * PDF_THREADS) {
+        const double t = philox_uniform(P.seed, 1, P.curve_id, (uint64_t)k) * total;
+        int lo = 0, hi = PDF_CELLS;  // cum[lo] <= t < cum[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cum[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+        const double a = P.u_min + lo * P.h;
+        const double r = t - cum[lo];
+        // start: root of the integral of the linear interpolant of the density
+        const double f0 = fe[lo], g = (fe[lo + 1] - f0) / P.h;
+        double s = 2.0 * r / (f0 + sqrt(fmax(f0 * f0 + 2.0 * g * r, 0.0)));
+        s = fmin(fmax(s, 0.0), P.h);
+#pragma unroll
+        for (int it = 0; it < 3; ++it) {
+            s -= (eq1_integral(P, a, s) - r) / eq1_density(P, a + s);
+            s = fmin(fmax(s, 0.0), P.h);
+        }
+        const double u = fmin(fmax(a + s, P.u_min), P.u_max);
+        P.out[k] = pow(10.0, u);
+    }
 }
 
 }  // namespace agn
