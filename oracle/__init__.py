@@ -86,6 +86,9 @@ def _load():
     lib.agn_oracle_pdf_draw.restype = C.c_int
     lib.agn_oracle_pdf_draw_at.argtypes = [C.POINTER(PdfParams), u64, u32, C.POINTER(C.c_int64), i64, pd]
     lib.agn_oracle_pdf_draw_at.restype = C.c_int
+    pu64 = C.POINTER(C.c_uint64)
+    lib.agn_oracle_lag_stats.argtypes = [pd, i64, C.POINTER(C.c_int64), i32, i32, pd, i32, d, pd, pu64, pu64]
+    lib.agn_oracle_lag_stats.restype = C.c_int
     for name in ("psd_spectrum", "dft", "rfft", "irfft", "replace", "argsort",
                  "iterate", "generate", "periodogram"):
         getattr(lib, "agn_oracle_" + name).restype = C.c_int
@@ -235,6 +238,24 @@ def pdf_draw_at(params: PdfParams, idx, seed, curve_id=0):
                                         idx.ctypes.data_as(C.POINTER(C.c_int64)), len(idx), _pd(out)),
          "pdf_draw_at")
     return out
+
+
+def lag_stats(x, lags, units=0, dm_ref=(), lam_cut=0.0):
+    """(sf2[K], exceed[K, J], pairs[K]) of one series: Eq. A6 structure function
+    of x (units 0) or of -2.5 log10 x (units 1), and counts of pairs with
+    |dm| above each threshold (Fig. 16), with an optional detection cut (Fig. 17)."""
+    x = _f64(x)
+    lags = np.ascontiguousarray(lags, dtype=np.int64)
+    dm = np.ascontiguousarray(dm_ref, dtype=np.float64)
+    K, J = len(lags), len(dm)
+    sf2 = np.full(K, np.nan)
+    exceed = np.zeros((K, max(J, 1)), dtype=np.uint64)
+    pairs = np.zeros(K, dtype=np.uint64)
+    pu64 = C.POINTER(C.c_uint64)
+    _chk(_load().agn_oracle_lag_stats(_pd(x), len(x), lags.ctypes.data_as(C.POINTER(C.c_int64)), K, int(units),
+                                      _pd(dm) if J else None, J, float(lam_cut), _pd(sf2),
+                                      exceed.ctypes.data_as(pu64), pairs.ctypes.data_as(pu64)), "lag_stats")
+    return sf2, exceed[:, :J], pairs
 
 
 def periodogram(x):

@@ -562,3 +562,57 @@ int agn_oracle_periodogram(const double* x, int64_t n, double* P)
     free(X);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Lag statistics of a series (App. A, Eq. A6; Sec. 3.2.10; Sec. 4.2).        */
+/* ------------------------------------------------------------------------ */
+int agn_oracle_lag_stats(const double* x, int64_t n, const int64_t* lags, int32_t n_lags, int32_t units,
+                         const double* dm_ref, int32_t n_thr, double lam_cut, double* sf2_out,
+                         uint64_t* exceed_out, uint64_t* pairs_out)
+{
+    if (!x || n < 2 || !lags || n_lags < 0 || n_thr < 0 || (units != 0 && units != 1)) return E_INVAL;
+    if (n_thr > 0 && (!dm_ref || !exceed_out)) return E_INVAL;
+    if (n_thr > 64) return E_INVAL;
+    for (int32_t j = 0; j < n_thr; ++j)
+        if (!(dm_ref[j] >= 0.0) || !isfinite(dm_ref[j])) return E_INVAL;
+    for (int64_t i = 0; i < n; ++i)
+        if (!(x[i] > 0.0) || !isfinite(x[i])) return E_INVAL;
+    for (int32_t l = 0; l < n_lags; ++l)
+        if (lags[l] < 1 || lags[l] >= n) return E_INVAL;
+    for (int32_t l = 0; l < n_lags; ++l) {
+        const int64_t k = lags[l];
+        /* Eq. A6: mean over the n - k pairs separated by k samples of the squared
+         * difference, of x itself or of the magnitude -2.5 log10 x (Sec. 3.2.10) */
+        long double acc = 0.0L;
+        for (int64_t i = 0; i + k < n; ++i) {
+            const double a = x[i], b = x[i + k];
+            const double d = units ? -2.5 * (log10(b) - log10(a)) : b - a;
+            acc += (long double)d * d;
+        }
+        if (sf2_out) sf2_out[l] = (double)(acc / (long double)(n - k));
+        /* Fig. 16 / Fig. 17: pairs whose |dm| exceeds each threshold.  A point
+         * fainter than the cut is replaced by the cut (an upper limit) and only
+         * pairs with at least one point at or above the cut count.  |dm| > D is
+         * taken as hi > lo * 10^(D / 2.5), the factor rounded once to double. */
+        uint64_t pairs = 0;
+        double fac[64];
+        for (int32_t j = 0; j < n_thr; ++j) {
+            exceed_out[(int64_t)l * n_thr + j] = 0;
+            fac[j] = pow(10.0, dm_ref[j] / 2.5);
+        }
+        for (int64_t i = 0; i + k < n; ++i) {
+            double a = x[i], b = x[i + k];
+            if (lam_cut > 0.0) {
+                if (a < lam_cut && b < lam_cut) continue;
+                if (a < lam_cut) a = lam_cut;
+                if (b < lam_cut) b = lam_cut;
+            }
+            ++pairs;
+            const double hi = a > b ? a : b, lo = a > b ? b : a;
+            for (int32_t j = 0; j < n_thr; ++j)
+                if (hi > lo * fac[j]) ++exceed_out[(int64_t)l * n_thr + j];
+        }
+        if (pairs_out) pairs_out[l] = pairs;
+    }
+    return E_OK;
+}

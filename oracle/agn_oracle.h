@@ -117,6 +117,17 @@ int agn_oracle_pdf_draw_at(const agn_oracle_pdf_params* p, uint64_t seed, uint32
 /* Periodogram, Eq. A2: P[j] = 2/n^2 |DFT_j|^2 for j = 0..n/2. */
 int agn_oracle_periodogram(const double* x, int64_t n, double* P);
 
+/* Lag statistics of one positive series x[n] at lags[n_lags] (1 <= lag < n):
+ *   sf2_out[l] (nullable): Eq. A6, the mean over the n - lag pairs of the squared
+ *     difference of x (units 0) or of the magnitude -2.5 log10 x (units 1);
+ *   exceed_out[l * n_thr + j]: pairs with |dm| > dm_ref[j] (Fig. 16), taken as
+ *     hi > lo * 10^(dm_ref[j] / 2.5); with lam_cut > 0 values below lam_cut are
+ *     replaced by it and only pairs with a value >= lam_cut count (Fig. 17);
+ *   pairs_out[l] (nullable): the pairs counted.  At most 64 thresholds. */
+int agn_oracle_lag_stats(const double* x, int64_t n, const int64_t* lags, int32_t n_lags, int32_t units,
+                         const double* dm_ref, int32_t n_thr, double lam_cut, double* sf2_out,
+                         uint64_t* exceed_out, uint64_t* pairs_out);
+
 #ifdef __cplusplus
 }
 #endif
