@@ -328,6 +328,39 @@ const char* agn_ctx_kernel_names(void);
 int agn_test_philox(uint64_t key0, uint64_t key1, uint64_t ctr0, int64_t n_blocks,
                     uint64_t* out, void* stream);
 
+/*
+ * Lag statistics of the output series (Eq. A6; Sec. 3.2.10; Sec. 4.2,
+ * Figs. 16-17), for n_curves positive series at the same n_lags lags
+ * (in samples; 1 <= lags[l] < n[c] for every curve):
+ *   sf2_out[c * n_lags + l]  Eq. A6: the mean over the n - k pairs (x_i,
+ *                            x_{i+k}) of (x_{i+k} - x_i)^2 with
+ *                            units AGN_SF_LINEAR, or of dm^2 with
+ *                            dm = -2.5 log10(x_{i+k} / x_i) (AGN_SF_MAGNITUDE;
+ *                            Sec. 3.2.10);
+ *   rep_out[l]               Eq. 6: the mean of sf2 over the curves (lag by lag);
+ *   exceed_out[(c * n_lags + l) * n_thr + j]
+ *                            pairs with |dm| > dm_ref[j] (Fig. 16), decided as
+ *                            hi > lo * 10^(dm_ref[j] / 2.5) with the factor
+ *                            rounded once to double; with lam_cut > 0 a value
+ *                            below lam_cut is replaced by lam_cut (an upper
+ *                            limit) and only pairs with a value >= lam_cut are
+ *                            counted (Fig. 17);
+ *   pairs_out[c * n_lags + l] the pairs counted (n - k without a cut).
+ * n, offset, lags, dm_ref: host arrays; x and all outputs: device (every output
+ * nullable; exceed_out required when n_thr > 0).  dm_ref ascending, >= 0, at
+ * most 16 values.  x must be positive (not checked on the device).  Each
+ * (curve, lag) is summed in a fixed order: results are deterministic.
+ * Workspace: agn_lag_stats_workspace_size; no allocation.  Errors: AGN_EINVAL
+ * (nothing is launched).
+ */
+enum { AGN_SF_LINEAR = 0, AGN_SF_MAGNITUDE = 1 };
+int agn_lag_stats_workspace_size(int32_t n_curves, const int64_t* n, int32_t n_lags, const int64_t* lags,
+                                 int32_t n_thr, size_t* bytes);
+int agn_lag_stats_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n, const int64_t* offset, const double* x,
+                        int32_t n_lags, const int64_t* lags, int32_t units, double* sf2_out, double* rep_out,
+                        int32_t n_thr, const double* dm_ref, double lam_cut, uint64_t* exceed_out,
+                        uint64_t* pairs_out, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -96,6 +96,8 @@ def _declare(lib):
     lib.agn_test_philox.argtypes = [u64, u64, u64, i64, vp, vp]
     lib.agn_erdf_draw.argtypes = [vp, C.POINTER(agn_erdf_params), i64, u64, u32, vp, vp]
     lib.agn_pdf_draw.argtypes = [vp, C.POINTER(agn_pdf_params), i64, u64, u32, vp, vp]
+    lib.agn_lag_stats_workspace_size.argtypes = [i32, vp, i32, vp, i32, C.POINTER(sz)]
+    lib.agn_lag_stats_batch.argtypes = [vp, i32, vp, vp, vp, i32, vp, i32, vp, vp, i32, vp, d, vp, vp, vp, sz, vp]
     lib.agn_batch_plan_create.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_int, vp, vp, vp,
                                           C.c_int, C.c_int, vp, sz, vp, C.POINTER(vp)]
     lib.agn_batch_plan_launch.argtypes = [vp, vp]
@@ -113,7 +115,8 @@ def _declare(lib):
               "agn_lc_iterate", "agn_lc_generate", "agn_lc_generate_batch", "agn_test_philox",
               "agn_ctx_set_profiling", "agn_ctx_kernel_time", "agn_erdf_draw", "agn_pdf_draw", "agn_batch_plan_create",
               "agn_batch_plan_launch", "agn_batch_plan_info", "agn_batch_plan_destroy", "agn_log_bin_count",
-              "agn_periodogram_workspace_size", "agn_periodogram_batch"):
+              "agn_periodogram_workspace_size", "agn_periodogram_batch", "agn_lag_stats_workspace_size",
+              "agn_lag_stats_batch"):
         getattr(lib, f).restype = C.c_int
 
 
@@ -339,6 +342,34 @@ def agn_periodogram_batch(ctx: Context, n, offset, x, p_offset, P_out, dex=0.0, 
     _check(lib().agn_periodogram_batch(
         ctx.handle, nc, n.ctypes.data_as(vp), offset.ctypes.data_as(vp), _ptr(x), p_offset.ctypes.data_as(vp),
         _ptr(P_out), float(dex), None if bo is None else bo.ctypes.data_as(vp), _ptr(bins_out), _ptr(ws),
+        0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, ctx.device)))
+
+
+AGN_SF_LINEAR, AGN_SF_MAGNITUDE = 0, 1
+
+
+def agn_lag_stats_workspace_size(n, lags, n_thr=0):
+    vp = C.c_void_p
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    lags = np.ascontiguousarray(lags, dtype=np.int64)
+    out = C.c_size_t(0)
+    _check(lib().agn_lag_stats_workspace_size(len(n), n.ctypes.data_as(vp), len(lags), lags.ctypes.data_as(vp),
+                                              int(n_thr), C.byref(out)))
+    return out.value
+
+
+def agn_lag_stats_batch(ctx: Context, n, offset, x, lags, units=AGN_SF_LINEAR, sf2_out=None, rep_out=None,
+                        dm_ref=(), lam_cut=0.0, exceed_out=None, pairs_out=None, ws=None, stream=None):
+    """n, offset, lags, dm_ref: host sequences; x, outputs, ws: GPU tensors (outputs float64 / uint64 or int64)."""
+    vp = C.c_void_p
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    offset = np.ascontiguousarray(offset, dtype=np.int64)
+    lags = np.ascontiguousarray(lags, dtype=np.int64)
+    dm = np.ascontiguousarray(dm_ref, dtype=np.float64)
+    _check(lib().agn_lag_stats_batch(
+        ctx.handle, len(n), n.ctypes.data_as(vp), offset.ctypes.data_as(vp), _ptr(x), len(lags),
+        lags.ctypes.data_as(vp), int(units), _ptr(sf2_out), _ptr(rep_out), len(dm),
+        dm.ctypes.data_as(vp) if len(dm) else None, float(lam_cut), _ptr(exceed_out), _ptr(pairs_out), _ptr(ws),
         0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, ctx.device)))
 
 

@@ -194,7 +194,7 @@ struct agn_ctx {
 
 static const char* KERNEL_NAMES =
     "spectrum_partial,spectrum_norm,spectrum_amp,lds_prep,lds_iterate,big_prep,fft_pass,fold,"
-    "sort_hist,sort_scan,sort_scatter,delta,big_output,erdf_draw,batch_graph,periodogram,log_bins";
+    "sort_hist,sort_scan,sort_scatter,delta,big_output,erdf_draw,batch_graph,periodogram,log_bins,lag_stats";
 
 // Kernel timing: events recorded on the launch stream around each launch.
 struct ProfScope {
@@ -1502,6 +1502,122 @@ extern "C" int agn_periodogram_batch(agn_ctx* ctx, int32_t n_curves, const int64
         hipLaunchKernelGGL(k_log_bins, dim3((unsigned)maxbins, (unsigned)nc), dim3(256), 0, st, d_bd);
         HIPCHK(hipGetLastError());
     }
+    return AGN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// lag statistics: structure function (Eq. A6), Eq. 6 mean, |dm| counts
+// ---------------------------------------------------------------------------
+struct LagLayout {
+    size_t curves, lags, pre, part_sum, part_cnt, sf2, total;
+    int64_t blocks;
+};
+
+static int lag_layout(int32_t nc, const int64_t* n, int32_t K, const int64_t* lags, int32_t J, bool need_sf2,
+                      std::vector<int64_t>* pre, LagLayout* L) {
+    if (nc < 0 || K < 0 || J < 0) return fail(AGN_EINVAL, "negative count");
+    if (nc > 0 && !n) return fail(AGN_EINVAL, "n is NULL");
+    if (K > 0 && !lags) return fail(AGN_EINVAL, "lags is NULL");
+    if (J > LAG_MAX_THR) return fail(AGN_EINVAL, "at most %d thresholds", LAG_MAX_THR);
+    if ((int64_t)nc * K > (int64_t)INT32_MAX / 2) return fail(AGN_EINVAL, "too many (curve, lag) items");
+    pre->assign((size_t)nc * K + 1, 0);
+    int64_t g = 0;
+    for (int32_t c = 0; c < nc; ++c) {
+        if (n[c] < 2) return fail(AGN_EINVAL, "n[%d] = %lld < 2", c, (long long)n[c]);
+        for (int32_t l = 0; l < K; ++l) {
+            if (lags[l] < 1 || lags[l] >= n[c])
+                return fail(AGN_EINVAL, "lag %lld outside [1, n - 1] for curve %d (n = %lld)", (long long)lags[l], c,
+                            (long long)n[c]);
+            (*pre)[(size_t)c * K + l] = g;
+            const int64_t P = n[c] - lags[l];
+            g += std::min<int64_t>((P + LAG_CHUNK - 1) / LAG_CHUNK, LAG_MAX_BLOCKS);
+        }
+    }
+    (*pre)[(size_t)nc * K] = g;
+    const size_t items = (size_t)nc * K;
+    L->blocks = g;
+    L->curves = 0;
+    L->lags = L->curves + align256(sizeof(LagCurve) * (size_t)nc);
+    L->pre = L->lags + align256(sizeof(int64_t) * (size_t)K);
+    L->part_sum = L->pre + align256(sizeof(int64_t) * (items + 1));
+    L->part_cnt = L->part_sum + align256(sizeof(double) * (size_t)g);
+    L->sf2 = L->part_cnt + align256(sizeof(uint32_t) * (size_t)g * (size_t)(1 + J));
+    L->total = L->sf2 + (need_sf2 ? align256(sizeof(double) * items) : 0);
+    return AGN_OK;
+}
+
+extern "C" int agn_lag_stats_workspace_size(int32_t n_curves, const int64_t* n, int32_t n_lags, const int64_t* lags,
+                                            int32_t n_thr, size_t* bytes) {
+    if (!bytes) return fail(AGN_EINVAL, "bytes is NULL");
+    std::vector<int64_t> pre;
+    LagLayout L;
+    int rc = lag_layout(n_curves, n, n_lags, lags, n_thr, true, &pre, &L);
+    if (rc) return rc;
+    *bytes = L.total;
+    return AGN_OK;
+}
+
+extern "C" int agn_lag_stats_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n, const int64_t* offset,
+                                   const double* x, int32_t n_lags, const int64_t* lags, int32_t units,
+                                   double* sf2_out, double* rep_out, int32_t n_thr, const double* dm_ref,
+                                   double lam_cut, uint64_t* exceed_out, uint64_t* pairs_out, void* ws,
+                                   size_t ws_bytes, void* stream) {
+    if (!ctx) return fail(AGN_EINVAL, "ctx is NULL");
+    if (n_curves < 0 || n_lags < 0 || n_thr < 0) return fail(AGN_EINVAL, "negative count");
+    if (n_curves == 0 || n_lags == 0) return AGN_OK;
+    if (!n || !offset || !x || !lags) return fail(AGN_EINVAL, "NULL argument");
+    if (units != AGN_SF_LINEAR && units != AGN_SF_MAGNITUDE) return fail(AGN_EINVAL, "unknown units");
+    if (n_thr > 0 && (!dm_ref || !exceed_out)) return fail(AGN_EINVAL, "thresholds need dm_ref and exceed_out");
+    if (!std::isfinite(lam_cut)) return fail(AGN_EINVAL, "lam_cut must be finite");
+    for (int32_t j = 0; j < n_thr; ++j) {
+        if (!(dm_ref[j] >= 0.0) || !std::isfinite(dm_ref[j])) return fail(AGN_EINVAL, "dm_ref[%d] must be >= 0", j);
+        if (j > 0 && dm_ref[j] < dm_ref[j - 1]) return fail(AGN_EINVAL, "dm_ref must be ascending");
+    }
+    for (int32_t c = 0; c < n_curves; ++c)
+        if (offset[c] < 0) return fail(AGN_EINVAL, "offset[%d] < 0", c);
+    std::vector<int64_t> pre;
+    LagLayout L;
+    int rc = lag_layout(n_curves, n, n_lags, lags, n_thr, true, &pre, &L);
+    if (rc) return rc;
+    if (!ws || ws_bytes < L.total)
+        return fail(AGN_EINVAL, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, L.total);
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    unsigned char* base = (unsigned char*)ws;
+    std::vector<unsigned char> hdr(L.part_sum, 0);
+    LagCurve* hc = (LagCurve*)(hdr.data() + L.curves);
+    for (int32_t c = 0; c < n_curves; ++c) {
+        hc[c].x = x + offset[c];
+        hc[c].n = n[c];
+    }
+    memcpy(hdr.data() + L.lags, lags, sizeof(int64_t) * (size_t)n_lags);
+    memcpy(hdr.data() + L.pre, pre.data(), sizeof(int64_t) * pre.size());
+    if ((rc = stage_upload(ctx, ws, hdr.data(), hdr.size(), st))) return rc;
+    LagArgs A;
+    memset(&A, 0, sizeof(A));
+    A.curves = (const LagCurve*)(base + L.curves);
+    A.lags = (const int64_t*)(base + L.lags);
+    A.pre = (const int64_t*)(base + L.pre);
+    A.part_sum = (double*)(base + L.part_sum);
+    A.part_cnt = (uint32_t*)(base + L.part_cnt);
+    A.sf2 = sf2_out ? sf2_out : (double*)(base + L.sf2);
+    A.exceed = n_thr > 0 ? exceed_out : nullptr;
+    A.pairs = pairs_out;
+    A.items = n_curves * n_lags;
+    A.K = n_lags;
+    A.J = n_thr;
+    A.units = units;
+    A.cut = lam_cut;
+    for (int32_t j = 0; j < n_thr; ++j) A.fac[j] = std::pow(10.0, dm_ref[j] / 2.5);
+    {
+        ProfScope ps(ctx, "lag_stats", st);
+        hipLaunchKernelGGL(k_lag_partial, dim3((unsigned)L.blocks), dim3(LAG_THREADS), 0, st, A);
+        hipLaunchKernelGGL(k_lag_finish, dim3((unsigned)A.items), dim3(LAG_THREADS), 0, st, A);
+        if (rep_out)
+            hipLaunchKernelGGL(k_lag_rep, dim3((unsigned)((n_lags + 255) / 256)), dim3(256), 0, st,
+                               (const double*)A.sf2, n_curves, n_lags, rep_out);
+    }
+    HIPCHK(hipGetLastError());
     return AGN_OK;
 }
 

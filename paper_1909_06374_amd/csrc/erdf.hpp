@@ -76,12 +76,11 @@ AGN_DEV double eq1_density(const PdfTable& P, double u) {
 
 // Six-point Gauss-Legendre integral of the density over [a, a + w].
 AGN_DEV double eq1_integral(const PdfTable& P, double a, double w) {
-    const double xn[3] = {0.2386191860831969086, 0.6612093864662645136, 0.9324695142031520279};
-    const double wn[3] = {0.4679139345726910473, 0.3607615730481386076, 0.1713244923791703450};
     const double c = a + 0.5 * w, hw = 0.5 * w;
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) s += wn[j] * (eq1_density(P, c - hw * xn[j]) + eq1_density(P, c + hw * xn[j]));
+    const double x0 = 0.2386191860831969086, x1 = 0.6612093864662645136, x2 = 0.9324695142031520279;
+    double s = 0.4679139345726910473 * (eq1_density(P, c - hw * x0) + eq1_density(P, c + hw * x0));
+    s += 0.3607615730481386076 * (eq1_density(P, c - hw * x1) + eq1_density(P, c + hw * x1));
+    s += 0.1713244923791703450 * (eq1_density(P, c - hw * x2) + eq1_density(P, c + hw * x2));
     return s * hw;
 }
 

@@ -1,7 +1,8 @@
-// observables.hpp -- the periodogram of App. A (Eq. A2) for a batch of real
-// series, e.g. the generator's output, and its means over logarithmic
-// frequency bins: P_j = 2 / N^2 |X_j|^2, X_j = sum_t x[t] exp(-2 pi i j t / N),
-// j = 0..N/2, in double precision.
+// observables.hpp -- what is measured on the generator's output (App. A,
+// Sec. 3.2.10, Sec. 4.2): the periodogram of Eq. A2 for a batch of real
+// series and its means over logarithmic frequency bins,
+// P_j = 2 / N^2 |X_j|^2, X_j = sum_t x[t] exp(-2 pi i j t / N), j = 0..N/2,
+// in double precision; and lag statistics (structure function, |dm| counts).
 //
 // Curves that fit one workgroup's LDS transform there (Stockham passes of the
 // half-length complex FFT of z[m] = x[2m] + i x[2m+1], then the real-spectrum
@@ -127,6 +128,162 @@ __global__ __launch_bounds__(256) void k_log_bins(const BinDesc* __restrict__ bd
     if (lane == 0) sh[wave] = acc;
     __syncthreads();
     if (tid == 0) b.out[bin] = ((sh[0] + sh[1]) + (sh[2] + sh[3])) / (double)(hi - lo);
+}
+
+// ---------------------------------------------------------------------------
+// Lag statistics (Eq. A6; Sec. 3.2.10; Figs. 16-17) of a batch of positive
+// series at caller-chosen lags.  Work item = (curve, lag); each item is split
+// over up to LAG_MAX_BLOCKS workgroups, each of which strides over chunks of
+// LAG_CHUNK pairs, reading x[i] and x[i + k] coalesced.  Every workgroup
+// writes its partial sum (FP64) and counts (u32) to the workspace; a second
+// kernel adds them per item in a fixed order, so results do not depend on
+// timing.  No atomics.
+// ---------------------------------------------------------------------------
+constexpr int LAG_THREADS = 256;
+constexpr int LAG_IPT = 8;
+constexpr int64_t LAG_CHUNK = (int64_t)LAG_THREADS * LAG_IPT;
+constexpr int LAG_MAX_BLOCKS = 64;
+constexpr int LAG_MAX_THR = 16;
+
+struct LagCurve {
+    const double* x;
+    int64_t n;
+};
+
+struct LagArgs {
+    const LagCurve* curves;
+    const int64_t* lags;     // [K]
+    const int64_t* pre;      // [items + 1], first workgroup of each item
+    double* part_sum;        // [workgroups]
+    uint32_t* part_cnt;      // [workgroups][1 + J]: counted pairs, then one per threshold
+    double* sf2;             // [items]
+    uint64_t* exceed;        // [items][J] or null
+    uint64_t* pairs;         // [items] or null
+    int32_t items, K, J, units;
+    double cut;              // <= 0: no detection cut
+    double fac[LAG_MAX_THR]; // 10^(dm_ref / 2.5), ascending
+};
+
+AGN_DEV int lag_item_of(const int64_t* pre, int items, int64_t g) {
+    int lo = 0, hi = items;  // pre[lo] <= g < pre[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(LAG_THREADS) void k_lag_partial(LagArgs A) {
+    __shared__ double wsum[LAG_THREADS / 64];
+    __shared__ uint32_t wcnt[LAG_THREADS / 64][1 + LAG_MAX_THR];
+    const int64_t g = blockIdx.x;
+    const int item = lag_item_of(A.pre, A.items, g);
+    const int64_t b = g - A.pre[item], nb = A.pre[item + 1] - A.pre[item];
+    const int c = item / A.K;
+    const int64_t k = A.lags[item - c * A.K];
+    const double* __restrict__ x = A.curves[c].x;
+    const int64_t P = A.curves[c].n - k;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int J = A.J;
+    double acc = 0.0;
+    uint32_t npairs = 0;
+    uint32_t cnt[LAG_MAX_THR];
+#pragma unroll
+    for (int j = 0; j < LAG_MAX_THR; ++j) cnt[j] = 0;
+    for (int64_t q = b; q * LAG_CHUNK < P; q += nb) {
+        const int64_t base = q * LAG_CHUNK + tid;
+        double va[LAG_IPT], vb[LAG_IPT];
+#pragma unroll
+        for (int e = 0; e < LAG_IPT; ++e) {
+            const int64_t i = base + (int64_t)e * LAG_THREADS;
+            va[e] = i < P ? x[i] : 1.0;
+            vb[e] = i < P ? x[i + k] : 1.0;
+        }
+#pragma unroll
+        for (int e = 0; e < LAG_IPT; ++e) {
+            if (base + (int64_t)e * LAG_THREADS >= P) break;
+            double a = va[e], bb = vb[e];
+            const double d = A.units ? -2.5 * (log10(bb) - log10(a)) : bb - a;
+            acc += d * d;
+            if (A.cut > 0.0) {
+                if (a < A.cut && bb < A.cut) continue;
+                a = fmax(a, A.cut);
+                bb = fmax(bb, A.cut);
+            }
+            ++npairs;
+            const double hi = fmax(a, bb), lo = fmin(a, bb);
+#pragma unroll
+            for (int j = 0; j < LAG_MAX_THR; ++j)
+                if (j < J && hi > lo * A.fac[j]) ++cnt[j];
+        }
+    }
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        acc += __shfl_xor(acc, s, 64);
+        npairs += __shfl_xor(npairs, s, 64);
+    }
+#pragma unroll
+    for (int j = 0; j < LAG_MAX_THR; ++j) {
+        if (j < J) {  // uniform
+            uint32_t v = cnt[j];
+#pragma unroll
+            for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, 64);
+            if (lane == 0) wcnt[wv][1 + j] = v;
+        }
+    }
+    if (lane == 0) {
+        wsum[wv] = acc;
+        wcnt[wv][0] = npairs;
+    }
+    __syncthreads();
+    if (tid == 0) A.part_sum[g] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+    if (tid <= J) A.part_cnt[g * (1 + J) + tid] = wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+}
+
+// One workgroup per item: the item's partials in a fixed order.
+__global__ __launch_bounds__(LAG_THREADS) void k_lag_finish(LagArgs A) {
+    __shared__ double ssum[LAG_THREADS];
+    __shared__ uint64_t scnt[LAG_THREADS];
+    const int item = blockIdx.x, tid = threadIdx.x;
+    const int64_t g0 = A.pre[item], g1 = A.pre[item + 1];
+    const int c = item / A.K;
+    const int64_t P = A.curves[c].n - A.lags[item - c * A.K];
+    const int J = A.J;
+    double acc = 0.0;
+    for (int64_t g = g0 + tid; g < g1; g += LAG_THREADS) acc += A.part_sum[g];
+    ssum[tid] = acc;
+    __syncthreads();
+    for (int s = LAG_THREADS / 2; s >= 1; s >>= 1) {
+        if (tid < s) ssum[tid] += ssum[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) A.sf2[item] = ssum[0] / (double)P;
+    for (int j = 0; j <= J; ++j) {
+        uint64_t v = 0;
+        for (int64_t g = g0 + tid; g < g1; g += LAG_THREADS) v += A.part_cnt[g * (1 + J) + j];
+        scnt[tid] = v;
+        __syncthreads();
+        for (int s = LAG_THREADS / 2; s >= 1; s >>= 1) {
+            if (tid < s) scnt[tid] += scnt[tid + s];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            if (j == 0 && A.pairs) A.pairs[item] = scnt[0];
+            if (j > 0 && A.exceed) A.exceed[(int64_t)item * J + (j - 1)] = scnt[0];
+        }
+        __syncthreads();
+    }
+}
+
+// Eq. 6: mean of SF^2 over the curves at each lag.  grid: ceil(K / 256).
+__global__ __launch_bounds__(256) void k_lag_rep(const double* __restrict__ sf2, int32_t n_curves, int32_t K,
+                                                 double* __restrict__ rep) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= K) return;
+    double acc = 0.0;
+    for (int c = 0; c < n_curves; ++c) acc += sf2[(int64_t)c * K + l];
+    rep[l] = acc / (double)n_curves;
 }
 
 }  // namespace agn
