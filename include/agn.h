@@ -350,12 +350,13 @@ int agn_test_philox(uint64_t key0, uint64_t key1, uint64_t ctr0, int64_t n_block
  * nullable; exceed_out required when n_thr > 0).  dm_ref ascending, >= 0, at
  * most 16 values.  x must be positive (not checked on the device).  Each
  * (curve, lag) is summed in a fixed order: results are deterministic.
- * Workspace: agn_lag_stats_workspace_size; no allocation.  Errors: AGN_EINVAL
+ * Workspace: agn_lag_stats_workspace_size (in magnitudes it holds -2.5 log10 x,
+ * 8 bytes per sample); no allocation.  Errors: AGN_EINVAL
  * (nothing is launched).
  */
 enum { AGN_SF_LINEAR = 0, AGN_SF_MAGNITUDE = 1 };
 int agn_lag_stats_workspace_size(int32_t n_curves, const int64_t* n, int32_t n_lags, const int64_t* lags,
-                                 int32_t n_thr, size_t* bytes);
+                                 int32_t n_thr, int32_t units, size_t* bytes);
 int agn_lag_stats_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n, const int64_t* offset, const double* x,
                         int32_t n_lags, const int64_t* lags, int32_t units, double* sf2_out, double* rep_out,
                         int32_t n_thr, const double* dm_ref, double lam_cut, uint64_t* exceed_out,

@@ -96,7 +96,7 @@ def _declare(lib):
     lib.agn_test_philox.argtypes = [u64, u64, u64, i64, vp, vp]
     lib.agn_erdf_draw.argtypes = [vp, C.POINTER(agn_erdf_params), i64, u64, u32, vp, vp]
     lib.agn_pdf_draw.argtypes = [vp, C.POINTER(agn_pdf_params), i64, u64, u32, vp, vp]
-    lib.agn_lag_stats_workspace_size.argtypes = [i32, vp, i32, vp, i32, C.POINTER(sz)]
+    lib.agn_lag_stats_workspace_size.argtypes = [i32, vp, i32, vp, i32, i32, C.POINTER(sz)]
     lib.agn_lag_stats_batch.argtypes = [vp, i32, vp, vp, vp, i32, vp, i32, vp, vp, i32, vp, d, vp, vp, vp, sz, vp]
     lib.agn_batch_plan_create.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_int, vp, vp, vp,
                                           C.c_int, C.c_int, vp, sz, vp, C.POINTER(vp)]
@@ -348,13 +348,13 @@ def agn_periodogram_batch(ctx: Context, n, offset, x, p_offset, P_out, dex=0.0, 
 AGN_SF_LINEAR, AGN_SF_MAGNITUDE = 0, 1
 
 
-def agn_lag_stats_workspace_size(n, lags, n_thr=0):
+def agn_lag_stats_workspace_size(n, lags, n_thr=0, units=AGN_SF_LINEAR):
     vp = C.c_void_p
     n = np.ascontiguousarray(n, dtype=np.int64)
     lags = np.ascontiguousarray(lags, dtype=np.int64)
     out = C.c_size_t(0)
     _check(lib().agn_lag_stats_workspace_size(len(n), n.ctypes.data_as(vp), len(lags), lags.ctypes.data_as(vp),
-                                              int(n_thr), C.byref(out)))
+                                              int(n_thr), int(units), C.byref(out)))
     return out.value
 
 

@@ -1328,14 +1328,24 @@ static size_t pg_header_ws(int32_t nc) {
            align256(sizeof(BinDesc) * (size_t)nc) + align256(sizeof(double*) * (size_t)nc);
 }
 
-static size_t pg_curve_ws(int64_t n, double dex) {
+// Bin edges per distinct length within one call (batches repeat lengths).
+struct EdgeCache {
+    double dex;
+    std::map<int64_t, std::vector<int64_t>> by_n;
+    const std::vector<int64_t>& get(int64_t n) {
+        auto it = by_n.find(n);
+        if (it == by_n.end()) {
+            it = by_n.emplace(n, std::vector<int64_t>()).first;
+            log_bin_edges(n, dex, &it->second);
+        }
+        return it->second;
+    }
+};
+
+static size_t pg_curve_ws(int64_t n, double dex, EdgeCache* ec) {
     size_t b = 0;
     if (!pg_lds(n)) b += 2 * align256((size_t)n * 8) + align256(16);  // FFT ping-pong + state
-    if (dex > 0.0) {
-        std::vector<int64_t> e;
-        log_bin_edges(n, dex, &e);
-        b += align256(e.size() * sizeof(int64_t));
-    }
+    if (dex > 0.0) b += align256(ec->get(n).size() * sizeof(int64_t));
     return b;
 }
 
@@ -1343,10 +1353,12 @@ extern "C" int agn_periodogram_workspace_size(int32_t n_curves, const int64_t* n
     if (!bytes || (n_curves > 0 && !n)) return fail(AGN_EINVAL, "NULL argument");
     if (n_curves < 0) return fail(AGN_EINVAL, "n_curves < 0");
     size_t b = pg_header_ws(n_curves);
+    EdgeCache ec;
+    ec.dex = dex;
     for (int32_t c = 0; c < n_curves; ++c) {
         if (!n_supported(n[c]) || n[c] < 4)
             return fail(AGN_EUNSUPPORTED_N, "n=%lld is not 2^a or 3*2^a in [4, 2^27]", (long long)n[c]);
-        b += pg_curve_ws(n[c], dex);
+        b += pg_curve_ws(n[c], dex, &ec);
     }
     *bytes = b;
     return AGN_OK;
@@ -1397,7 +1409,9 @@ extern "C" int agn_periodogram_batch(agn_ctx* ctx, int32_t n_curves, const int64
     std::vector<BigCurve> bg(nc);
     std::vector<BinDesc> bd(nc);
     std::vector<double*> pp(nc);
-    std::vector<std::vector<int64_t>> edges(nc);
+    EdgeCache ec;
+    ec.dex = dex;
+    std::vector<const std::vector<int64_t>*> edges(nc, nullptr);
     size_t off = pg_header_ws(nc);
     int32_t maxbins = 0;
     int n_lds = 0;
@@ -1426,13 +1440,13 @@ extern "C" int agn_periodogram_batch(agn_ctx* ctx, int32_t n_curves, const int64
             b.state = (int32_t*)(base + off); off += align256(16);
         }
         if (bins_out) {
-            log_bin_edges(nn, dex, &edges[i]);
+            edges[i] = &ec.get(nn);
             bd[i].P = P_out + p_offset[c];
             bd[i].out = bins_out + b_offset[c];
             bd[i].edges = (const int64_t*)(base + off);
-            bd[i].nbins = (int32_t)(edges[i].size() / 2);
+            bd[i].nbins = (int32_t)(edges[i]->size() / 2);
             maxbins = std::max(maxbins, bd[i].nbins);
-            off += align256(edges[i].size() * sizeof(int64_t));
+            off += align256(edges[i]->size() * sizeof(int64_t));
         }
     }
     // one upload: header, then the bin edges
@@ -1443,9 +1457,9 @@ extern "C" int agn_periodogram_batch(agn_ctx* ctx, int32_t n_curves, const int64
         memcpy(hdr.data() + ((unsigned char*)d_bd - base), bd.data(), sizeof(BinDesc) * (size_t)nc);
         memcpy(hdr.data() + ((unsigned char*)d_pp - base), pp.data(), sizeof(double*) * (size_t)nc);
         for (int i = 0; i < nc; ++i)
-            if (bins_out && !edges[i].empty())
-                memcpy(hdr.data() + ((const unsigned char*)bd[i].edges - base), edges[i].data(),
-                       edges[i].size() * sizeof(int64_t));
+            if (bins_out && edges[i] && !edges[i]->empty())
+                memcpy(hdr.data() + ((const unsigned char*)bd[i].edges - base), edges[i]->data(),
+                       edges[i]->size() * sizeof(int64_t));
         if ((rc = stage_upload(ctx, ws, hdr.data(), hdr.size(), st))) return rc;
     }
     {
@@ -1509,16 +1523,17 @@ extern "C" int agn_periodogram_batch(agn_ctx* ctx, int32_t n_curves, const int64
 // lag statistics: structure function (Eq. A6), Eq. 6 mean, |dm| counts
 // ---------------------------------------------------------------------------
 struct LagLayout {
-    size_t curves, lags, pre, part_sum, part_cnt, sf2, total;
+    size_t curves, lags, pre, part_sum, part_cnt, sf2, mag, total;
     int64_t blocks;
 };
 
-static int lag_layout(int32_t nc, const int64_t* n, int32_t K, const int64_t* lags, int32_t J, bool need_sf2,
-                      std::vector<int64_t>* pre, LagLayout* L) {
+static int lag_layout(int32_t nc, const int64_t* n, int32_t K, const int64_t* lags, int32_t J, int32_t units,
+                      std::vector<int64_t>* pre, std::vector<size_t>* mag_off, LagLayout* L) {
     if (nc < 0 || K < 0 || J < 0) return fail(AGN_EINVAL, "negative count");
     if (nc > 0 && !n) return fail(AGN_EINVAL, "n is NULL");
     if (K > 0 && !lags) return fail(AGN_EINVAL, "lags is NULL");
     if (J > LAG_MAX_THR) return fail(AGN_EINVAL, "at most %d thresholds", LAG_MAX_THR);
+    if (units != AGN_SF_LINEAR && units != AGN_SF_MAGNITUDE) return fail(AGN_EINVAL, "unknown units");
     if ((int64_t)nc * K > (int64_t)INT32_MAX / 2) return fail(AGN_EINVAL, "too many (curve, lag) items");
     pre->assign((size_t)nc * K + 1, 0);
     int64_t g = 0;
@@ -1542,16 +1557,24 @@ static int lag_layout(int32_t nc, const int64_t* n, int32_t K, const int64_t* la
     L->part_sum = L->pre + align256(sizeof(int64_t) * (items + 1));
     L->part_cnt = L->part_sum + align256(sizeof(double) * (size_t)g);
     L->sf2 = L->part_cnt + align256(sizeof(uint32_t) * (size_t)g * (size_t)(1 + J));
-    L->total = L->sf2 + (need_sf2 ? align256(sizeof(double) * items) : 0);
+    L->mag = L->sf2 + align256(sizeof(double) * items);
+    L->total = L->mag;
+    mag_off->assign((size_t)nc, 0);
+    if (units == AGN_SF_MAGNITUDE)
+        for (int32_t c = 0; c < nc; ++c) {
+            (*mag_off)[c] = L->total;
+            L->total += align256(sizeof(double) * (size_t)n[c]);
+        }
     return AGN_OK;
 }
 
 extern "C" int agn_lag_stats_workspace_size(int32_t n_curves, const int64_t* n, int32_t n_lags, const int64_t* lags,
-                                            int32_t n_thr, size_t* bytes) {
+                                            int32_t n_thr, int32_t units, size_t* bytes) {
     if (!bytes) return fail(AGN_EINVAL, "bytes is NULL");
     std::vector<int64_t> pre;
+    std::vector<size_t> mag;
     LagLayout L;
-    int rc = lag_layout(n_curves, n, n_lags, lags, n_thr, true, &pre, &L);
+    int rc = lag_layout(n_curves, n, n_lags, lags, n_thr, units, &pre, &mag, &L);
     if (rc) return rc;
     *bytes = L.total;
     return AGN_OK;
@@ -1576,8 +1599,9 @@ extern "C" int agn_lag_stats_batch(agn_ctx* ctx, int32_t n_curves, const int64_t
     for (int32_t c = 0; c < n_curves; ++c)
         if (offset[c] < 0) return fail(AGN_EINVAL, "offset[%d] < 0", c);
     std::vector<int64_t> pre;
+    std::vector<size_t> mag;
     LagLayout L;
-    int rc = lag_layout(n_curves, n, n_lags, lags, n_thr, true, &pre, &L);
+    int rc = lag_layout(n_curves, n, n_lags, lags, n_thr, units, &pre, &mag, &L);
     if (rc) return rc;
     if (!ws || ws_bytes < L.total)
         return fail(AGN_EINVAL, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, L.total);
@@ -1588,6 +1612,7 @@ extern "C" int agn_lag_stats_batch(agn_ctx* ctx, int32_t n_curves, const int64_t
     LagCurve* hc = (LagCurve*)(hdr.data() + L.curves);
     for (int32_t c = 0; c < n_curves; ++c) {
         hc[c].x = x + offset[c];
+        hc[c].m = units == AGN_SF_MAGNITUDE ? (double*)(base + mag[c]) : nullptr;
         hc[c].n = n[c];
     }
     memcpy(hdr.data() + L.lags, lags, sizeof(int64_t) * (size_t)n_lags);
@@ -1611,6 +1636,12 @@ extern "C" int agn_lag_stats_batch(agn_ctx* ctx, int32_t n_curves, const int64_t
     for (int32_t j = 0; j < n_thr; ++j) A.fac[j] = std::pow(10.0, dm_ref[j] / 2.5);
     {
         ProfScope ps(ctx, "lag_stats", st);
+        if (units == AGN_SF_MAGNITUDE) {
+            int64_t nmax = 0;
+            for (int32_t c = 0; c < n_curves; ++c) nmax = std::max(nmax, n[c]);
+            hipLaunchKernelGGL(k_lag_mag, dim3((unsigned)((nmax + 1023) / 1024), (unsigned)n_curves), dim3(256), 0,
+                               st, A.curves);
+        }
         hipLaunchKernelGGL(k_lag_partial, dim3((unsigned)L.blocks), dim3(LAG_THREADS), 0, st, A);
         hipLaunchKernelGGL(k_lag_finish, dim3((unsigned)A.items), dim3(LAG_THREADS), 0, st, A);
         if (rep_out)

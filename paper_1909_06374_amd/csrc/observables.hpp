@@ -134,10 +134,11 @@ __global__ __launch_bounds__(256) void k_log_bins(const BinDesc* __restrict__ bd
 // Lag statistics (Eq. A6; Sec. 3.2.10; Figs. 16-17) of a batch of positive
 // series at caller-chosen lags.  Work item = (curve, lag); each item is split
 // over up to LAG_MAX_BLOCKS workgroups, each of which strides over chunks of
-// LAG_CHUNK pairs, reading x[i] and x[i + k] coalesced.  Every workgroup
-// writes its partial sum (FP64) and counts (u32) to the workspace; a second
-// kernel adds them per item in a fixed order, so results do not depend on
-// timing.  No atomics.
+// LAG_CHUNK pairs, reading x[i] and x[i + k] coalesced.  In magnitudes, a first
+// pass writes m = -2.5 log10 x once per sample, so the pair loop takes no
+// logarithms.  Every workgroup writes its partial sum (FP64) and counts (u32)
+// to the workspace; a second kernel adds them per item in a fixed order, so
+// results do not depend on timing.  No atomics.
 // ---------------------------------------------------------------------------
 constexpr int LAG_THREADS = 256;
 constexpr int LAG_IPT = 8;
@@ -147,8 +148,17 @@ constexpr int LAG_MAX_THR = 16;
 
 struct LagCurve {
     const double* x;
+    double* m;        // -2.5 log10 x (magnitude units), workspace
     int64_t n;
 };
+
+// m = -2.5 log10 x for every curve.  grid: (ceil(max n / 1024), curves).
+__global__ __launch_bounds__(256) void k_lag_mag(const LagCurve* __restrict__ cv) {
+    const LagCurve& c = cv[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x; i < c.n && i < (int64_t)(blockIdx.x + 1) * 1024;
+         i += 256)
+        c.m[i] = -2.5 * log10(c.x[i]);
+}
 
 struct LagArgs {
     const LagCurve* curves;
@@ -183,6 +193,7 @@ __global__ __launch_bounds__(LAG_THREADS) void k_lag_partial(LagArgs A) {
     const int c = item / A.K;
     const int64_t k = A.lags[item - c * A.K];
     const double* __restrict__ x = A.curves[c].x;
+    const double* __restrict__ mg = A.curves[c].m;
     const int64_t P = A.curves[c].n - k;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int J = A.J;
@@ -193,19 +204,28 @@ __global__ __launch_bounds__(LAG_THREADS) void k_lag_partial(LagArgs A) {
     for (int j = 0; j < LAG_MAX_THR; ++j) cnt[j] = 0;
     for (int64_t q = b; q * LAG_CHUNK < P; q += nb) {
         const int64_t base = q * LAG_CHUNK + tid;
-        double va[LAG_IPT], vb[LAG_IPT];
+        double va[LAG_IPT], vb[LAG_IPT], d[LAG_IPT];
 #pragma unroll
         for (int e = 0; e < LAG_IPT; ++e) {
             const int64_t i = base + (int64_t)e * LAG_THREADS;
             va[e] = i < P ? x[i] : 1.0;
             vb[e] = i < P ? x[i + k] : 1.0;
         }
+        if (A.units) {
+#pragma unroll
+            for (int e = 0; e < LAG_IPT; ++e) {
+                const int64_t i = base + (int64_t)e * LAG_THREADS;
+                d[e] = i < P ? mg[i + k] - mg[i] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < LAG_IPT; ++e) d[e] = vb[e] - va[e];
+        }
 #pragma unroll
         for (int e = 0; e < LAG_IPT; ++e) {
             if (base + (int64_t)e * LAG_THREADS >= P) break;
             double a = va[e], bb = vb[e];
-            const double d = A.units ? -2.5 * (log10(bb) - log10(a)) : bb - a;
-            acc += d * d;
+            acc += d[e] * d[e];
             if (A.cut > 0.0) {
                 if (a < A.cut && bb < A.cut) continue;
                 a = fmax(a, A.cut);
