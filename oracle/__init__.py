@@ -89,6 +89,8 @@ def _load():
     pu64 = C.POINTER(C.c_uint64)
     lib.agn_oracle_lag_stats.argtypes = [pd, i64, C.POINTER(C.c_int64), i32, i32, pd, i32, d, pd, pu64, pu64]
     lib.agn_oracle_lag_stats.restype = C.c_int
+    lib.agn_oracle_psd_fit.argtypes = [pd, pd, i64, d, d, d, pd]
+    lib.agn_oracle_psd_fit.restype = C.c_int
     for name in ("psd_spectrum", "dft", "rfft", "irfft", "replace", "argsort",
                  "iterate", "generate", "periodogram"):
         getattr(lib, "agn_oracle_" + name).restype = C.c_int
@@ -263,6 +265,30 @@ def periodogram(x):
     P = np.full(len(x) // 2 + 1, np.nan, dtype=np.float64)
     _chk(_load().agn_oracle_periodogram(_pd(x), len(x), _pd(P)), "periodogram")
     return P
+
+
+def psd_fit(f, pbar, f_br, a_low0=1.0, a_high0=2.0):
+    """Eq. 3 fitted to a binned periodogram in log10 space with the break held
+    at f_br: returns (log10 A, a_low, a_high, rms of the log10 residuals)."""
+    f, pbar = _f64(f), _f64(pbar)
+    out = np.full(4, np.nan)
+    _chk(_load().agn_oracle_psd_fit(_pd(f), _pd(pbar), len(f), float(f_br), float(a_low0), float(a_high0),
+                                    _pd(out)), "psd_fit")
+    return out
+
+
+def log_binned_mean_f(P, n, dt, dex=0.1):
+    """The log bins of log_binned, with each bin's frequency the arithmetic mean
+    of the f_j it holds.  Returns (f_mean, mean P)."""
+    j = np.arange(1, n // 2 + 1)
+    f = j / (n * dt)
+    b = np.floor(np.log10(f / f[0]) / dex + 1e-9).astype(np.int64)
+    nb = int(b.max()) + 1
+    s = np.bincount(b, weights=P[1:], minlength=nb)
+    sf = np.bincount(b, weights=f, minlength=nb)
+    c = np.bincount(b, minlength=nb)
+    keep = c > 0
+    return sf[keep] / c[keep], s[keep] / c[keep]
 
 
 def log_binned(P, n, dt, dex=0.1):

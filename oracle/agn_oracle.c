@@ -616,3 +616,101 @@ int agn_oracle_lag_stats(const double* x, int64_t n, const int64_t* lags, int32_
     }
     return E_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Fit of Eq. 3 to a binned periodogram (the convergence test of Sec. 3.2.2). */
+/* ------------------------------------------------------------------------ */
+/* Least squares in log10 P over the bins with pbar > 0:
+ *   model(f) = a - log10((f / f_br)^a_low + (f / f_br)^a_high),
+ * with f_br held at the input value and (a, a_low, a_high) free; Gauss-Newton
+ * in extended precision with step halving, from a_low0 / a_high0 and the best
+ * a for them, until the step is below 1e-14 of the parameters. */
+static long double fit_sse(const double* f, const double* pbar, int64_t nb, double f_br, const long double th[3])
+{
+    long double sse = 0.0L;
+    for (int64_t b = 0; b < nb; ++b) {
+        if (!(pbar[b] > 0.0)) continue;
+        const long double lu = logl((long double)f[b] / (long double)f_br);
+        const long double m = th[0] - log10l(expl(th[1] * lu) + expl(th[2] * lu));
+        const long double r = log10l((long double)pbar[b]) - m;
+        sse += r * r;
+    }
+    return sse;
+}
+
+int agn_oracle_psd_fit(const double* f, const double* pbar, int64_t nb, double f_br, double a_low0, double a_high0,
+                       double out[4])
+{
+    if (!f || !pbar || !out || nb < 0 || !(f_br > 0.0)) return E_INVAL;
+    int64_t used = 0, below = 0, above = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        if (!(pbar[b] > 0.0)) continue;
+        if (!(f[b] > 0.0)) return E_INVAL;
+        ++used;
+        below += f[b] < f_br;
+        above += f[b] > f_br;
+    }
+    if (used < 3 || below < 1 || above < 1) return E_INVAL;
+    long double th[3] = {0.0L, a_low0, a_high0};
+    {
+        long double s = 0.0L;
+        for (int64_t b = 0; b < nb; ++b) {
+            if (!(pbar[b] > 0.0)) continue;
+            const long double lu = logl((long double)f[b] / (long double)f_br);
+            s += log10l((long double)pbar[b]) + log10l(expl(th[1] * lu) + expl(th[2] * lu));
+        }
+        th[0] = s / used;
+    }
+    long double sse = fit_sse(f, pbar, nb, f_br, th);
+    for (int it = 0; it < 500; ++it) {
+        long double A[3][3] = {{0}}, g[3] = {0};
+        for (int64_t b = 0; b < nb; ++b) {
+            if (!(pbar[b] > 0.0)) continue;
+            const long double lu = logl((long double)f[b] / (long double)f_br), L = lu / logl(10.0L);
+            const long double tl = expl(th[1] * lu), thh = expl(th[2] * lu), S = tl + thh;
+            const long double r = log10l((long double)pbar[b]) - (th[0] - log10l(S));
+            const long double J[3] = {1.0L, -tl / S * L, -thh / S * L};  /* d model / d theta */
+            for (int i = 0; i < 3; ++i) {
+                g[i] += J[i] * r;
+                for (int k = 0; k < 3; ++k) A[i][k] += J[i] * J[k];
+            }
+        }
+        /* solve A d = g by Cramer's rule */
+        const long double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                                A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                                A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+        if (!(fabsl(det) > 0.0L)) return E_INVAL;
+        long double d[3];
+        for (int c = 0; c < 3; ++c) {
+            long double M[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int k = 0; k < 3; ++k) M[i][k] = (k == c) ? g[i] : A[i][k];
+            d[c] = (M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                    M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                    M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0])) / det;
+        }
+        long double step = 1.0L, nt[3], nsse = 0.0L;
+        for (int h = 0; h < 60; ++h) {
+            for (int i = 0; i < 3; ++i) nt[i] = th[i] + step * d[i];
+            nsse = fit_sse(f, pbar, nb, f_br, nt);
+            if (nsse <= sse) break;
+            step *= 0.5L;
+        }
+        if (!(nsse <= sse)) break;  /* no descent left: at the minimum to working precision */
+        long double mx = 0.0L;
+        for (int i = 0; i < 3; ++i) {
+            const long double rel = fabsl(nt[i] - th[i]) / (1.0L + fabsl(th[i]));
+            if (rel > mx) mx = rel;
+            th[i] = nt[i];
+        }
+        sse = nsse;
+        if (mx < 1e-14L) break;
+    }
+    /* Eq. 3 is symmetric in its two slopes; the smaller one is the
+     * low-frequency slope */
+    out[0] = (double)th[0];
+    out[1] = (double)(th[1] < th[2] ? th[1] : th[2]);
+    out[2] = (double)(th[1] < th[2] ? th[2] : th[1]);
+    out[3] = (double)sqrtl(sse / used);
+    return E_OK;
+}

@@ -128,6 +128,15 @@ int agn_oracle_lag_stats(const double* x, int64_t n, const int64_t* lags, int32_
                          const double* dm_ref, int32_t n_thr, double lam_cut, double* sf2_out,
                          uint64_t* exceed_out, uint64_t* pairs_out);
 
+/* Fit of Eq. 3 to a binned periodogram (f[b], pbar[b], bins with pbar <= 0
+ * skipped): least squares in log10 P with the break held at f_br, free
+ * (a = log10 A, a_low, a_high), started from a_low0 / a_high0.  Needs >= 3 used
+ * bins with at least one below and one above f_br.  out = {a, a_low, a_high,
+ * rms of the log10 residuals}; the model is symmetric in the two slopes, and
+ * a_low is reported as the smaller. */
+int agn_oracle_psd_fit(const double* f, const double* pbar, int64_t nb, double f_br, double a_low0, double a_high0,
+                       double out[4]);
+
 #ifdef __cplusplus
 }
 #endif
