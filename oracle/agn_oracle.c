@@ -675,19 +675,48 @@ int agn_oracle_psd_fit(const double* f, const double* pbar, int64_t nb, double f
                 for (int k = 0; k < 3; ++k) A[i][k] += J[i] * J[k];
             }
         }
-        /* solve A d = g by Cramer's rule */
-        const long double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
-                                A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
-                                A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
-        if (!(fabsl(det) > 0.0L)) return E_INVAL;
-        long double d[3];
-        for (int c = 0; c < 3; ++c) {
-            long double M[3][3];
-            for (int i = 0; i < 3; ++i)
-                for (int k = 0; k < 3; ++k) M[i][k] = (k == c) ? g[i] : A[i][k];
-            d[c] = (M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
-                    M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
-                    M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0])) / det;
+        /* minimum-norm solution of A d = g: A = V diag(w) V^T by Jacobi
+         * rotations, directions with w below 1e-15 of the largest dropped (with
+         * equal slopes the two slope columns of the Jacobian coincide) */
+        long double V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+        for (int sweep = 0; sweep < 60; ++sweep) {
+            long double off = 0.0L;
+            for (int p = 0; p < 3; ++p)
+                for (int q = p + 1; q < 3; ++q) off += A[p][q] * A[p][q];
+            if (off < 1e-60L) break;
+            for (int p = 0; p < 3; ++p)
+                for (int q = p + 1; q < 3; ++q) {
+                    if (A[p][q] == 0.0L) continue;
+                    const long double tau = (A[q][q] - A[p][p]) / (2.0L * A[p][q]);
+                    const long double t = (tau >= 0.0L ? 1.0L : -1.0L) / (fabsl(tau) + sqrtl(1.0L + tau * tau));
+                    const long double c = 1.0L / sqrtl(1.0L + t * t), sn = t * c;
+                    for (int k = 0; k < 3; ++k) {  /* A <- A J */
+                        const long double akp = A[k][p], akq = A[k][q];
+                        A[k][p] = c * akp - sn * akq;
+                        A[k][q] = sn * akp + c * akq;
+                    }
+                    for (int k = 0; k < 3; ++k) {  /* A <- J^T A */
+                        const long double apk = A[p][k], aqk = A[q][k];
+                        A[p][k] = c * apk - sn * aqk;
+                        A[q][k] = sn * apk + c * aqk;
+                    }
+                    for (int k = 0; k < 3; ++k) {  /* V <- V J */
+                        const long double vkp = V[k][p], vkq = V[k][q];
+                        V[k][p] = c * vkp - sn * vkq;
+                        V[k][q] = sn * vkp + c * vkq;
+                    }
+                }
+        }
+        long double wmax = 0.0L;
+        for (int i = 0; i < 3; ++i)
+            if (A[i][i] > wmax) wmax = A[i][i];
+        if (!(wmax > 0.0L)) return E_INVAL;
+        long double d[3] = {0.0L, 0.0L, 0.0L};
+        for (int i = 0; i < 3; ++i) {
+            if (!(A[i][i] > 1e-15L * wmax)) continue;
+            long double vg = 0.0L;
+            for (int k = 0; k < 3; ++k) vg += V[k][i] * g[k];
+            for (int k = 0; k < 3; ++k) d[k] += V[k][i] * vg / A[i][i];
         }
         long double step = 1.0L, nt[3], nsse = 0.0L;
         for (int h = 0; h < 60; ++h) {

@@ -91,3 +91,25 @@ def test_fit_rejects_bad_input():
         oracle.psd_fit(f[:2], y[:2], 2e-3)   # fewer than 3 bins
     with pytest.raises(oracle.OracleError):
         oracle.psd_fit(f, y, -1.0)
+
+
+def test_fit_single_power_law_reaches_the_minimum():
+    """Noisy data from one power law (equal slopes): there the two slope
+    columns of the Jacobian coincide; the fit still reaches the least-squares
+    minimum found by scipy from several starts (rms to 1e-9, log10 A and the
+    mean slope to 1e-6)."""
+    rng = np.random.default_rng(11)
+    n, fb = 2 ** 14, 1 / 300.0
+    fm, _ = oracle.log_binned_mean_f(np.ones(n // 2 + 1), n, 1.0, 0.1)
+    y = eq3_log(fm, 0.5, fb, 1.6, 1.6) + rng.normal(0, 0.15, len(fm))
+    p = oracle.psd_fit(fm, 10 ** y, fb, 1.0, 2.0)
+    best = None
+    for x0 in ([0.0, 1.0, 2.0], [0.0, 1.6, 1.6001], [0.0, 0.5, 3.0]):
+        res = optimize.least_squares(lambda t: eq3_log(fm, t[0], fb, t[1], t[2]) - y, x0,
+                                     xtol=1e-15, ftol=1e-15, gtol=1e-15)
+        r = np.sqrt(np.mean(res.fun ** 2))
+        if best is None or r < best[0]:
+            best = (r, res.x)
+    assert p[3] == pytest.approx(best[0], rel=1e-9)
+    assert p[0] == pytest.approx(best[1][0], abs=1e-6)
+    assert 0.5 * (p[1] + p[2]) == pytest.approx(0.5 * (best[1][1] + best[1][2]), abs=1e-6)
