@@ -329,6 +329,26 @@ int agn_test_philox(uint64_t key0, uint64_t key1, uint64_t ctr0, int64_t n_block
                     uint64_t* out, void* stream);
 
 /*
+ * agn_psd_fit_batch -- the convergence test of Sec. 3.2.2: Eq. 3 fitted to
+ * each curve's log-binned periodogram, as written by agn_periodogram_batch
+ * with the same dex (bins_out at b_offset[c], agn_log_bin_count(n[c], dex)
+ * bins).  Least squares in log10 P over the bins with a positive mean; each
+ * bin sits at the mean frequency of the f_j = j / (n dt) it holds; the break
+ * is held at p[c].f_br and (log10 A, a_low, a_high) are free, started from
+ * p[c].a_low / p[c].a_high (Levenberg-Marquardt, FP64).
+ *   fit_out[4 c + {0,1,2,3}] = log10 A, a_low, a_high, rms of the log10
+ *   residuals; Eq. 3 is symmetric in its slopes, so a_low is the smaller.
+ *   NaN if fewer than 3 bins are positive or none lies on one side of f_br.
+ * n, dt, p, b_offset: host; bins, fit_out: device.  Workspace:
+ * agn_psd_fit_workspace_size.  Errors: AGN_EINVAL / AGN_EUNSUPPORTED_N,
+ * including an f_br outside the binned frequency range (nothing launched).
+ */
+int agn_psd_fit_workspace_size(int32_t n_curves, const int64_t* n, double dex, size_t* bytes);
+int agn_psd_fit_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n, const double* dt, const agn_psd_params* p,
+                      double dex, const int64_t* b_offset, const double* bins, double* fit_out, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/*
  * Lag statistics of the output series (Eq. A6; Sec. 3.2.10; Sec. 4.2,
  * Figs. 16-17), for n_curves positive series at the same n_lags lags
  * (in samples; 1 <= lags[l] < n[c] for every curve):

@@ -98,6 +98,8 @@ def _declare(lib):
     lib.agn_pdf_draw.argtypes = [vp, C.POINTER(agn_pdf_params), i64, u64, u32, vp, vp]
     lib.agn_lag_stats_workspace_size.argtypes = [i32, vp, i32, vp, i32, i32, C.POINTER(sz)]
     lib.agn_lag_stats_batch.argtypes = [vp, i32, vp, vp, vp, i32, vp, i32, vp, vp, i32, vp, d, vp, vp, vp, sz, vp]
+    lib.agn_psd_fit_workspace_size.argtypes = [i32, vp, d, C.POINTER(sz)]
+    lib.agn_psd_fit_batch.argtypes = [vp, i32, vp, vp, vp, d, vp, vp, vp, vp, sz, vp]
     lib.agn_batch_plan_create.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_int, vp, vp, vp,
                                           C.c_int, C.c_int, vp, sz, vp, C.POINTER(vp)]
     lib.agn_batch_plan_launch.argtypes = [vp, vp]
@@ -116,7 +118,7 @@ def _declare(lib):
               "agn_ctx_set_profiling", "agn_ctx_kernel_time", "agn_erdf_draw", "agn_pdf_draw", "agn_batch_plan_create",
               "agn_batch_plan_launch", "agn_batch_plan_info", "agn_batch_plan_destroy", "agn_log_bin_count",
               "agn_periodogram_workspace_size", "agn_periodogram_batch", "agn_lag_stats_workspace_size",
-              "agn_lag_stats_batch"):
+              "agn_lag_stats_batch", "agn_psd_fit_workspace_size", "agn_psd_fit_batch"):
         getattr(lib, f).restype = C.c_int
 
 
@@ -346,6 +348,26 @@ def agn_periodogram_batch(ctx: Context, n, offset, x, p_offset, P_out, dex=0.0, 
 
 
 AGN_SF_LINEAR, AGN_SF_MAGNITUDE = 0, 1
+
+
+def agn_psd_fit_workspace_size(n, dex) -> int:
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    b = C.c_size_t()
+    _check(lib().agn_psd_fit_workspace_size(len(n), n.ctypes.data_as(C.c_void_p), float(dex), C.byref(b)))
+    return b.value
+
+
+def agn_psd_fit_batch(ctx: Context, n, dt, params, dex, b_offset, bins, fit_out, ws=None, stream=None):
+    """n, dt, params, b_offset: host sequences; bins, fit_out (n_curves x 4 float64), ws: GPU tensors."""
+    vp = C.c_void_p
+    nc = len(n)
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    bo = np.ascontiguousarray(b_offset, dtype=np.int64)
+    parr = (agn_psd_params * max(nc, 1))(*params)
+    _check(lib().agn_psd_fit_batch(ctx.handle, nc, n.ctypes.data_as(vp), dt.ctypes.data_as(vp), parr, float(dex),
+                                   bo.ctypes.data_as(vp), _ptr(bins), _ptr(fit_out), _ptr(ws),
+                                   0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, ctx.device)))
 
 
 def agn_lag_stats_workspace_size(n, lags, n_thr=0, units=AGN_SF_LINEAR):

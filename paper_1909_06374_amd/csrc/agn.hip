@@ -194,7 +194,7 @@ struct agn_ctx {
 
 static const char* KERNEL_NAMES =
     "spectrum_partial,spectrum_norm,spectrum_amp,lds_prep,lds_iterate,big_prep,fft_pass,fold,"
-    "sort_hist,sort_scan,sort_scatter,delta,big_output,erdf_draw,batch_graph,periodogram,log_bins,lag_stats";
+    "sort_hist,sort_scan,sort_scatter,delta,big_output,erdf_draw,batch_graph,periodogram,log_bins,lag_stats,psd_fit";
 
 // Kernel timing: events recorded on the launch stream around each launch.
 struct ProfScope {
@@ -1516,6 +1516,90 @@ extern "C" int agn_periodogram_batch(agn_ctx* ctx, int32_t n_curves, const int64
         hipLaunchKernelGGL(k_log_bins, dim3((unsigned)maxbins, (unsigned)nc), dim3(256), 0, st, d_bd);
         HIPCHK(hipGetLastError());
     }
+    return AGN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// fit of Eq. 3 to log-binned periodograms (convergence test)
+// ---------------------------------------------------------------------------
+static size_t fit_layout(int32_t nc, const int64_t* n, double dex, EdgeCache* ec, std::vector<size_t>* f_off) {
+    size_t off = align256(sizeof(FitDesc) * (size_t)nc);
+    f_off->assign((size_t)nc, 0);
+    for (int32_t c = 0; c < nc; ++c) {
+        (*f_off)[c] = off;
+        off += align256(sizeof(double) * (ec->get(n[c]).size() / 2));
+    }
+    return off;
+}
+
+extern "C" int agn_psd_fit_workspace_size(int32_t n_curves, const int64_t* n, double dex, size_t* bytes) {
+    if (!bytes || (n_curves > 0 && !n)) return fail(AGN_EINVAL, "NULL argument");
+    if (n_curves < 0) return fail(AGN_EINVAL, "n_curves < 0");
+    if (!(dex > 0.0) || !std::isfinite(dex)) return fail(AGN_EINVAL, "dex must be finite and > 0");
+    for (int32_t c = 0; c < n_curves; ++c)
+        if (!n_supported(n[c]) || n[c] < 4)
+            return fail(AGN_EUNSUPPORTED_N, "n=%lld is not 2^a or 3*2^a in [4, 2^27]", (long long)n[c]);
+    EdgeCache ec;
+    ec.dex = dex;
+    std::vector<size_t> f_off;
+    *bytes = fit_layout(n_curves, n, dex, &ec, &f_off);
+    return AGN_OK;
+}
+
+extern "C" int agn_psd_fit_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n, const double* dt,
+                                 const agn_psd_params* p, double dex, const int64_t* b_offset, const double* bins,
+                                 double* fit_out, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx) return fail(AGN_EINVAL, "ctx is NULL");
+    if (n_curves < 0) return fail(AGN_EINVAL, "n_curves < 0");
+    if (n_curves == 0) return AGN_OK;
+    if (!n || !dt || !p || !b_offset || !bins || !fit_out) return fail(AGN_EINVAL, "NULL argument");
+    size_t need = 0;
+    int rc = agn_psd_fit_workspace_size(n_curves, n, dex, &need);
+    if (rc) return rc;
+    if (!ws || ws_bytes < need)
+        return fail(AGN_EINVAL, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+    EdgeCache ec;
+    ec.dex = dex;
+    std::vector<size_t> f_off;
+    fit_layout(n_curves, n, dex, &ec, &f_off);
+    std::vector<unsigned char> hdr(need, 0);
+    FitDesc* fd = (FitDesc*)hdr.data();
+    unsigned char* base = (unsigned char*)ws;
+    for (int32_t c = 0; c < n_curves; ++c) {
+        if (!(dt[c] > 0.0) || !std::isfinite(dt[c])) return fail(AGN_EINVAL, "dt[%d] must be finite and > 0", c);
+        if (!(p[c].f_br > 0.0) || !std::isfinite(p[c].f_br) || !std::isfinite(p[c].a_low) ||
+            !std::isfinite(p[c].a_high))
+            return fail(AGN_EINVAL, "invalid PSD parameters for curve %d", c);
+        if (b_offset[c] < 0) return fail(AGN_EINVAL, "b_offset[%d] < 0", c);
+        const std::vector<int64_t>& e = ec.get(n[c]);
+        const int nb = (int)(e.size() / 2);
+        double* fc = (double*)(hdr.data() + f_off[c]);
+        int below = 0, above = 0;
+        for (int b = 0; b < nb; ++b) {
+            // mean of f_j = j / (n dt) over the bin's j in [lo, hi)
+            fc[b] = 0.5 * (double)(e[2 * b] + e[2 * b + 1] - 1) / ((double)n[c] * dt[c]);
+            below += fc[b] < p[c].f_br;
+            above += fc[b] > p[c].f_br;
+        }
+        if (below < 1 || above < 1)
+            return fail(AGN_EINVAL, "curve %d: f_br must lie inside the binned frequency range", c);
+        fd[c].f = (const double*)(base + f_off[c]);
+        fd[c].pbar = bins + b_offset[c];
+        fd[c].out = fit_out + 4 * (int64_t)c;
+        fd[c].f_br = p[c].f_br;
+        fd[c].a_low0 = p[c].a_low;
+        fd[c].a_high0 = p[c].a_high;
+        fd[c].nb = nb;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(ctx->device));
+    if ((rc = stage_upload(ctx, ws, hdr.data(), hdr.size(), st))) return rc;
+    {
+        ProfScope ps(ctx, "psd_fit", st);
+        hipLaunchKernelGGL(k_psd_fit, dim3((unsigned)((n_curves + 63) / 64)), dim3(64), 0, st, (const FitDesc*)ws,
+                           n_curves);
+    }
+    HIPCHK(hipGetLastError());
     return AGN_OK;
 }
 

@@ -306,4 +306,133 @@ __global__ __launch_bounds__(256) void k_lag_rep(const double* __restrict__ sf2,
     rep[l] = acc / (double)n_curves;
 }
 
+// ---------------------------------------------------------------------------
+// Fit of Eq. 3 to each curve's log-binned periodogram (the convergence test
+// of Sec. 3.2.2): least squares in log10 P, the break held at the input f_br,
+// (a = log10 A, a_low, a_high) free; Levenberg-Marquardt from the input
+// slopes, one thread per curve (a few dozen bins each).
+// ---------------------------------------------------------------------------
+struct FitDesc {
+    const double* f;     // bin frequencies (mean f_j of the bin)
+    const double* pbar;  // bin means of the periodogram
+    double* out;         // {a, a_low, a_high, rms}
+    double f_br, a_low0, a_high0;
+    int32_t nb;
+    int32_t pad_;
+};
+
+struct FitEval {
+    double sse;
+    double A[3][3];
+    double g[3];
+};
+
+AGN_DEV void fit_eval(const FitDesc& d, const double th[3], bool jac, FitEval* e) {
+    const double inv_ln10 = 0.43429448190325182765;
+    e->sse = 0.0;
+    if (jac)
+        for (int i = 0; i < 3; ++i) {
+            e->g[i] = 0.0;
+            for (int k = 0; k < 3; ++k) e->A[i][k] = 0.0;
+        }
+    for (int b = 0; b < d.nb; ++b) {
+        const double pb = d.pbar[b];
+        if (!(pb > 0.0)) continue;
+        const double lu = log(d.f[b] / d.f_br);
+        const double tl = exp(th[1] * lu), tH = exp(th[2] * lu), S = tl + tH;
+        const double r = log10(pb) - (th[0] - log10(S));
+        e->sse += r * r;
+        if (jac) {
+            const double L = lu * inv_ln10;
+            const double J[3] = {1.0, -tl / S * L, -tH / S * L};
+            for (int i = 0; i < 3; ++i) {
+                e->g[i] += J[i] * r;
+                for (int k = 0; k < 3; ++k) e->A[i][k] += J[i] * J[k];
+            }
+        }
+    }
+}
+
+// Solves the symmetric positive definite 3x3 system M x = y by Cholesky.
+AGN_DEV bool chol3(const double M[3][3], const double y[3], double x[3]) {
+    const double l00 = M[0][0];
+    if (!(l00 > 0.0)) return false;
+    const double L00 = sqrt(l00), L10 = M[1][0] / L00, L20 = M[2][0] / L00;
+    const double l11 = M[1][1] - L10 * L10;
+    if (!(l11 > 0.0)) return false;
+    const double L11 = sqrt(l11), L21 = (M[2][1] - L20 * L10) / L11;
+    const double l22 = M[2][2] - L20 * L20 - L21 * L21;
+    if (!(l22 > 0.0)) return false;
+    const double L22 = sqrt(l22);
+    const double z0 = y[0] / L00, z1 = (y[1] - L10 * z0) / L11, z2 = (y[2] - L20 * z0 - L21 * z1) / L22;
+    x[2] = z2 / L22;
+    x[1] = (z1 - L21 * x[2]) / L11;
+    x[0] = (z0 - L10 * x[1] - L20 * x[2]) / L00;
+    return true;
+}
+
+__global__ __launch_bounds__(64) void k_psd_fit(const FitDesc* __restrict__ descs, int32_t n_curves) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_curves) return;
+    const FitDesc d = descs[c];
+    int used = 0, below = 0, above = 0;
+    for (int b = 0; b < d.nb; ++b)
+        if (d.pbar[b] > 0.0) {
+            ++used;
+            below += d.f[b] < d.f_br;
+            above += d.f[b] > d.f_br;
+        }
+    const double nan = __builtin_nan("");
+    if (used < 3 || below < 1 || above < 1) {
+        for (int i = 0; i < 4; ++i) d.out[i] = nan;
+        return;
+    }
+    double th[3] = {0.0, d.a_low0, d.a_high0};
+    {
+        double s = 0.0;
+        for (int b = 0; b < d.nb; ++b) {
+            if (!(d.pbar[b] > 0.0)) continue;
+            const double lu = log(d.f[b] / d.f_br);
+            s += log10(d.pbar[b]) + log10(exp(th[1] * lu) + exp(th[2] * lu));
+        }
+        th[0] = s / used;
+    }
+    FitEval e;
+    fit_eval(d, th, true, &e);
+    double lambda = 1e-3;
+    for (int it = 0; it < 200; ++it) {
+        bool moved = false;
+        double rel = 0.0;
+        while (lambda < 1e16) {
+            double M[3][3], dx[3];
+            for (int i = 0; i < 3; ++i)
+                for (int k = 0; k < 3; ++k) M[i][k] = e.A[i][k] + (i == k ? lambda * e.A[i][i] : 0.0);
+            if (chol3(M, e.g, dx)) {
+                const double tn[3] = {th[0] + dx[0], th[1] + dx[1], th[2] + dx[2]};
+                FitEval en;
+                fit_eval(d, tn, false, &en);
+                if (en.sse < e.sse) {
+                    rel = 0.0;
+                    for (int i = 0; i < 3; ++i) {
+                        rel = fmax(rel, fabs(dx[i]) / (1.0 + fabs(th[i])));
+                        th[i] = tn[i];
+                    }
+                    lambda = fmax(lambda / 3.0, 1e-15);
+                    moved = true;
+                    break;
+                }
+            }
+            lambda *= 4.0;
+        }
+        if (!moved) break;  // no descent at any damping: at the minimum
+        fit_eval(d, th, true, &e);
+        if (rel < 1e-15) break;
+    }
+    // Eq. 3 is symmetric in its two slopes; the smaller one is the low-frequency slope
+    d.out[0] = th[0];
+    d.out[1] = fmin(th[1], th[2]);
+    d.out[2] = fmax(th[1], th[2]);
+    d.out[3] = sqrt(e.sse / used);
+}
+
 }  // namespace agn
