@@ -127,3 +127,29 @@ def test_fit_degenerate_and_errors(gpu_ctx):
                             ws[:8])
     with pytest.raises(m.AgnError):
         m.agn_psd_fit_workspace_size([1000], dex)
+
+
+def test_segmented_run_equals_one_run(gpu_ctx):
+    """The convergence workload iterates in segments, restarting the batch
+    generator from the previous output (a permutation of the same draw, with
+    the same seeds, hence the same sorted values and spectrum).  In FP64 that
+    equals one uninterrupted run bit for bit, on both paths (LDS and multi-pass)."""
+    m = agn()
+    ns = [4096, 2 ** 16]
+    offs = [0, 4096]
+    tot = sum(ns)
+    params = [m.psd_params(0.0, 1 / 300.0, 1.6, 1.6), m.psd_params(0.0, 1 / 1000.0, 1.0, 2.0)]
+    erdf = np.concatenate([oracle.erdf_bpl(oracle.erdf_params(), n, 9, c) for c, n in enumerate(ns)])
+    e = torch.as_tensor(erdf).to("cuda:0")
+    ws = torch.empty(m.agn_batch_workspace_size(ns, m.AGN_FP64), dtype=torch.uint8, device="cuda:0")
+    one = torch.empty(tot, dtype=torch.float64, device="cuda:0")
+    m.agn_lc_generate_batch(gpu_ctx, ns, offs, params, [1.0, 1.0], [12, 12], [5, 6], [0, 1], e, -1.0, m.AGN_FP64,
+                            one, None, None, ws)
+    a = torch.empty(tot, dtype=torch.float64, device="cuda:0")
+    b = torch.empty(tot, dtype=torch.float64, device="cuda:0")
+    m.agn_lc_generate_batch(gpu_ctx, ns, offs, params, [1.0, 1.0], [5, 5], [5, 6], [0, 1], e, -1.0, m.AGN_FP64,
+                            a, None, None, ws)
+    m.agn_lc_generate_batch(gpu_ctx, ns, offs, params, [1.0, 1.0], [7, 7], [5, 6], [0, 1], a, -1.0, m.AGN_FP64,
+                            b, None, None, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(one, b)
