@@ -599,7 +599,7 @@ static void launch_sort_pass(agn_ctx* ctx, const BigCurve* d, int nc, int64_t nt
     }
     {
         ProfScope ps(ctx, "sort_scatter", st);
-        hipLaunchKernelGGL((k_sort_scatter<K>), gt, dim3(SCAT_THREADS), 0, st, d, P, ntiles);
+        hipLaunchKernelGGL((k_sort_scatter<K>), gt, dim3(BIG_TILE / scat_ipt<K>::value), 0, st, d, P, ntiles);
     }
 }
 

@@ -32,9 +32,13 @@ namespace agn {
 constexpr int BIG_TILE = 8192;       // sort / delta tile
 constexpr int BIG_THREADS = 256;     // block of the streaming kernels (BIG_IPT elements each)
 constexpr int BIG_IPT = BIG_TILE / BIG_THREADS;
-constexpr int SCAT_THREADS = 512;    // block of the scatter kernel (SCAT_IPT keys each)
-constexpr int SCAT_IPT = BIG_TILE / SCAT_THREADS;
-constexpr int SCAT_WAVES = SCAT_THREADS / 64;
+// Keys per thread of the scatter kernel: 16 for 32-bit keys (512 threads per
+// tile), 8 for 64-bit keys (1024 threads: the tile's staging fills most of the
+// LDS, so one workgroup per CU; more threads keep more loads in flight).
+template <typename K>
+struct scat_ipt {
+    static constexpr int value = sizeof(K) == 4 ? 16 : 8;
+};
 constexpr int FFT_COLS_MIN = 16;     // fewest butterflies per FFT workgroup
 constexpr int FFT_COLS_MAX = 64;     // most butterflies per FFT workgroup
 constexpr int TW_LO_BITS = 12;       // two-level twiddle split
@@ -418,15 +422,18 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sort_scan_digits(const BigCurve
     d.dstart[tid] = wpre + inc - v;
 }
 
-// grid: (ntiles, curves), block SCAT_THREADS.  Stable scatter of one 8-bit
-// digit.  Each wave ranks its 64 x SCAT_IPT keys with ballots and per-wave
+// grid: (ntiles, curves), block BIG_TILE / scat_ipt<K>.  Stable scatter of
+// one 8-bit digit.  Each wave ranks its 64 x SCAT_IPT keys with ballots and per-wave
 // running digit counters; the tile is then rearranged in LDS into digit order,
 // and thread q takes tile positions q, q + SCAT_THREADS, ... so that
 // consecutive threads write consecutive global positions inside each digit's
 // run (8192-key tiles: runs of 32 keys on average).
 template <typename K>
-__global__ __launch_bounds__(SCAT_THREADS) void k_sort_scatter(const BigCurve* __restrict__ cv, SortPass P,
-                                                               int64_t ntiles) {
+__global__ __launch_bounds__(BIG_TILE / scat_ipt<K>::value) void k_sort_scatter(const BigCurve* __restrict__ cv,
+                                                                                SortPass P, int64_t ntiles) {
+    constexpr int SCAT_IPT = scat_ipt<K>::value;
+    constexpr int SCAT_THREADS = BIG_TILE / SCAT_IPT;
+    constexpr int SCAT_WAVES = SCAT_THREADS / 64;
     __shared__ uint16_t wcnt[SCAT_WAVES][256];  // per-wave running digit counters (<= 64 * SCAT_IPT)
     __shared__ uint16_t wpre[SCAT_WAVES][256];  // exclusive prefix over waves
     __shared__ uint32_t tstart[256];            // digit start inside the tile
@@ -435,6 +442,7 @@ __global__ __launch_bounds__(SCAT_THREADS) void k_sort_scatter(const BigCurve* _
     __shared__ K skey[BIG_TILE];
     __shared__ uint32_t sval[BIG_TILE];
     static_assert(64 * SCAT_IPT * (SCAT_WAVES - 1) < 65536, "wave prefix must fit 16 bits");
+    static_assert(SCAT_THREADS >= 256 && SCAT_WAVES >= 4, "the digit phase takes the first 256 threads");
     const BigCurve& d = cv[blockIdx.y];
     if (d.state[1] == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
