@@ -213,13 +213,59 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
             K key[IPT];
             uint32_t idx2[IPT / 2];
             const int tk = opaque(tid);
+            if constexpr (sizeof(T) == 4) {
+                // FP32 form: keys are y mapped in FP64 onto 2^30 levels over
+                // [min y, max y].  The map is monotone, so order is kept; its
+                // step, range * 2^-30, lies far below the FP32 round-off of the
+                // transforms, and 30-bit keys take 6 radix passes instead of 7.
+                float y[IPT];
+                float mn = Zf[rpad<T>(tk * IPT)], mx = mn;
 #pragma unroll
-            for (int i = 0; i < IPT; ++i) key[i] = ord_key(Zf[rpad<T>(tk * IPT + i)]);
+                for (int i = 0; i < IPT; ++i) {
+                    y[i] = Zf[rpad<T>(tk * IPT + i)];
+                    mn = fminf(mn, y[i]);
+                    mx = fmaxf(mx, y[i]);
+                }
+                // block min / max (the block is a power of two: one partial
+                // wave, or whole waves)
+                float* fs = (float*)scratch;  // free until the sort below (barrier before it)
+                if (nt < 64) {
+                    fs[tid] = mn;
+                    fs[32 + tid] = mx;
+                    __syncthreads();
+                    for (int w = 0; w < nt; ++w) {
+                        mn = fminf(mn, fs[w]);
+                        mx = fmaxf(mx, fs[32 + w]);
+                    }
+                } else {
+#pragma unroll
+                    for (int o = 32; o >= 1; o >>= 1) {
+                        mn = fminf(mn, __shfl_xor(mn, o, 64));
+                        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+                    }
+                    if ((tid & 63) == 0) {
+                        fs[tid >> 6] = mn;
+                        fs[32 + (tid >> 6)] = mx;
+                    }
+                    __syncthreads();
+                    for (int w = 0; w < (nt >> 6); ++w) {
+                        mn = fminf(mn, fs[w]);
+                        mx = fmaxf(mx, fs[32 + w]);
+                    }
+                }
+                const double lo = (double)mn, rng = (double)mx - lo;
+                const double sc = rng > 0.0 ? 1073741823.0 / rng : 0.0;
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) key[i] = (K)fmin(((double)y[i] - lo) * sc, 1073741823.0);
+            } else {
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) key[i] = ord_key(Zf[rpad<T>(tk * IPT + i)]);
+            }
 #pragma unroll
             for (int j = 0; j < IPT / 2; ++j)
                 idx2[j] = (uint32_t)(tk * IPT + 2 * j) | ((uint32_t)(tk * IPT + 2 * j + 1) << 16);
             __syncthreads();
-            block_radix_sort<K, IPT, true>(key, idx2, smem, ibuf, scratch);
+            block_radix_sort<K, IPT, true, sizeof(T) == 4 ? 30 : 8 * (int)sizeof(K)>(key, idx2, smem, ibuf, scratch);
         }
 
         // x_i[t] = s[k]; Eq. 4 terms from the log10 table.  The exact

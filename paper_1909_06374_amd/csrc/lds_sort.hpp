@@ -97,12 +97,13 @@ __host__ __device__ inline size_t sort_ibuf_bytes(int n) {
 // when IPT divides the pad period, the read-back addresses of a thread's
 // IPT keys and IPT/2 index words are a per-thread base plus i (or j).  The
 // addresses are the same as the padded formulas, with fewer instructions.
-template <typename K, int IPT, bool SEP, bool ALIGNED>
+template <typename K, int IPT, bool SEP, bool ALIGNED, int KBITS>
 AGN_DEV void block_radix_sort_impl(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned char* work,
                                    uint16_t* ibuf, uint32_t* scratch) {
     static_assert(IPT % 2 == 0, "IPT must be even");
+    static_assert(KBITS >= 1 && KBITS <= 8 * (int)sizeof(K), "key bits out of range");
     const int T = blockDim.x;
-    constexpr int NPASS = (int)((8 * sizeof(K) + SORT_RB - 1) / SORT_RB);
+    constexpr int NPASS = (KBITS + SORT_RB - 1) / SORT_RB;
     constexpr int KPER = sizeof(K) == 4 ? 32 : 16;  // key pad period
     constexpr bool KFAST = (KPER % IPT) == 0;
     constexpr bool IFAST = (32 % (IPT / 2)) == 0;
@@ -208,18 +209,19 @@ AGN_DEV void block_radix_sort_impl(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], uns
 
 // IPT 16 is used only with 1024-thread blocks (the host checks that the
 // block size is a multiple of 32 for it), so only the aligned form is built.
-template <typename K, int IPT, bool SEP>
+// Keys use their low KBITS bits (all others must be zero).
+template <typename K, int IPT, bool SEP, int KBITS = 8 * (int)sizeof(K)>
 AGN_DEV void block_radix_sort(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned char* work,
                               uint16_t* ibuf, uint32_t* scratch) {
     if constexpr (IPT >= 16) {
-        block_radix_sort_impl<K, IPT, SEP, true>(key, idx2, work, ibuf, scratch);
+        block_radix_sort_impl<K, IPT, SEP, true, KBITS>(key, idx2, work, ibuf, scratch);
     } else if constexpr (sizeof(K) == 8) {
         // 64-bit keys (one-time draw sort, FP64 path): one general form keeps
         // register pressure low
-        block_radix_sort_impl<K, IPT, SEP, false>(key, idx2, work, ibuf, scratch);
+        block_radix_sort_impl<K, IPT, SEP, false, KBITS>(key, idx2, work, ibuf, scratch);
     } else {
-        if ((blockDim.x & 31) == 0) block_radix_sort_impl<K, IPT, SEP, true>(key, idx2, work, ibuf, scratch);
-        else block_radix_sort_impl<K, IPT, SEP, false>(key, idx2, work, ibuf, scratch);
+        if ((blockDim.x & 31) == 0) block_radix_sort_impl<K, IPT, SEP, true, KBITS>(key, idx2, work, ibuf, scratch);
+        else block_radix_sort_impl<K, IPT, SEP, false, KBITS>(key, idx2, work, ibuf, scratch);
     }
 }
 
