@@ -46,10 +46,20 @@ def recorded_traffic(workload, kernel):
     recorded in profiles/traffic.txt (FETCH_SIZE and WRITE_SIZE per dispatch,
     scaled by the copy calibration), or None if none is recorded or the HIP
     sources changed since the counters were taken."""
+    kv, rows, _ = read_counters()
+    if kv.get("sources") != source_hash() or (workload, kernel) not in rows:
+        return None
+    f, w = rows[(workload, kernel)]
+    return (f * float(kv["fetch_scale"]) + w * float(kv["write_scale"])) * 1024.0
+
+
+def read_counters():
+    """profiles/traffic.txt as (settings, {(workload, kernel): (fetch KiB, write KiB)},
+    {(workload, kernel): VALU instructions per launch})."""
+    kv, rows, valu = {}, {}, {}
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
-        return None
-    kv, rows = {}, {}
+        return kv, rows, valu
     for line in open(path):
         line = line.split("#", 1)[0].strip()
         if not line:
@@ -57,12 +67,21 @@ def recorded_traffic(workload, kernel):
         parts = line.split()
         if len(parts) == 3 and parts[1] == "=":
             kv[parts[0]] = parts[2]
+        elif len(parts) == 4 and parts[2] == "valu_insts":
+            valu[(parts[0], parts[1])] = float(parts[3])
         elif len(parts) == 4:
             rows[(parts[0], parts[1])] = (float(parts[2]), float(parts[3]))
-    if kv.get("sources") != source_hash() or (workload, kernel) not in rows:
+    return kv, rows, valu
+
+
+def recorded_valu(workload, kernel):
+    """VALU (wave64) instructions per launch of `kernel` from the rocprofv3
+    SQ_INSTS_VALU run recorded in profiles/traffic.txt, or None if none is
+    recorded or the HIP sources changed since."""
+    kv, _, valu = read_counters()
+    if kv.get("sources") != source_hash():
         return None
-    f, w = rows[(workload, kernel)]
-    return (f * float(kv["fetch_scale"]) + w * float(kv["write_scale"])) * 1024.0
+    return valu.get((workload, kernel))
 
 
 def lds_flops_per_sample_iter(n):
@@ -132,10 +151,18 @@ def main():
         import torch
         a = torch.empty(2**30, dtype=torch.uint8, device="cuda:0")
         b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
+        b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_per_launch": 2**30, "launches": 5}))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(4):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 4
+        print(json.dumps({"copy_bytes_per_launch": 2**30, "launches": 5, "copy_ms": ms,
+                          "copy_read_plus_write_gbs": 2 * 2**30 / (ms / 1000.0) / 1e9}))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the generator shards "
@@ -251,6 +278,13 @@ def main():
                 "flops_per_sample_iter": fl, "avg_launch_ms": round(dom_ms, 4),
                 "lds_view": {"achieved_gbs": round(lds_gbs, 1), "peak_gbs": round(LDS_PEAK_GBS, 1),
                              "frac": round(lds_gbs / LDS_PEAK_GBS, 4), "bytes_per_sample_iter": per}}
+        vi = recorded_valu(args.workload, dom)
+        if vi is not None:
+            # issue view: a wave64 VALU instruction holds a 16-lane SIMD for 4
+            # cycles; 1024 SIMDs at 2.4 GHz
+            cap = 1024 * 2.4e9 * (dom_ms / 1000.0) / 4.0
+            roof["valu_issue_view"] = {"insts_per_launch": vi, "frac": round(vi / cap, 4),
+                                       "source": "rocprofv3 SQ_INSTS_VALU, profiles/ptf_batch.md"}
     else:
         per = hbm_bytes_per_sample(dom, pb)
         achieved = per * samples / (dom_ms / 1000.0) / 1e9
