@@ -675,7 +675,7 @@ def run_observables(args, agn, synth, np, torch):
     }
     if not args.no_cpu_baseline:
         import oracle
-        k = 2
+        k = 384  # about 10 s of single-threaded oracle work
         xh = x[:k * n].cpu().numpy()
         t = time.perf_counter()
         for c in range(k):
