@@ -91,6 +91,10 @@ def _load():
     lib.agn_oracle_lag_stats.restype = C.c_int
     lib.agn_oracle_psd_fit.argtypes = [pd, pd, i64, d, d, d, pd]
     lib.agn_oracle_psd_fit.restype = C.c_int
+    lib.agn_oracle_uniform_chain.argtypes = [u64, u32, u32, u64, u64]
+    lib.agn_oracle_uniform_chain.restype = d
+    lib.agn_oracle_pdf_slice.argtypes = [C.POINTER(PdfParams), i64, i32, i32, u64, u32, pd]
+    lib.agn_oracle_pdf_slice.restype = C.c_int
     for name in ("psd_spectrum", "dft", "rfft", "irfft", "replace", "argsort",
                  "iterate", "generate", "periodogram"):
         getattr(lib, "agn_oracle_" + name).restype = C.c_int
@@ -258,6 +262,18 @@ def lag_stats(x, lags, units=0, dm_ref=(), lam_cut=0.0):
                                       _pd(dm) if J else None, J, float(lam_cut), _pd(sf2),
                                       exceed.ctypes.data_as(pu64), pairs.ctypes.data_as(pu64)), "lag_stats")
     return sf2, exceed[:, :J], pairs
+
+
+def uniform_chain(seed, stream, curve, chain, k):
+    return _load().agn_oracle_uniform_chain(int(seed), int(stream), int(curve), int(chain), int(k))
+
+
+def pdf_slice(params: PdfParams, n, n_chains, burn, seed, curve_id=0):
+    """n slice-sampling draws (lambda values), chains interleaved."""
+    out = np.full(n, np.nan, dtype=np.float64)
+    _chk(_load().agn_oracle_pdf_slice(C.byref(params), int(n), int(n_chains), int(burn), int(seed),
+                                      int(curve_id), _pd(out)), "pdf_slice")
+    return out
 
 
 def periodogram(x):

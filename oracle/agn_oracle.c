@@ -743,3 +743,65 @@ int agn_oracle_psd_fit(const double* f, const double* pbar, int64_t nb, double f
     out[3] = (double)sqrtl(sse / used);
     return E_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Slice sampling of the PDF in linear lambda (Sec. 3.1; Neal 2003).          */
+/* ------------------------------------------------------------------------ */
+/* Uniform #k of chain `chain`: counter (k / 4, chain, 0, 0), word k % 4. */
+double agn_oracle_uniform_chain(uint64_t seed, uint32_t stream, uint32_t curve_id, uint64_t chain, uint64_t k)
+{
+    uint64_t key[2] = {seed, ((uint64_t)stream << 32) | (uint64_t)curve_id};
+    uint64_t ctr[4] = {k / 4, chain, 0, 0};
+    uint64_t out[4];
+    agn_oracle_philox4x64(ctr, key, out);
+    return ((double)(out[k % 4] >> 12) + 0.5) * 0x1.0p-52;
+}
+
+/* ln of the density of lambda (per unit lambda), up to a constant. */
+static double slice_log_density(const agn_oracle_pdf_params* p, double lam)
+{
+    const double u = log10(lam), x = u - p->u_star;
+    double l10;  /* log10 of the shape in u */
+    if (p->kind == 0) l10 = -(x < 0.0 ? p->d1 : p->d2) * x;
+    else if (p->kind == 1) l10 = -log10(pow(10.0, p->d1 * x) + pow(10.0, p->d2 * x));
+    else l10 = -x * x / (2.0 * p->sigma * p->sigma) / LN10;
+    /* per dex (measure 0) -> per unit lambda: divide by lambda ln 10 */
+    if (p->measure == 0) l10 -= u;
+    return l10 * LN10;
+}
+
+int agn_oracle_pdf_slice(const agn_oracle_pdf_params* p, int64_t n, int32_t n_chains, int32_t burn,
+                         uint64_t seed, uint32_t curve_id, double* out)
+{
+    if (!p || n < 0 || (n > 0 && !out) || n_chains < 1 || burn < 0) return E_INVAL;
+    if (!(p->u_min < p->u_max) || !isfinite(p->u_min) || !isfinite(p->u_max) || !isfinite(p->u_star))
+        return E_INVAL;
+    if (p->kind < 0 || p->kind > 2 || (p->measure != 0 && p->measure != 1)) return E_INVAL;
+    if (p->kind != 2 && (!isfinite(p->d1) || !isfinite(p->d2))) return E_INVAL;
+    if (p->kind == 2 && !(p->sigma > 0.0 && isfinite(p->sigma))) return E_INVAL;
+    const double lo = pow(10.0, p->u_min), hi = pow(10.0, p->u_max);
+    double start = pow(10.0, p->u_star);
+    if (!(start > lo && start < hi)) start = 0.5 * (lo + hi);
+    for (int64_t c = 0; c < n_chains && c < (n > 0 ? n : 0); ++c) {
+        double lam = start, lf = slice_log_density(p, lam);
+        uint64_t k = 0;
+        for (int64_t step = 0; ; ++step) {
+            const int64_t j = (step - burn) * (int64_t)n_chains + c;  /* output slot */
+            if (step >= burn && j >= n) break;
+            /* the slice: ln f > ln f(lam) + ln U; then shrink [lo, hi] toward lam */
+            const double level = lf + log(agn_oracle_uniform_chain(seed, 6, curve_id, (uint64_t)c, k++));
+            double L = lo, R = hi, next = lam, lnext = lf;
+            for (int t = 0; t < 200; ++t) {
+                const double cand = L + agn_oracle_uniform_chain(seed, 6, curve_id, (uint64_t)c, k++) * (R - L);
+                const double lc = slice_log_density(p, cand);
+                if (lc > level) { next = cand; lnext = lc; break; }
+                if (cand < lam) L = cand;
+                else R = cand;
+            }
+            lam = next;
+            lf = lnext;
+            if (step >= burn) out[j] = lam;
+        }
+    }
+    return E_OK;
+}

@@ -114,6 +114,21 @@ int agn_oracle_pdf_draw(const agn_oracle_pdf_params* p, int64_t n, uint64_t seed
 int agn_oracle_pdf_draw_at(const agn_oracle_pdf_params* p, uint64_t seed, uint32_t curve_id,
                            const int64_t* idx, int64_t m, double* out);
 
+/* Uniform #k of chain `chain` of a stream: Philox counter (k / 4, chain, 0, 0). */
+double agn_oracle_uniform_chain(uint64_t seed, uint32_t stream, uint32_t curve_id, uint64_t chain, uint64_t k);
+
+/* Slice sampling (Sec. 3.1; Neal 2003) of the PDF above in linear lambda on
+ * [10^u_min, 10^u_max], target density per unit lambda (measure 0: the shape
+ * per dex divided by lambda; measure 1: the shape itself).  n_chains chains
+ * start at lambda* (the middle of the support if lambda* lies outside); each
+ * step draws a level ln f(lambda) + ln U, then proposals uniform on the
+ * support interval, shrunk toward the current point after each rejection (at
+ * most 200; the point is kept if none is accepted).  Chain c takes uniforms
+ * #0, 1, ... of Philox stream 6, counter (k / 4, c, 0, 0); after `burn`
+ * steps, its step t fills out[t * n_chains + c]. */
+int agn_oracle_pdf_slice(const agn_oracle_pdf_params* p, int64_t n, int32_t n_chains, int32_t burn,
+                         uint64_t seed, uint32_t curve_id, double* out);
+
 /* Periodogram, Eq. A2: P[j] = 2/n^2 |DFT_j|^2 for j = 0..n/2. */
 int agn_oracle_periodogram(const double* x, int64_t n, double* P);
 
