@@ -278,6 +278,26 @@ int agn_pdf_draw(agn_ctx* ctx, const agn_pdf_params* p, int64_t n, uint64_t seed
                  double* out, void* stream);
 
 /*
+ * agn_pdf_slice -- the PDF draw as the paper makes it (Sec. 3.1): slice
+ * sampling (Neal 2003) in linear lambda of the PDF above, with n_chains
+ * independent chains.  Target density per unit lambda: the shape per dex
+ * divided by lambda (AGN_PDF_PER_LOG) or the shape itself (AGN_PDF_PER_LINEAR).
+ * Each chain starts at lambda* (the middle of the support if lambda* lies
+ * outside it); a step draws the level ln f(lambda) + ln U, then proposals
+ * uniform on [10^u_min, 10^u_max] shrunk toward the current point after each
+ * rejection (at most 200; the point is kept if none is accepted).  Chain c
+ * draws uniforms 0, 1, ... of Philox stream 6 with counter (k / 4, c, 0, 0)
+ * (key (seed, 6 << 32 | curve_id)); after `burn` steps its step t fills
+ * out[t * n_chains + c].  Successive steps of one chain are correlated (over
+ * several decades the lag-one correlation is 0.6-0.8); n_chains = n gives
+ * one draw per chain.
+ *   p: host; out: device, n doubles.  n_chains >= 1, 0 <= burn <= 2^24.
+ * Errors: AGN_EINVAL (nothing launched).  Stream-ordered; no allocation.
+ */
+int agn_pdf_slice(agn_ctx* ctx, const agn_pdf_params* p, int64_t n, int32_t n_chains, int32_t burn, uint64_t seed,
+                  uint32_t curve_id, double* out, void* stream);
+
+/*
  * Observables after the path (App. A).
  *
  * agn_periodogram_batch -- the periodogram of Eq. A2 of n_curves real series

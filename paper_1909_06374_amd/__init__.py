@@ -100,6 +100,7 @@ def _declare(lib):
     lib.agn_lag_stats_batch.argtypes = [vp, i32, vp, vp, vp, i32, vp, i32, vp, vp, i32, vp, d, vp, vp, vp, sz, vp]
     lib.agn_psd_fit_workspace_size.argtypes = [i32, vp, d, C.POINTER(sz)]
     lib.agn_psd_fit_batch.argtypes = [vp, i32, vp, vp, vp, d, vp, vp, vp, vp, sz, vp]
+    lib.agn_pdf_slice.argtypes = [vp, C.POINTER(agn_pdf_params), i64, i32, i32, u64, u32, vp, vp]
     lib.agn_batch_plan_create.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_int, vp, vp, vp,
                                           C.c_int, C.c_int, vp, sz, vp, C.POINTER(vp)]
     lib.agn_batch_plan_launch.argtypes = [vp, vp]
@@ -115,7 +116,7 @@ def _declare(lib):
     for f in ("agn_ctx_create", "agn_ctx_destroy", "agn_supported_n", "agn_spectrum_workspace_size",
               "agn_workspace_size", "agn_batch_workspace_size", "agn_psd_spectrum",
               "agn_lc_iterate", "agn_lc_generate", "agn_lc_generate_batch", "agn_test_philox",
-              "agn_ctx_set_profiling", "agn_ctx_kernel_time", "agn_erdf_draw", "agn_pdf_draw", "agn_batch_plan_create",
+              "agn_ctx_set_profiling", "agn_ctx_kernel_time", "agn_erdf_draw", "agn_pdf_draw", "agn_pdf_slice", "agn_batch_plan_create",
               "agn_batch_plan_launch", "agn_batch_plan_info", "agn_batch_plan_destroy", "agn_log_bin_count",
               "agn_periodogram_workspace_size", "agn_periodogram_batch", "agn_lag_stats_workspace_size",
               "agn_lag_stats_batch", "agn_psd_fit_workspace_size", "agn_psd_fit_batch"):
@@ -403,6 +404,11 @@ def agn_erdf_draw(ctx: Context, params, n, seed, curve_id, out, stream=None):
 def agn_pdf_draw(ctx: Context, params, n, seed, curve_id, out, stream=None):
     _check(lib().agn_pdf_draw(ctx.handle, C.byref(params), int(n), int(seed), int(curve_id), _ptr(out),
                               _stream(stream, ctx.device)))
+
+
+def agn_pdf_slice(ctx: Context, params, n, n_chains, burn, seed, curve_id, out, stream=None):
+    _check(lib().agn_pdf_slice(ctx.handle, C.byref(params), int(n), int(n_chains), int(burn), int(seed),
+                               int(curve_id), _ptr(out), _stream(stream, ctx.device)))
 
 
 def agn_test_philox(key0, key1, ctr0, n_blocks, out, stream=None, device=0):

@@ -1828,6 +1828,43 @@ extern "C" int agn_pdf_draw(agn_ctx* ctx, const agn_pdf_params* p, int64_t n, ui
     return AGN_OK;
 }
 
+extern "C" int agn_pdf_slice(agn_ctx* ctx, const agn_pdf_params* p, int64_t n, int32_t n_chains, int32_t burn,
+                             uint64_t seed, uint32_t curve_id, double* out, void* stream) {
+    if (!ctx || !p || (n > 0 && !out)) return fail(AGN_EINVAL, "NULL argument");
+    if (n < 0) return fail(AGN_EINVAL, "n < 0");
+    if (n_chains < 1) return fail(AGN_EINVAL, "n_chains must be >= 1");
+    if (burn < 0 || burn > (1 << 24)) return fail(AGN_EINVAL, "burn must be in [0, 2^24]");
+    if (p->kind < AGN_PDF_SHARP_BPL || p->kind > AGN_PDF_LOGNORMAL) return fail(AGN_EINVAL, "unknown PDF kind");
+    if (p->measure != AGN_PDF_PER_LOG && p->measure != AGN_PDF_PER_LINEAR) return fail(AGN_EINVAL, "unknown measure");
+    if (!std::isfinite(p->u_min) || !std::isfinite(p->u_max) || !std::isfinite(p->u_star) || !(p->u_min < p->u_max))
+        return fail(AGN_EINVAL, "need finite u_min < u_max and u_star");
+    if (p->kind != AGN_PDF_LOGNORMAL && (!std::isfinite(p->d1) || !std::isfinite(p->d2)))
+        return fail(AGN_EINVAL, "non-finite slopes");
+    if (p->kind == AGN_PDF_LOGNORMAL && !(p->sigma > 0.0 && std::isfinite(p->sigma)))
+        return fail(AGN_EINVAL, "log-normal needs sigma > 0");
+    if (n == 0) return AGN_OK;
+    PdfSlice S;
+    memset(&S, 0, sizeof(S));
+    S.kind = p->kind; S.measure = p->measure;
+    S.u_star = p->u_star; S.d1 = p->d1; S.d2 = p->d2;
+    S.gauss = p->kind == AGN_PDF_LOGNORMAL ? 1.0 / (2.0 * p->sigma * p->sigma * std::log(10.0)) : 0.0;
+    S.lo = std::pow(10.0, p->u_min);
+    S.hi = std::pow(10.0, p->u_max);
+    S.start = std::pow(10.0, p->u_star);
+    if (!(S.start > S.lo && S.start < S.hi)) S.start = 0.5 * (S.lo + S.hi);
+    if (!(S.lo > 0.0) || !std::isfinite(S.hi)) return fail(AGN_EINVAL, "support outside double range");
+    S.n = n; S.n_chains = n_chains; S.burn = burn; S.seed = seed; S.curve_id = curve_id; S.out = out;
+    const int64_t chains = std::min<int64_t>(n_chains, n);
+    HIPCHK(hipSetDevice(ctx->device));
+    {
+        ProfScope ps(ctx, "erdf_draw", (hipStream_t)stream);
+        hipLaunchKernelGGL(k_pdf_slice, dim3((unsigned)((chains + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                           S);
+    }
+    HIPCHK(hipGetLastError());
+    return AGN_OK;
+}
+
 // ---------------------------------------------------------------------------
 // test exports
 // ---------------------------------------------------------------------------

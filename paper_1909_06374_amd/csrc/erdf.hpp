@@ -145,4 +145,70 @@ __global__ __launch_bounds__(PDF_THREADS) void k_pdf_eq1(PdfTable P) {
     }
 }
 
+// Slice sampling (Neal 2003) of the same PDFs in linear lambda, as the paper
+// draws them: the chain state is lambda, the target density per unit lambda
+// is the shape per dex divided by lambda (measure 0) or the shape itself
+// (measure 1).  One thread per chain; each step draws the level
+// ln f(lambda) + ln U, then proposals uniform on [lambda_min, lambda_max],
+// the interval shrunk toward the current point after each rejection (at most
+// SLICE_MAX_SHRINK; the point is kept if none is accepted).  Chain c uses
+// uniforms 0, 1, ... of Philox stream 6 on counter word 1 = c; after `burn`
+// steps its step t writes out[t * n_chains + c] (coalesced over chains).
+// Multiply-adds are not fused here (contract off), so that every proposal
+// and log-density is rounded operation by operation, as in a plain C build.
+constexpr int SLICE_MAX_SHRINK = 200;
+constexpr uint32_t SLICE_STREAM = 6;
+
+struct PdfSlice {
+    int kind, measure;
+    double u_star, d1, d2, gauss;  // gauss = 1 / (2 sigma^2 ln 10)
+    double lo, hi, start;          // support and starting point in lambda
+    int64_t n;
+    int32_t n_chains, burn;
+    uint64_t seed;
+    uint32_t curve_id;
+    double* out;
+};
+
+AGN_DEV double slice_lnf(const PdfSlice& P, double lam) {
+#pragma clang fp contract(off)
+    const double ln10 = 2.30258509299404568402;
+    const double u = log10(lam), x = u - P.u_star;
+    double l10;
+    if (P.kind == 0) l10 = -(x < 0.0 ? P.d1 : P.d2) * x;
+    else if (P.kind == 1) l10 = -log10(pow(10.0, P.d1 * x) + pow(10.0, P.d2 * x));
+    else l10 = -x * x * P.gauss;
+    if (P.measure == 0) l10 -= u;
+    return l10 * ln10;
+}
+
+__global__ __launch_bounds__(256) void k_pdf_slice(PdfSlice P) {
+#pragma clang fp contract(off)
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P.n_chains || c >= P.n) return;
+    double lam = P.start, lf = slice_lnf(P, lam);
+    uint64_t k = 0;
+    for (int64_t step = 0;; ++step) {
+        const int64_t j = (step - P.burn) * (int64_t)P.n_chains + c;
+        if (step >= P.burn && j >= P.n) break;
+        const double level = lf + log(philox_uniform_chain(P.seed, SLICE_STREAM, P.curve_id, (uint64_t)c, k++));
+        double L = P.lo, R = P.hi, next = lam, lnext = lf;
+        for (int t = 0; t < SLICE_MAX_SHRINK; ++t) {
+            const double U = philox_uniform_chain(P.seed, SLICE_STREAM, P.curve_id, (uint64_t)c, k++);
+            const double cand = L + U * (R - L);
+            const double lc = slice_lnf(P, cand);
+            if (lc > level) {
+                next = cand;
+                lnext = lc;
+                break;
+            }
+            if (cand < lam) L = cand;
+            else R = cand;
+        }
+        lam = next;
+        lf = lnext;
+        if (step >= P.burn) P.out[j] = lam;
+    }
+}
+
 }  // namespace agn

@@ -34,4 +34,12 @@ AGN_DEV double philox_uniform(uint64_t seed, uint32_t stream, uint32_t curve, ui
     return ((double)(w >> 12) + 0.5) * 0x1.0p-52;
 }
 
+// Uniform #k of chain `chain` of a stream: counter (k/4, chain, 0, 0), same
+// key and mapping as philox_uniform (which is chain 0).
+AGN_DEV double philox_uniform_chain(uint64_t seed, uint32_t stream, uint32_t curve, uint64_t chain, uint64_t k) {
+    u64x4 o = philox4x64_10(k >> 2, chain, 0, 0, seed, ((uint64_t)stream << 32) | curve);
+    uint64_t w = o.v[k & 3];
+    return ((double)(w >> 12) + 0.5) * 0x1.0p-52;
+}
+
 }  // namespace agn
