@@ -141,7 +141,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ptf_batch",
                     choices=["ptf_batch", "single_curve", "lsst_long", "lsst_long_fp64", "uneven_batch", "serving",
-                             "paper_scale", "observables", "convergence"])
+                             "paper_scale", "observables", "convergence", "pdf_draw"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the FP32-vs-FP64 accuracy report")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -188,6 +188,9 @@ def main():
         return
     if args.workload == "convergence":
         print(json.dumps(run_convergence(args, agn, np, torch)))
+        return
+    if args.workload == "pdf_draw":
+        print(json.dumps(run_pdf_draw(args, agn, np, torch)))
         return
     if args.workload == "ptf_batch":
         n_curves, n, iters, prec = 1024, 2**14, 100, agn.AGN_FP32
@@ -768,6 +771,58 @@ def run_convergence(args, agn, np, torch):
                    "n_curves": nc, "n": n},
         "setups": results,
     }
+
+
+def run_pdf_draw(args, agn, np, torch):
+    """The PDF draw of Sec. 2.1 step (ii) at the long-curve size: 2^26 draws of
+    Table 2's Eq. 1 PDF read as dN/dlambda, by the exact inverse CDF
+    (agn_pdf_draw) and by the paper's slice sampling in linear lambda
+    (agn_pdf_slice on 2^22 draws: 2^18 chains of 16 draws after 200 steps of
+    burn-in; burn-in included in its time)."""
+    dev = "cuda:0"
+    ctx = agn.Context(0)
+    n = 2**26
+    p = agn.pdf_params(agn.AGN_PDF_EQ1, agn.AGN_PDF_PER_LINEAR)
+    out = torch.empty(n, dtype=torch.float64, device=dev)
+    chains, burn, n_slice = 2**18, 200, 2**22
+
+    def timed(f, reps):
+        f()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            f()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms_inv = timed(lambda: agn.agn_pdf_draw(ctx, p, n, 1, 0, out), max(args.steps, 3))
+    ms_slice = timed(lambda: agn.agn_pdf_slice(ctx, p, n_slice, chains, burn, 1, 0, out), 1)
+    gbs = 8.0 * n / (ms_inv / 1000.0) / 1e9
+    res = {
+        "metric": "PDF draws/s (Sec. 2.1 step ii), inverse CDF on the device", "value": n / (ms_inv / 1000.0),
+        "unit": "draws/s", "n_gpus": 1, "steps": max(args.steps, 3), "warmup": 1, "ms_per_step": ms_inv,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "2^26 draws of Table 2's Eq. 1 PDF (lambda* = 0.11, slopes 0.47 / 2.53, "
+                               "log lambda in [-3.75, 0.5]) read as dN/dlambda", "n": n},
+        "roofline": {"bound": "hbm", "kernel": "erdf_draw (k_pdf_eq1)", "achieved": round(gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_draw": 8, "avg_launch_ms": round(ms_inv, 4)},
+        "slice_sampling": {"draws": n_slice, "ms": ms_slice, "draws_per_s": n_slice / (ms_slice / 1000.0),
+                           "chains": chains, "burn": burn, "steps_per_chain": burn + n_slice // chains},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        op = oracle.pdf_params(1, 1)
+        k = 400000
+        t = time.perf_counter()
+        oracle.pdf_draw(op, k, 1, 0)
+        el = time.perf_counter() - t
+        res["cpu_baseline"] = {"value": k / el, "unit": "draws/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{k} inverse-CDF draws of the single-threaded FP64 oracle ({el:.1f} s)"}
+    return res
 
 
 if __name__ == "__main__":

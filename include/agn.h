@@ -250,7 +250,9 @@ int agn_erdf_draw(agn_ctx* ctx, const agn_erdf_params* p, int64_t n, uint64_t se
  * measure AGN_PDF_PER_LOG reads the shape as dN/dlog10(lambda); measure
  * AGN_PDF_PER_LINEAR reads it as dN/dlambda (the paper samples in linear
  * lambda), so that the density in u carries an extra factor 10^x.  Slopes are
- * limited so that the shape spans under 10^260 over the support. */
+ * limited so that the shape spans under 10^260 over the support, and for
+ * Eq. 1 so that (u_max - u_min) |d2 - d1| ln 10 <= 512 (the break spans at
+ * least two cells of the 1024-cell CDF table). */
 enum { AGN_PDF_SHARP_BPL = 0, AGN_PDF_EQ1 = 1, AGN_PDF_LOGNORMAL = 2 };
 enum { AGN_PDF_PER_LOG = 0, AGN_PDF_PER_LINEAR = 1 };
 typedef struct {

@@ -1812,6 +1812,9 @@ extern "C" int agn_pdf_draw(agn_ctx* ctx, const agn_pdf_params* p, int64_t n, ui
         P.n = n; P.seed = seed; P.curve_id = curve_id; P.out = out;
         return launch_pdf_closed(ctx, P, stream);
     }
+    if ((p->u_max - p->u_min) / PDF_CELLS * std::fabs(p->d2 - p->d1) * ln10 > 0.5)
+        return fail(AGN_EINVAL, "Eq. 1 break sharper than two table cells: (u_max - u_min) |d2 - d1| ln 10 must "
+                                "be <= %g", 0.5 * PDF_CELLS);
     PdfTable T{};
     T.u_min = p->u_min; T.u_max = p->u_max; T.u_star = p->u_star;
     T.c1 = (p->d1 - shift) * ln10; T.c2 = (p->d2 - shift) * ln10;

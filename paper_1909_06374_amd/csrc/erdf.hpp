@@ -6,7 +6,7 @@
 //     erfcinv on whichever tail keeps the argument small;
 //   smooth broken power law, Eq. 1: CDF tabulated per block in LDS
 //     (Gauss-Legendre per cell), search over the cells, then Newton inside
-//     the cell on the exact integral.
+//     the cell on the exact integral until the step is below the ulp of u.
 // With the dN/dlambda measure the density in u gains a factor 10^(u - u*):
 // the power-law slopes drop by one and the log-normal mean moves up by
 // sigma^2 ln 10; the host folds that into the parameters below.
@@ -74,13 +74,18 @@ AGN_DEV double eq1_density(const PdfTable& P, double u) {
     return 1.0 / (exp(P.c1 * x) + exp(P.c2 * x));
 }
 
-// Six-point Gauss-Legendre integral of the density over [a, a + w].
+// Eight-point Gauss-Legendre integral of the density over [a, a + w].  The
+// host keeps the break's width at two cells or more (h |c2 - c1| <= 0.5), so
+// the density's complex poles lie over six cell widths from the real axis
+// and the rule is exact to rounding.
 AGN_DEV double eq1_integral(const PdfTable& P, double a, double w) {
     const double c = a + 0.5 * w, hw = 0.5 * w;
-    const double x0 = 0.2386191860831969086, x1 = 0.6612093864662645136, x2 = 0.9324695142031520279;
-    double s = 0.4679139345726910473 * (eq1_density(P, c - hw * x0) + eq1_density(P, c + hw * x0));
-    s += 0.3607615730481386076 * (eq1_density(P, c - hw * x1) + eq1_density(P, c + hw * x1));
-    s += 0.1713244923791703450 * (eq1_density(P, c - hw * x2) + eq1_density(P, c + hw * x2));
+    const double x0 = 0.1834346424956498049, x1 = 0.5255324099163289858, x2 = 0.7966664774136267396,
+                 x3 = 0.9602898564975362317;
+    double s = 0.3626837833783619830 * (eq1_density(P, c - hw * x0) + eq1_density(P, c + hw * x0));
+    s += 0.3137066458778872873 * (eq1_density(P, c - hw * x1) + eq1_density(P, c + hw * x1));
+    s += 0.2223810344533744706 * (eq1_density(P, c - hw * x2) + eq1_density(P, c + hw * x2));
+    s += 0.1012285362903762591 * (eq1_density(P, c - hw * x3) + eq1_density(P, c + hw * x3));
     return s * hw;
 }
 
@@ -135,10 +140,14 @@ __global__ __launch_bounds__(PDF_THREADS) void k_pdf_eq1(PdfTable P) {
         const double f0 = fe[lo], g = (fe[lo + 1] - f0) / P.h;
         double s = 2.0 * r / (f0 + sqrt(fmax(f0 * f0 + 2.0 * g * r, 0.0)));
         s = fmin(fmax(s, 0.0), P.h);
-#pragma unroll
-        for (int it = 0; it < 3; ++it) {
-            s -= (eq1_integral(P, a, s) - r) / eq1_density(P, a + s);
-            s = fmin(fmax(s, 0.0), P.h);
+        // Newton on the exact integral: quadratic convergence from the start
+        // above, to the ulp of u (two or three steps for moderate slopes,
+        // more for cells as wide as the host allows)
+        const double tol = 0x1.0p-52 * (fabs(a) + P.h);
+        for (int it = 0; it < 8; ++it) {
+            const double ds = (eq1_integral(P, a, s) - r) / eq1_density(P, a + s);
+            s = fmin(fmax(s - ds, 0.0), P.h);
+            if (fabs(ds) <= tol) break;
         }
         const double u = fmin(fmax(a + s, P.u_min), P.u_max);
         P.out[k] = pow(10.0, u);

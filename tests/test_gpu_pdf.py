@@ -4,7 +4,7 @@ sharp broken power law; dN/dlog10(lambda) and dN/dlambda) against the oracle.
 Both sides invert the same uniform, so they differ only by rounding.  A
 rounding error dF in probability moves the draw by dF / p(u), p the
 normalised density of u; the device builds its Eq. 1 CDF from 1024 cells
-(each a six-point Gauss-Legendre sum, then a scan of depth <= 13) and the
+(each an eight-point Gauss-Legendre sum, then a scan of depth <= 13) and the
 log-normal one from erfc / erfcinv (a few ulp each), the oracle sums in
 extended precision or bisects on erfc.  The bar is
     |u_gpu - u_ref| <= 64 eps / p(u) + 8 eps (1 + |u|),   eps = 2^-52,
@@ -26,6 +26,8 @@ CASES = {
     "eq1_table2_log": dict(kind=1, measure=0),
     "eq1_table2_linear": dict(kind=1, measure=1),
     "eq1_wide_steep": dict(kind=1, measure=0, u_min=-8.0, u_max=2.0, u_star=-2.0, d1=-0.3, d2=3.5),
+    # near the accepted sharpness of the break (12 * 17 * ln 10 = 470 <= 512)
+    "eq1_extreme": dict(kind=1, measure=0, u_min=-6.0, u_max=6.0, u_star=0.0, d1=-2.0, d2=15.0),
     "eq2_log": dict(kind=2, measure=0, u_min=-6.0, u_max=1.0, u_star=-3.25),
     "eq2_linear": dict(kind=2, measure=1, u_min=-6.0, u_max=1.0, u_star=-3.25),
     "eq2_upper_tail": dict(kind=2, measure=0, u_min=-1.5, u_max=0.5, u_star=-3.25),
@@ -126,7 +128,8 @@ def test_pdf_draw_streams_and_errors(gpu_ctx):
     m.agn_pdf_draw(gpu_ctx, p, 0, 4, 0, a)  # n = 0 is a no-op
     bad = [m.pdf_params(3), m.pdf_params(1, 2), m.pdf_params(1, 0, 1.0, 0.0),
            m.pdf_params(2, sigma=-1.0), m.pdf_params(0, u_star=2.0),
-           m.pdf_params(1, 0, -300.0, 300.0, 0.0, 0.5, 2.5)]
+           m.pdf_params(1, 0, -300.0, 300.0, 0.0, 0.5, 2.5),
+           m.pdf_params(1, 0, -6.0, 6.0, 0.0, -5.0, 40.0)]  # break sharper than two table cells
     for q in bad:
         with pytest.raises(m.AgnError):
             m.agn_pdf_draw(gpu_ctx, q, 1000, 4, 0, a)
