@@ -191,11 +191,17 @@ int agn_lc_generate_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n,
  *              with hipGraphLaunch (no per-kernel host work).
  *              AGN_PLAN_AUTOTUNE: choose the number of concurrent launch
  *              chains (1, 2 or 4; the lengths are dealt to chains longest
- *              first) by timing each on the batch cut to two iterations per
- *              curve; the choice is cached in ctx per batch layout.  This
- *              synchronises `stream` and runs kernels that write x_out.
- *              The chain count changes only the order in which independent
- *              curves run, never their arithmetic.
+ *              first) and, in the FP32 form, the tile of the multi-pass
+ *              radix sort (8192 or 16384 keys, the latter for lengths it
+ *              divides), by timing each pair on the batch cut to two
+ *              iterations per curve; the choice is cached in ctx per batch
+ *              layout.  This synchronises `stream` and runs kernels that
+ *              write x_out.  Neither choice changes any arithmetic: chains
+ *              only reorder independent curves, and the sort is exact.
+ *              AGN_PLAN_LARGE_SORT_TILE: use the 16384-key sort tile
+ *              without tuning (not with AGN_PLAN_AUTOTUNE).  The FFT
+ *              decomposition is fixed per length, because it sets the
+ *              rounding of the transforms.
  *   branches   chain count when AGN_PLAN_AUTOTUNE is not set (0 or 1: one
  *              chain; at most 8).  Chains run on plan-owned streams of
  *              default priority that fork from and join back into the
@@ -206,7 +212,7 @@ int agn_lc_generate_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n,
  * launches of one plan must not overlap in time (they share ws).
  */
 typedef struct agn_batch_plan agn_batch_plan;
-enum { AGN_PLAN_GRAPH = 1, AGN_PLAN_AUTOTUNE = 2 };
+enum { AGN_PLAN_GRAPH = 1, AGN_PLAN_AUTOTUNE = 2, AGN_PLAN_LARGE_SORT_TILE = 4 };
 
 int agn_batch_plan_create(agn_ctx* ctx, int32_t n_curves, const int64_t* n, const int64_t* offset,
                           const agn_psd_params* p, const double* dt, const int32_t* iters,
@@ -217,6 +223,9 @@ int agn_batch_plan_create(agn_ctx* ctx, int32_t n_curves, const int64_t* n, cons
 int agn_batch_plan_launch(agn_batch_plan* plan, void* stream);
 /* Chain count in use, number of launch groups (distinct lengths per path), 1 if graph mode. */
 int agn_batch_plan_info(const agn_batch_plan* plan, int32_t* branches, int32_t* groups, int32_t* uses_graph);
+/* The tuned (or requested) choices: chain count and sort tile (8192 or 16384;
+ * 16384 applies to FP32 multi-pass curves whose length it divides). */
+int agn_batch_plan_tuning(const agn_batch_plan* plan, int32_t* branches, int32_t* sort_tile);
 int agn_batch_plan_destroy(agn_batch_plan* plan);
 
 /* Parameters of the PDF draw: a sharp broken power law in dN/dlog10(lambda)

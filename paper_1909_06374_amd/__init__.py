@@ -105,6 +105,7 @@ def _declare(lib):
                                           C.c_int, C.c_int, vp, sz, vp, C.POINTER(vp)]
     lib.agn_batch_plan_launch.argtypes = [vp, vp]
     lib.agn_batch_plan_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    lib.agn_batch_plan_tuning.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
     lib.agn_batch_plan_destroy.argtypes = [vp]
     lib.agn_log_bin_count.argtypes = [i64, d, C.POINTER(i32)]
     lib.agn_periodogram_workspace_size.argtypes = [i32, vp, d, C.POINTER(sz)]
@@ -117,7 +118,7 @@ def _declare(lib):
               "agn_workspace_size", "agn_batch_workspace_size", "agn_psd_spectrum",
               "agn_lc_iterate", "agn_lc_generate", "agn_lc_generate_batch", "agn_test_philox",
               "agn_ctx_set_profiling", "agn_ctx_kernel_time", "agn_erdf_draw", "agn_pdf_draw", "agn_pdf_slice", "agn_batch_plan_create",
-              "agn_batch_plan_launch", "agn_batch_plan_info", "agn_batch_plan_destroy", "agn_log_bin_count",
+              "agn_batch_plan_launch", "agn_batch_plan_info", "agn_batch_plan_tuning", "agn_batch_plan_destroy", "agn_log_bin_count",
               "agn_periodogram_workspace_size", "agn_periodogram_batch", "agn_lag_stats_workspace_size",
               "agn_lag_stats_batch", "agn_psd_fit_workspace_size", "agn_psd_fit_batch"):
         getattr(lib, f).restype = C.c_int
@@ -263,6 +264,7 @@ def agn_lc_generate_batch(ctx: Context, n, offset, params, dt, iters, seed, curv
 
 AGN_PLAN_GRAPH = 1
 AGN_PLAN_AUTOTUNE = 2
+AGN_PLAN_LARGE_SORT_TILE = 4
 
 
 class BatchPlan:
@@ -276,7 +278,9 @@ class BatchPlan:
     def info(self):
         b, g, u = C.c_int32(), C.c_int32(), C.c_int32()
         _check(lib().agn_batch_plan_info(self.handle, C.byref(b), C.byref(g), C.byref(u)))
-        return {"branches": b.value, "groups": g.value, "graph": bool(u.value)}
+        t = C.c_int32()
+        _check(lib().agn_batch_plan_tuning(self.handle, None, C.byref(t)))
+        return {"branches": b.value, "groups": g.value, "graph": bool(u.value), "sort_tile": t.value}
 
     def close(self):
         if self.handle:

@@ -189,7 +189,7 @@ struct agn_ctx {
     std::vector<void*> tw64_mem;
     std::vector<StageSlot> ring;
     size_t ring_next = 0;
-    std::map<std::string, int> tuned;  // batch signature -> chain count chosen by the autotuner
+    std::map<std::string, std::pair<int, int>> tuned;  // batch signature -> (chains, sort tile) chosen by the autotuner
 };
 
 static const char* KERNEL_NAMES =
@@ -584,13 +584,14 @@ static void launch_fft_pass(agn_ctx* ctx, const BigCurve* d, int nc, const FftPa
     }
 }
 
-template <typename K, typename T>
-static void launch_sort_pass(agn_ctx* ctx, const BigCurve* d, int nc, int64_t ntiles, const SortPass& P,
-                             hipStream_t st) {
+template <typename K, int TILE>
+static void launch_sort_pass_t(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, const SortPass& P,
+                               hipStream_t st) {
+    const int64_t ntiles = n / TILE;
     dim3 gt((unsigned)ntiles, (unsigned)nc);
     {
         ProfScope ps(ctx, "sort_hist", st);
-        hipLaunchKernelGGL((k_sort_hist<K>), gt, dim3(BIG_THREADS), 0, st, d, P, ntiles);
+        hipLaunchKernelGGL((k_sort_hist<K, TILE>), gt, dim3(BIG_THREADS), 0, st, d, P, ntiles);
     }
     {
         ProfScope ps(ctx, "sort_scan", st);
@@ -599,8 +600,26 @@ static void launch_sort_pass(agn_ctx* ctx, const BigCurve* d, int nc, int64_t nt
     }
     {
         ProfScope ps(ctx, "sort_scatter", st);
-        hipLaunchKernelGGL((k_sort_scatter<K>), gt, dim3(BIG_TILE / scat_ipt<K>::value), 0, st, d, P, ntiles);
+        hipLaunchKernelGGL((k_sort_scatter<K, TILE>), gt, dim3(TILE / scat_ipt<K>::value), 0, st, d, P, ntiles);
     }
+}
+
+// Sort tile actually used for keys K on a curve of length n (a multiple of BIG_TILE).
+template <typename K>
+static int sort_tile_for(int64_t n, int want) {
+    return (sizeof(K) == 4 && want == SORT_TILE_BIG && n % SORT_TILE_BIG == 0) ? SORT_TILE_BIG : BIG_TILE;
+}
+
+template <typename K, typename T>
+static void launch_sort_pass(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, const SortPass& P, int tile,
+                             hipStream_t st) {
+    if constexpr (sizeof(K) == 4) {
+        if (sort_tile_for<K>(n, tile) == SORT_TILE_BIG) {
+            launch_sort_pass_t<K, SORT_TILE_BIG>(ctx, d, nc, n, P, st);
+            return;
+        }
+    }
+    launch_sort_pass_t<K, BIG_TILE>(ctx, d, nc, n, P, st);
 }
 
 // Checks the multi-pass FFT plan of length n and resolves its twiddle table.
@@ -624,7 +643,7 @@ static int big_group_setup(agn_ctx* ctx, int64_t n, agn_precision prec, TwTable*
 // big_group_setup).  ctx may be NULL (no kernel timing, e.g. under capture).
 template <typename T>
 static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, int32_t max_iters,
-                          const TwTable& tb, const std::vector<int>& rad, hipStream_t st) {
+                          const TwTable& tb, const std::vector<int>& rad, int sort_tile, hipStream_t st) {
     typedef typename key_of<T>::type K;
     const int64_t M = n / 2, ntiles = n / BIG_TILE;
     const dim3 gt((unsigned)ntiles, (unsigned)nc);
@@ -639,7 +658,7 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
             P.src_sel = p & 1;
             P.mode = p == 7 ? SORT_MODE_PREP : SORT_MODE_MOVE;
             P.rank_sel = 0;
-            launch_sort_pass<uint64_t, T>(nullptr, d, nc, ntiles, P, st);
+            launch_sort_pass<uint64_t, T>(nullptr, d, nc, n, P, BIG_TILE, st);
         }
     }
     hipLaunchKernelGGL(k_big_after_prep, dim3((unsigned)nc), dim3(64), 0, st, d);
@@ -696,7 +715,7 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
             P.src_sel = src;
             P.mode = p == npass_sort - 1 ? SORT_MODE_RANK : SORT_MODE_MOVE;
             P.rank_sel = 1 - cur;
-            launch_sort_pass<K, T>(ctx, d, nc, ntiles, P, st);
+            launch_sort_pass<K, T>(ctx, d, nc, n, P, sort_tile, st);
             src = 1 - src;
         }
     }
@@ -742,6 +761,7 @@ struct agn_batch_plan {
     std::vector<BigGroup> big;
     std::vector<double> lds_cost, big_cost;  // relative run time of each group
     int branches = 1;                         // concurrent launch chains
+    int sort_tile = BIG_TILE;                 // requested tile of 32-bit-key sorts (multi-pass curves)
     int flags = 0;
     std::vector<hipStream_t> aux;             // chains 1..branches-1 (default priority)
     std::vector<hipEvent_t> ev;               // fork + one join event per chain
@@ -932,8 +952,10 @@ static void enqueue_group(const agn_batch_plan& pl, agn_ctx* pctx, bool is_big, 
         else launch_lds_E<double>(pctx, g.E, pl.d_lc + g.first, g.count, g.nt, g.pl, g.il, st);
     } else {
         const BigGroup& g = pl.big[k];
-        if (pl.prec == AGN_FP32) run_big_group<float>(pctx, pl.d_bg + g.first, g.count, g.n, g.max_it, g.tb, g.rad, st);
-        else run_big_group<double>(pctx, pl.d_bg + g.first, g.count, g.n, g.max_it, g.tb, g.rad, st);
+        if (pl.prec == AGN_FP32)
+            run_big_group<float>(pctx, pl.d_bg + g.first, g.count, g.n, g.max_it, g.tb, g.rad, pl.sort_tile, st);
+        else
+            run_big_group<double>(pctx, pl.d_bg + g.first, g.count, g.n, g.max_it, g.tb, g.rad, pl.sort_tile, st);
     }
 }
 
@@ -1148,11 +1170,12 @@ static std::string plan_signature(const agn_batch_plan& pl) {
     return sig;
 }
 
-// Times each candidate chain count on a copy of the batch with at most two
-// iterations per curve (same workspace, so the real plan is built after it)
-// and returns the fastest.  Synchronises st.
-static int autotune_branches(agn_ctx* ctx, std::vector<CurveReq> rq, double tol, agn_precision prec, void* ws,
-                             size_t ws_bytes, hipStream_t st, int* best) {
+// Times each candidate (chain count, sort tile) on a copy of the batch with at
+// most two iterations per curve (same workspace, so the real plan is built
+// after it) and returns the fastest.  Both choices leave every result
+// bit-identical.  Synchronises st.
+static int autotune_plan(agn_ctx* ctx, std::vector<CurveReq> rq, double tol, agn_precision prec, void* ws,
+                         size_t ws_bytes, hipStream_t st, int* best_branches, int* best_tile) {
     for (auto& r : rq) {
         r.iters = std::min(r.iters, 2);
         r.delta_out = nullptr;  // the real plan's delta rows are laid out for its own iteration count
@@ -1161,29 +1184,44 @@ static int autotune_branches(agn_ctx* ctx, std::vector<CurveReq> rq, double tol,
     int rc = build_plan(ctx, rq, tol, prec, ws, ws_bytes, st, tp);
     if (rc) { destroy_plan_resources(tp); return rc; }
     const int ng = (int)(tp.lds.size() + tp.big.size());
+    bool big_tile_ok = false;  // some 32-bit-key group whose length the larger tile divides
+    for (const auto& g : tp.big)
+        if (prec == AGN_FP32 && g.n % SORT_TILE_BIG == 0) big_tile_ok = true;
     const int cand[3] = {1, 2, 4};
+    const int tiles[2] = {BIG_TILE, SORT_TILE_BIG};
     hipEvent_t a = nullptr, b = nullptr;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
     float best_ms = 0.f;
-    *best = 1;
+    bool have = false;
+    *best_branches = 1;
+    *best_tile = BIG_TILE;
     rc = AGN_OK;
-    for (int ci = 0; ci < 3 && rc == AGN_OK; ++ci) {
-        if (cand[ci] > 1 && cand[ci] > ng) break;
-        float m = 0.f;
-        for (int rep = 0; rep < 3 && rc == AGN_OK; ++rep) {  // first run warms up
-            if (hipEventRecord(a, st) != hipSuccess) { rc = fail(AGN_EDEVICE, "event record failed"); break; }
-            rc = enqueue_plan(tp, nullptr, cand[ci], st);
-            if (rc) break;
-            if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
-                rc = fail(AGN_EDEVICE, "event wait failed");
-                break;
+    for (int ti = 0; ti < 2 && rc == AGN_OK; ++ti) {
+        if (ti == 1 && !big_tile_ok) break;
+        tp.sort_tile = tiles[ti];
+        for (int ci = 0; ci < 3 && rc == AGN_OK; ++ci) {
+            if (cand[ci] > 1 && cand[ci] > ng) break;
+            float m = 0.f;
+            for (int rep = 0; rep < 3 && rc == AGN_OK; ++rep) {  // first run warms up
+                if (hipEventRecord(a, st) != hipSuccess) { rc = fail(AGN_EDEVICE, "event record failed"); break; }
+                rc = enqueue_plan(tp, nullptr, cand[ci], st);
+                if (rc) break;
+                if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+                    rc = fail(AGN_EDEVICE, "event wait failed");
+                    break;
+                }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, a, b);
+                if (rep == 1 || (rep == 2 && ms < m)) m = ms;
             }
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, a, b);
-            if (rep == 1 || (rep == 2 && ms < m)) m = ms;
+            if (rc == AGN_OK && (!have || m < best_ms)) {
+                best_ms = m;
+                *best_branches = cand[ci];
+                *best_tile = tiles[ti];
+                have = true;
+            }
         }
-        if (rc == AGN_OK && (ci == 0 || m < best_ms)) { best_ms = m; *best = cand[ci]; }
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
@@ -1199,7 +1237,10 @@ extern "C" int agn_batch_plan_create(agn_ctx* ctx, int32_t n_curves, const int64
                                      void* stream, agn_batch_plan** out) {
     if (!ctx || !out) return fail(AGN_EINVAL, "NULL argument");
     *out = nullptr;
-    if (flags & ~(AGN_PLAN_GRAPH | AGN_PLAN_AUTOTUNE)) return fail(AGN_EINVAL, "unknown plan flags 0x%x", flags);
+    if (flags & ~(AGN_PLAN_GRAPH | AGN_PLAN_AUTOTUNE | AGN_PLAN_LARGE_SORT_TILE))
+        return fail(AGN_EINVAL, "unknown plan flags 0x%x", flags);
+    if ((flags & AGN_PLAN_AUTOTUNE) && (flags & AGN_PLAN_LARGE_SORT_TILE))
+        return fail(AGN_EINVAL, "AGN_PLAN_LARGE_SORT_TILE fixes the tile that AGN_PLAN_AUTOTUNE would choose");
     if (branches < 0 || branches > 8) return fail(AGN_EINVAL, "branches must be 0..8");
     std::vector<CurveReq> rq;
     int rc = batch_requests(n_curves, n, offset, p, dt, iters, seed, curve_id, erdf, tol, prec, x_out, delta_out,
@@ -1210,16 +1251,17 @@ extern "C" int agn_batch_plan_create(agn_ctx* ctx, int32_t n_curves, const int64
     pl->flags = flags;
     if ((rc = build_plan(ctx, rq, tol, prec, ws, ws_bytes, st, *pl))) { destroy_plan_resources(*pl); return rc; }
     int nb = branches > 0 ? branches : 1;
+    int tile = (flags & AGN_PLAN_LARGE_SORT_TILE) ? SORT_TILE_BIG : BIG_TILE;
     if ((flags & AGN_PLAN_AUTOTUNE) && !rq.empty()) {
         const std::string sig = plan_signature(*pl);
         bool hit = false;
         {
             std::lock_guard<std::mutex> lk(ctx->mu);
             auto it = ctx->tuned.find(sig);
-            if (it != ctx->tuned.end()) { nb = it->second; hit = true; }
+            if (it != ctx->tuned.end()) { nb = it->second.first; tile = it->second.second; hit = true; }
         }
         if (!hit) {
-            if ((rc = autotune_branches(ctx, rq, tol, prec, ws, ws_bytes, st, &nb))) {
+            if ((rc = autotune_plan(ctx, rq, tol, prec, ws, ws_bytes, st, &nb, &tile))) {
                 destroy_plan_resources(*pl);
                 return rc;
             }
@@ -1232,10 +1274,11 @@ extern "C" int agn_batch_plan_create(agn_ctx* ctx, int32_t n_curves, const int64
                 return rc;
             }
             std::lock_guard<std::mutex> lk(ctx->mu);
-            ctx->tuned[sig] = nb;
+            ctx->tuned[sig] = std::make_pair(nb, tile);
         }
     }
     pl->branches = nb;
+    pl->sort_tile = tile;
     *out = pl.release();
     return AGN_OK;
 }
@@ -1273,6 +1316,13 @@ extern "C" int agn_batch_plan_info(const agn_batch_plan* pl, int32_t* branches, 
     if (branches) *branches = pl->branches;
     if (groups) *groups = (int32_t)(pl->lds.size() + pl->big.size());
     if (uses_graph) *uses_graph = (pl->flags & AGN_PLAN_GRAPH) ? 1 : 0;
+    return AGN_OK;
+}
+
+extern "C" int agn_batch_plan_tuning(const agn_batch_plan* pl, int32_t* branches, int32_t* sort_tile) {
+    if (!pl) return fail(AGN_EINVAL, "plan is NULL");
+    if (branches) *branches = pl->branches;
+    if (sort_tile) *sort_tile = pl->sort_tile;
     return AGN_OK;
 }
 

@@ -39,6 +39,11 @@ template <typename K>
 struct scat_ipt {
     static constexpr int value = sizeof(K) == 4 ? 16 : 8;
 };
+// Larger sort tile for 32-bit keys (curves whose length it divides): digit
+// runs twice as long, 146 KB of LDS, one 1024-thread workgroup per CU.  Its
+// staging does not fit for 64-bit keys.  Exact either way; the batch-plan
+// autotuner chooses.
+constexpr int SORT_TILE_BIG = 16384;
 constexpr int FFT_COLS_MIN = 16;     // fewest butterflies per FFT workgroup
 constexpr int FFT_COLS_MAX = 64;     // most butterflies per FFT workgroup
 constexpr int TW_LO_BITS = 12;       // two-level twiddle split
@@ -346,23 +351,24 @@ struct SortPass {
 // grid: (ntiles, curves), block 256.  hist[d * ntiles + tile] = count of digit d.
 // All loads of a thread are issued before its counting; each wave counts into
 // its own LDS histogram (fewer colliding atomics when few digits dominate).
-template <typename K>
+template <typename K, int TILE>
 __global__ __launch_bounds__(BIG_THREADS) void k_sort_hist(const BigCurve* __restrict__ cv, SortPass P,
                                                            int64_t ntiles) {
+    constexpr int IPT = TILE / BIG_THREADS;
     __shared__ uint32_t h[BIG_THREADS / 64][256];
     const BigCurve& d = cv[blockIdx.y];
     if (d.state[1] == 0) return;
     const int tid = threadIdx.x, wave = tid >> 6;
     const K* keys = (const K*)(P.src_sel ? d.sortB : d.sortA);
-    const int64_t base = (int64_t)blockIdx.x * BIG_TILE;
-    K k[BIG_IPT];
+    const int64_t base = (int64_t)blockIdx.x * TILE;
+    K k[IPT];
 #pragma unroll
-    for (int i = 0; i < BIG_IPT; ++i) k[i] = keys[base + i * BIG_THREADS + tid];
+    for (int i = 0; i < IPT; ++i) k[i] = keys[base + i * BIG_THREADS + tid];
 #pragma unroll
     for (int w = 0; w < BIG_THREADS / 64; ++w) h[w][tid] = 0;
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < BIG_IPT; ++i) atomicAdd(&h[wave][(uint32_t)(k[i] >> P.shift) & 255u], 1u);
+    for (int i = 0; i < IPT; ++i) atomicAdd(&h[wave][(uint32_t)(k[i] >> P.shift) & 255u], 1u);
     __syncthreads();
     uint32_t c = 0;
 #pragma unroll
@@ -422,25 +428,26 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sort_scan_digits(const BigCurve
     d.dstart[tid] = wpre + inc - v;
 }
 
-// grid: (ntiles, curves), block BIG_TILE / scat_ipt<K>.  Stable scatter of
-// one 8-bit digit.  Each wave ranks its 64 x SCAT_IPT keys with ballots and per-wave
+// grid: (ntiles, curves), block TILE / scat_ipt<K>.  Stable scatter of one
+// 8-bit digit.  Each wave ranks its 64 x SCAT_IPT keys with ballots and per-wave
 // running digit counters; the tile is then rearranged in LDS into digit order,
 // and thread q takes tile positions q, q + SCAT_THREADS, ... so that
 // consecutive threads write consecutive global positions inside each digit's
-// run (8192-key tiles: runs of 32 keys on average).
-template <typename K>
-__global__ __launch_bounds__(BIG_TILE / scat_ipt<K>::value) void k_sort_scatter(const BigCurve* __restrict__ cv,
-                                                                                SortPass P, int64_t ntiles) {
+// run (runs of TILE / 256 keys on average).
+template <typename K, int TILE>
+__global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(const BigCurve* __restrict__ cv,
+                                                                            SortPass P, int64_t ntiles) {
     constexpr int SCAT_IPT = scat_ipt<K>::value;
-    constexpr int SCAT_THREADS = BIG_TILE / SCAT_IPT;
+    constexpr int SCAT_THREADS = TILE / SCAT_IPT;
+    static_assert(SCAT_THREADS <= 1024, "tile too large for one workgroup");
     constexpr int SCAT_WAVES = SCAT_THREADS / 64;
     __shared__ uint16_t wcnt[SCAT_WAVES][256];  // per-wave running digit counters (<= 64 * SCAT_IPT)
     __shared__ uint16_t wpre[SCAT_WAVES][256];  // exclusive prefix over waves
     __shared__ uint32_t tstart[256];            // digit start inside the tile
     __shared__ uint32_t gbase[256];             // global start of the tile's digit run
     __shared__ uint32_t wtot[4];                // digit-scan totals of the first four waves
-    __shared__ K skey[BIG_TILE];
-    __shared__ uint32_t sval[BIG_TILE];
+    __shared__ K skey[TILE];
+    __shared__ uint32_t sval[TILE];
     static_assert(64 * SCAT_IPT * (SCAT_WAVES - 1) < 65536, "wave prefix must fit 16 bits");
     static_assert(SCAT_THREADS >= 256 && SCAT_WAVES >= 4, "the digit phase takes the first 256 threads");
     const BigCurve& d = cv[blockIdx.y];
@@ -448,7 +455,7 @@ __global__ __launch_bounds__(BIG_TILE / scat_ipt<K>::value) void k_sort_scatter(
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n = d.n;
     const int64_t tile = blockIdx.x;
-    const int64_t base = tile * BIG_TILE + (int64_t)wave * 64 * SCAT_IPT;
+    const int64_t base = tile * TILE + (int64_t)wave * 64 * SCAT_IPT;
     const unsigned char* srcb = P.src_sel ? d.sortB : d.sortA;
     const K* skeys = (const K*)srcb;
     const uint32_t* svals = (const uint32_t*)(srcb + (size_t)n * sizeof(K));
@@ -527,7 +534,7 @@ __global__ __launch_bounds__(BIG_TILE / scat_ipt<K>::value) void k_sort_scatter(
     uint32_t* rnk = P.rank_sel ? d.rankB : d.rankA;
     double* xn = P.rank_sel ? d.X1 : d.X0;
 #pragma unroll 4
-    for (int q = tid; q < BIG_TILE; q += SCAT_THREADS) {
+    for (int q = tid; q < TILE; q += SCAT_THREADS) {
         const K k = skey[q];
         const uint32_t v = sval[q];
         const uint32_t dg = (uint32_t)(k >> P.shift) & 255u;

@@ -55,8 +55,10 @@ def _plan(ctx, b, erdf_t, o, flags, branches):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("flags,branches", [(0, 1), (0, 3), (1, 1), (1, 4)])
+@pytest.mark.parametrize("flags,branches", [(0, 1), (0, 3), (1, 1), (1, 4), (4, 1), (5, 2)])
 def test_plan_launch_equals_batch(gpu_ctx, prec, flags, branches):
+    """Also with the 16384-key sort tile (flag 4): in FP32 it applies to the
+    2^15 and 2^16 curves of the batch, whose sorts must stay exact."""
     m = agn()
     b = _batch(prec)
     erdf_t = dev(b["erdf"])
@@ -66,6 +68,7 @@ def test_plan_launch_equals_batch(gpu_ctx, prec, flags, branches):
     info = plan.info()
     assert info["groups"] == len(set(NS)) and info["graph"] == bool(flags & m.AGN_PLAN_GRAPH)
     assert info["branches"] == max(branches, 1)
+    assert info["sort_tile"] == (16384 if flags & m.AGN_PLAN_LARGE_SORT_TILE else 8192)
     for rep in range(3):
         o["x"].fill_(float("nan"))
         o["done"].fill_(-7)
@@ -114,12 +117,13 @@ def test_autotune_choice_is_cached_and_exact(gpu_ctx):
     o = _buffers(b)
     plan = _plan(gpu_ctx, b, erdf_t, o, m.AGN_PLAN_AUTOTUNE | m.AGN_PLAN_GRAPH, 0)
     chosen = plan.info()["branches"]
-    assert chosen in (1, 2, 4)
+    tile = plan.info()["sort_tile"]
+    assert chosen in (1, 2, 4) and tile in (8192, 16384)
     m.agn_batch_plan_launch(plan)
     assert np.array_equal(host(o["x"]), xr) and np.array_equal(host(o["d"]), dr)
     assert np.array_equal(host(o["done"]), doner)
     plan2 = _plan(gpu_ctx, b, erdf_t, o, m.AGN_PLAN_AUTOTUNE, 0)
-    assert plan2.info()["branches"] == chosen
+    assert plan2.info()["branches"] == chosen and plan2.info()["sort_tile"] == tile
     m.agn_batch_plan_launch(plan2)
     assert np.array_equal(host(o["x"]), xr)
     plan.close()
@@ -133,6 +137,8 @@ def test_plan_argument_errors(gpu_ctx):
     o = _buffers(b)
     with pytest.raises(m.AgnError):
         _plan(gpu_ctx, b, erdf_t, o, 8, 1)
+    with pytest.raises(m.AgnError):  # a fixed tile and tuning exclude each other
+        _plan(gpu_ctx, b, erdf_t, o, m.AGN_PLAN_AUTOTUNE | m.AGN_PLAN_LARGE_SORT_TILE, 1)
     with pytest.raises(m.AgnError):
         _plan(gpu_ctx, b, erdf_t, o, 0, 9)
     small = dict(o, ws=o["ws"][:1024])
