@@ -357,7 +357,8 @@ def log_binned_periodogram(np, x, dex=0.1):
 def fp32_accuracy(agn, np, torch, ctx, x32_all, ns, offs, params, dt_days, iters, seeds, ids, erdf_t, k):
     """FP32 form against the FP64 path (bit-identical to the oracle) on the
     first k curves: value multiset, end-to-end and one-step rank agreement,
-    |rank difference| quantiles, log-binned periodogram difference."""
+    |rank difference| quantiles, log-binned periodogram difference after all
+    iterations and after one step from the same input."""
     dev = "cuda:0"
     ns_k, offs_k = ns[:k], offs[:k]
     tot = int(sum(ns_k))
@@ -368,7 +369,7 @@ def fp32_accuracy(agn, np, torch, ctx, x32_all, ns, offs, params, dt_days, iters
     torch.cuda.synchronize()
     a64 = x64.cpu().numpy()
     a32 = x32_all[:tot].cpu().numpy()
-    multiset, e2e, one, drank, pdiff = True, [], [], [], []
+    multiset, e2e, one, drank, pdiff, pdiff1 = True, [], [], [], [], []
     for c in range(k):
         n, o = ns_k[c], offs_k[c]
         u32, u64 = a32[o:o + n], a64[o:o + n]
@@ -381,7 +382,7 @@ def fp32_accuracy(agn, np, torch, ctx, x32_all, ns, offs, params, dt_days, iters
         p32, p64 = log_binned_periodogram(np, u32), log_binned_periodogram(np, u64)
         pdiff.append(np.abs(p32 / p64 - 1.0))
         # one step from the same input (the FP64 result) in both precisions
-        ranks = []
+        ranks, outs = [], []
         for prec in (agn.AGN_FP32, agn.AGN_FP64):
             el = torch.float32 if prec == agn.AGN_FP32 else torch.float64
             amp = torch.empty(n // 2 + 1, dtype=el, device=dev)
@@ -393,15 +394,20 @@ def fp32_accuracy(agn, np, torch, ctx, x32_all, ns, offs, params, dt_days, iters
             agn.agn_lc_iterate(ctx, amp, x64[o:o + n], n, 1, -1.0, prec, xo, None, None, rk, iws)
             torch.cuda.synchronize()
             ranks.append(rk.cpu().numpy())
+            outs.append(xo.cpu().numpy())
         one.append(np.mean(ranks[0] == ranks[1]))
+        q32, q64 = log_binned_periodogram(np, outs[0]), log_binned_periodogram(np, outs[1])
+        pdiff1.append(np.abs(q32 / q64 - 1.0))
     dr = np.concatenate(drank)
     pd = np.concatenate(pdiff)
+    pd1 = np.concatenate(pdiff1)
     return {"curves": k, "reference": "FP64 GPU path (bit-identical to the FP64 oracle)",
             "value_multiset_exact": multiset,
             "one_step_rank_agreement": round(float(np.mean(one)), 6),
             "end_to_end_agreement": round(float(np.mean(e2e)), 6),
             "abs_rank_diff_p50_p99_max": [int(np.percentile(dr, 50)), int(np.percentile(dr, 99)), int(dr.max())],
-            "log_binned_periodogram_rel_diff_median_max": [float(np.median(pd)), float(pd.max())]}
+            "log_binned_periodogram_rel_diff_median_max": [float(np.median(pd)), float(pd.max())],
+            "one_step_log_binned_periodogram_rel_diff_median_max": [float(np.median(pd1)), float(pd1.max())]}
 
 
 def run_uneven(args, agn, synth, np, torch):
