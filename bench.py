@@ -482,6 +482,16 @@ def run_uneven(args, agn, synth, np, torch):
         "roofline": {"bound": "hbm" if dom != "lds_iterate" else "alu", "kernel": dom,
                      "avg_launch_ms": round(dom_ms, 4), "note": "per-kernel times from one eager profiled run"},
     }
+    if dom == "sort_scatter":
+        # algorithmic bytes of every scatter launch of the eager run: multi-pass
+        # curves only; per iteration 4 passes of 32-bit keys (2 (4 + 4) bytes per
+        # key), once 8 passes of the 64-bit draw keys (2 (8 + 4) bytes per key)
+        big = [nn for nn in ns if not ((nn % 3 == 0 and nn <= 12288) or (nn % 3 != 0 and nn <= 16384))]
+        byts = float(sum(big)) * (iters * 4 * 16 + 8 * 24)
+        achieved = byts / (kt[dom][0] / 1000.0) / 1e9
+        out["roofline"].update({"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                                "bytes": "16 per key per pass (FP32 keys), 24 for the one-time draw sort"})
     if not args.no_cpu_baseline:
         import oracle
         # bounded sample: the first curves of the batch up to 2^21 samples, 3 iterations
