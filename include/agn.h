@@ -366,7 +366,7 @@ int agn_test_philox(uint64_t key0, uint64_t key1, uint64_t ctr0, int64_t n_block
  * bins).  Least squares in log10 P over the bins with a positive mean; each
  * bin sits at the mean frequency of the f_j = j / (n dt) it holds; the break
  * is held at p[c].f_br and (log10 A, a_low, a_high) are free, started from
- * p[c].a_low / p[c].a_high (Levenberg-Marquardt, FP64).
+ * p[c].a_low / p[c].a_high (Levenberg-Marquardt, FP64, one wave per curve).
  *   fit_out[4 c + {0,1,2,3}] = log10 A, a_low, a_high, rms of the log10
  *   residuals; Eq. 3 is symmetric in its slopes, so a_low is the smaller.
  *   NaN if fewer than 3 bins are positive or none lies on one side of f_br.

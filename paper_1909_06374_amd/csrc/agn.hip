@@ -1646,8 +1646,7 @@ extern "C" int agn_psd_fit_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* 
     if ((rc = stage_upload(ctx, ws, hdr.data(), hdr.size(), st))) return rc;
     {
         ProfScope ps(ctx, "psd_fit", st);
-        hipLaunchKernelGGL(k_psd_fit, dim3((unsigned)((n_curves + 63) / 64)), dim3(64), 0, st, (const FitDesc*)ws,
-                           n_curves);
+        hipLaunchKernelGGL(k_psd_fit, dim3((unsigned)n_curves), dim3(64), 0, st, (const FitDesc*)ws, n_curves);
     }
     HIPCHK(hipGetLastError());
     return AGN_OK;

@@ -310,7 +310,7 @@ __global__ __launch_bounds__(256) void k_lag_rep(const double* __restrict__ sf2,
 // Fit of Eq. 3 to each curve's log-binned periodogram (the convergence test
 // of Sec. 3.2.2): least squares in log10 P, the break held at the input f_br,
 // (a = log10 A, a_low, a_high) free; Levenberg-Marquardt from the input
-// slopes, one thread per curve (a few dozen bins each).
+// slopes, one wave per curve (its bins spread over the lanes).
 // ---------------------------------------------------------------------------
 struct FitDesc {
     const double* f;     // bin frequencies (mean f_j of the bin)
@@ -327,29 +327,52 @@ struct FitEval {
     double g[3];
 };
 
-AGN_DEV void fit_eval(const FitDesc& d, const double th[3], bool jac, FitEval* e) {
+// Wave sum by an xor butterfly: every lane ends with the same bits (each
+// stage adds two partial sums that are equal up to commutation).
+AGN_DEV double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum of squares, and if jac the normal equations, over the bins; the 64
+// lanes of the wave take bins lane, lane + 64, ...
+AGN_DEV void fit_eval(const FitDesc& d, const double th[3], bool jac, FitEval* e, int lane) {
     const double inv_ln10 = 0.43429448190325182765;
-    e->sse = 0.0;
-    if (jac)
-        for (int i = 0; i < 3; ++i) {
-            e->g[i] = 0.0;
-            for (int k = 0; k < 3; ++k) e->A[i][k] = 0.0;
-        }
-    for (int b = 0; b < d.nb; ++b) {
+    double sse = 0.0, a00 = 0.0, a01 = 0.0, a02 = 0.0, a11 = 0.0, a12 = 0.0, a22 = 0.0, g0 = 0.0, g1 = 0.0,
+           g2 = 0.0;
+    for (int b = lane; b < d.nb; b += 64) {
         const double pb = d.pbar[b];
         if (!(pb > 0.0)) continue;
         const double lu = log(d.f[b] / d.f_br);
         const double tl = exp(th[1] * lu), tH = exp(th[2] * lu), S = tl + tH;
         const double r = log10(pb) - (th[0] - log10(S));
-        e->sse += r * r;
+        sse += r * r;
         if (jac) {
             const double L = lu * inv_ln10;
-            const double J[3] = {1.0, -tl / S * L, -tH / S * L};
-            for (int i = 0; i < 3; ++i) {
-                e->g[i] += J[i] * r;
-                for (int k = 0; k < 3; ++k) e->A[i][k] += J[i] * J[k];
-            }
+            const double j1 = -tl / S * L, j2 = -tH / S * L;  // d model / d(a, a_low, a_high) = (1, j1, j2)
+            a00 += 1.0;
+            a01 += j1;
+            a02 += j2;
+            a11 += j1 * j1;
+            a12 += j1 * j2;
+            a22 += j2 * j2;
+            g0 += r;
+            g1 += j1 * r;
+            g2 += j2 * r;
         }
+    }
+    e->sse = wave_sum(sse);
+    if (jac) {
+        e->A[0][0] = wave_sum(a00);
+        e->A[0][1] = e->A[1][0] = wave_sum(a01);
+        e->A[0][2] = e->A[2][0] = wave_sum(a02);
+        e->A[1][1] = wave_sum(a11);
+        e->A[1][2] = e->A[2][1] = wave_sum(a12);
+        e->A[2][2] = wave_sum(a22);
+        e->g[0] = wave_sum(g0);
+        e->g[1] = wave_sum(g1);
+        e->g[2] = wave_sum(g2);
     }
 }
 
@@ -371,34 +394,30 @@ AGN_DEV bool chol3(const double M[3][3], const double y[3], double x[3]) {
     return true;
 }
 
+// grid: n_curves workgroups of one wave; all lanes run the same damping
+// steps on the same (bit-identical) sums, lane 0 writes the result.
 __global__ __launch_bounds__(64) void k_psd_fit(const FitDesc* __restrict__ descs, int32_t n_curves) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.x, lane = threadIdx.x;
     if (c >= n_curves) return;
     const FitDesc d = descs[c];
-    int used = 0, below = 0, above = 0;
-    for (int b = 0; b < d.nb; ++b)
+    double cu = 0.0, cb = 0.0, ca = 0.0, s0 = 0.0;
+    for (int b = lane; b < d.nb; b += 64)
         if (d.pbar[b] > 0.0) {
-            ++used;
-            below += d.f[b] < d.f_br;
-            above += d.f[b] > d.f_br;
+            cu += 1.0;
+            cb += d.f[b] < d.f_br ? 1.0 : 0.0;
+            ca += d.f[b] > d.f_br ? 1.0 : 0.0;
+            const double lu = log(d.f[b] / d.f_br);
+            s0 += log10(d.pbar[b]) + log10(exp(d.a_low0 * lu) + exp(d.a_high0 * lu));
         }
-    const double nan = __builtin_nan("");
-    if (used < 3 || below < 1 || above < 1) {
-        for (int i = 0; i < 4; ++i) d.out[i] = nan;
+    const double used = wave_sum(cu), below = wave_sum(cb), above = wave_sum(ca);
+    s0 = wave_sum(s0);
+    if (used < 3.0 || below < 1.0 || above < 1.0) {
+        if (lane < 4) d.out[lane] = __builtin_nan("");
         return;
     }
-    double th[3] = {0.0, d.a_low0, d.a_high0};
-    {
-        double s = 0.0;
-        for (int b = 0; b < d.nb; ++b) {
-            if (!(d.pbar[b] > 0.0)) continue;
-            const double lu = log(d.f[b] / d.f_br);
-            s += log10(d.pbar[b]) + log10(exp(th[1] * lu) + exp(th[2] * lu));
-        }
-        th[0] = s / used;
-    }
+    double th[3] = {s0 / used, d.a_low0, d.a_high0};
     FitEval e;
-    fit_eval(d, th, true, &e);
+    fit_eval(d, th, true, &e, lane);
     double lambda = 1e-3;
     for (int it = 0; it < 200; ++it) {
         bool moved = false;
@@ -410,7 +429,7 @@ __global__ __launch_bounds__(64) void k_psd_fit(const FitDesc* __restrict__ desc
             if (chol3(M, e.g, dx)) {
                 const double tn[3] = {th[0] + dx[0], th[1] + dx[1], th[2] + dx[2]};
                 FitEval en;
-                fit_eval(d, tn, false, &en);
+                fit_eval(d, tn, false, &en, lane);
                 if (en.sse < e.sse) {
                     rel = 0.0;
                     for (int i = 0; i < 3; ++i) {
@@ -425,14 +444,16 @@ __global__ __launch_bounds__(64) void k_psd_fit(const FitDesc* __restrict__ desc
             lambda *= 4.0;
         }
         if (!moved) break;  // no descent at any damping: at the minimum
-        fit_eval(d, th, true, &e);
+        fit_eval(d, th, true, &e, lane);
         if (rel < 1e-15) break;
     }
-    // Eq. 3 is symmetric in its two slopes; the smaller one is the low-frequency slope
-    d.out[0] = th[0];
-    d.out[1] = fmin(th[1], th[2]);
-    d.out[2] = fmax(th[1], th[2]);
-    d.out[3] = sqrt(e.sse / used);
+    if (lane == 0) {
+        // Eq. 3 is symmetric in its two slopes; the smaller one is the low-frequency slope
+        d.out[0] = th[0];
+        d.out[1] = fmin(th[1], th[2]);
+        d.out[2] = fmax(th[1], th[2]);
+        d.out[3] = sqrt(e.sse / used);
+    }
 }
 
 }  // namespace agn
