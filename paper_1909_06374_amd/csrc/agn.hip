@@ -595,8 +595,12 @@ static void launch_sort_pass_t(agn_ctx* ctx, const BigCurve* d, int nc, int64_t 
     }
     {
         ProfScope ps(ctx, "sort_scan", st);
-        hipLaunchKernelGGL(k_sort_scan_rows, dim3(256, (unsigned)nc), dim3(BIG_THREADS), 0, st, d, ntiles);
-        hipLaunchKernelGGL(k_sort_scan_digits, dim3((unsigned)nc), dim3(BIG_THREADS), 0, st, d);
+        if (ntiles <= SCAN_SMALL_TILES) {
+            hipLaunchKernelGGL(k_sort_scan_small, dim3((unsigned)nc), dim3(BIG_THREADS), 0, st, d, ntiles);
+        } else {
+            hipLaunchKernelGGL(k_sort_scan_rows, dim3(256, (unsigned)nc), dim3(BIG_THREADS), 0, st, d, ntiles);
+            hipLaunchKernelGGL(k_sort_scan_digits, dim3((unsigned)nc), dim3(BIG_THREADS), 0, st, d);
+        }
     }
     {
         ProfScope ps(ctx, "sort_scatter", st);

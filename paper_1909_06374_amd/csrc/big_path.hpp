@@ -407,6 +407,36 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sort_scan_rows(const BigCurve* 
     if (tid == 0) d.dstart[blockIdx.x] = carry;
 }
 
+// Curves of at most SCAN_SMALL_TILES tiles: both scans in one launch.  grid:
+// (curves), block 256; thread d scans digit d's row of tile counts in place,
+// then the digit totals are scanned across the block into dstart.
+constexpr int64_t SCAN_SMALL_TILES = 128;
+
+__global__ __launch_bounds__(BIG_THREADS) void k_sort_scan_small(const BigCurve* __restrict__ cv, int64_t ntiles) {
+    __shared__ uint32_t sh[8];
+    const BigCurve& d = cv[blockIdx.x];
+    if (d.state[1] == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t* row = d.hist + (int64_t)tid * ntiles;
+    uint32_t v = 0;
+    for (int64_t i = 0; i < ntiles; ++i) {
+        const uint32_t c = row[i];
+        row[i] = v;
+        v += c;
+    }
+    uint32_t inc = v;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const uint32_t o = __shfl_up(inc, s, 64);
+        if (lane >= s) inc += o;
+    }
+    if (lane == 63) sh[wave] = inc;
+    __syncthreads();
+    uint32_t wpre = 0;
+    for (int w = 0; w < wave; ++w) wpre += sh[w];
+    d.dstart[tid] = wpre + inc - v;
+}
+
 // grid: (curves), block 256: digit totals -> exclusive digit starts.
 __global__ __launch_bounds__(BIG_THREADS) void k_sort_scan_digits(const BigCurve* __restrict__ cv) {
     __shared__ uint32_t sh[8];
