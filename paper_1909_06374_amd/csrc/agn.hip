@@ -440,7 +440,7 @@ static bool valid_params(const agn_psd_params* p, double dt) {
 }
 
 template <typename T, int E>
-static void launch_lds(agn_ctx* ctx, const LcDesc* d, int count, int nt, size_t prep_lds,
+static void launch_lds(agn_ctx* ctx, const LcDesc* d, int count, int nt, bool fuse2, size_t prep_lds,
                        size_t iter_lds, hipStream_t st) {
     {
         ProfScope ps(ctx, "lds_prep", st);
@@ -448,21 +448,29 @@ static void launch_lds(agn_ctx* ctx, const LcDesc* d, int count, int nt, size_t 
     }
     {
         ProfScope ps(ctx, "lds_iterate", st);
-        hipLaunchKernelGGL((k_lds_iterate<T, E>), dim3(count), dim3(nt), iter_lds, st, d);
+        if (fuse2) hipLaunchKernelGGL((k_lds_iterate<T, E, true>), dim3(count), dim3(nt), iter_lds, st, d);
+        else hipLaunchKernelGGL((k_lds_iterate<T, E, false>), dim3(count), dim3(nt), iter_lds, st, d);
     }
 }
 
+// Whether the LDS kernel fuses the forward transform's last pass into the
+// replacement: the half-length plan ends with radix 2.
+static bool lds_fuse2(int64_t n) {
+    const FftPlan pl = make_plan(n / 2);
+    return pl.npass >= 2 && pl.radix[pl.npass - 1] == 2 && n / 2 >= 16;
+}
+
 template <typename T>
-static int launch_lds_E(agn_ctx* ctx, int E, const LcDesc* d, int count, int nt, size_t prep_lds,
+static int launch_lds_E(agn_ctx* ctx, int E, const LcDesc* d, int count, int nt, bool fuse2, size_t prep_lds,
                         size_t iter_lds, hipStream_t st) {
     if (E >= 8 && nt % 32 != 0) return fail(AGN_EINVAL, "internal: %d-thread block for E=%d", nt, E);
     switch (E) {
-        case 1: launch_lds<T, 1>(ctx, d, count, nt, prep_lds, iter_lds, st); break;
-        case 2: launch_lds<T, 2>(ctx, d, count, nt, prep_lds, iter_lds, st); break;
-        case 3: launch_lds<T, 3>(ctx, d, count, nt, prep_lds, iter_lds, st); break;
-        case 4: launch_lds<T, 4>(ctx, d, count, nt, prep_lds, iter_lds, st); break;
-        case 6: launch_lds<T, 6>(ctx, d, count, nt, prep_lds, iter_lds, st); break;
-        case 8: launch_lds<T, 8>(ctx, d, count, nt, prep_lds, iter_lds, st); break;
+        case 1: launch_lds<T, 1>(ctx, d, count, nt, fuse2, prep_lds, iter_lds, st); break;
+        case 2: launch_lds<T, 2>(ctx, d, count, nt, fuse2, prep_lds, iter_lds, st); break;
+        case 3: launch_lds<T, 3>(ctx, d, count, nt, fuse2, prep_lds, iter_lds, st); break;
+        case 4: launch_lds<T, 4>(ctx, d, count, nt, fuse2, prep_lds, iter_lds, st); break;
+        case 6: launch_lds<T, 6>(ctx, d, count, nt, fuse2, prep_lds, iter_lds, st); break;
+        case 8: launch_lds<T, 8>(ctx, d, count, nt, fuse2, prep_lds, iter_lds, st); break;
         default: return fail(AGN_EINVAL, "internal: no kernel for E=%d", E);
     }
     return AGN_OK;
@@ -952,8 +960,9 @@ static int build_plan(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_p
 static void enqueue_group(const agn_batch_plan& pl, agn_ctx* pctx, bool is_big, int k, hipStream_t st) {
     if (!is_big) {
         const LdsGroup& g = pl.lds[k];
-        if (pl.prec == AGN_FP32) launch_lds_E<float>(pctx, g.E, pl.d_lc + g.first, g.count, g.nt, g.pl, g.il, st);
-        else launch_lds_E<double>(pctx, g.E, pl.d_lc + g.first, g.count, g.nt, g.pl, g.il, st);
+        const bool f2 = lds_fuse2(g.n);
+        if (pl.prec == AGN_FP32) launch_lds_E<float>(pctx, g.E, pl.d_lc + g.first, g.count, g.nt, f2, g.pl, g.il, st);
+        else launch_lds_E<double>(pctx, g.E, pl.d_lc + g.first, g.count, g.nt, f2, g.pl, g.il, st);
     } else {
         const BigGroup& g = pl.big[k];
         if (pl.prec == AGN_FP32)

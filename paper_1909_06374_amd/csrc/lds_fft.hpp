@@ -203,11 +203,13 @@ AGN_DEV void lds_pass(cplx<T>* buf, int M, int Ns, int tid, int nt, const TwLds&
     __syncthreads();
 }
 
-// Full transform; E = M / nt complex values per thread (compile-time bound).
+// Passes p0 .. p1-1 of the plan, starting at stride Ns0; E = M / nt complex
+// values per thread (compile-time bound).
 template <typename T, int E, bool INV>
-AGN_DEV void lds_fft(cplx<T>* buf, int M, const FftPlan& plan, int tid, int nt, const TwLds& tw) {
-    int Ns = 1;
-    for (int p = 0; p < plan.npass; ++p) {
+AGN_DEV void lds_fft_passes(cplx<T>* buf, int M, const FftPlan& plan, int p0, int p1, int Ns0, int tid, int nt,
+                            const TwLds& tw) {
+    int Ns = Ns0;
+    for (int p = p0; p < p1; ++p) {
         const int R = plan.radix[p];
         if (R == 8) lds_pass<T, 8, (E + 7) / 8, INV>(buf, M, Ns, tid, nt, tw);
         else if (R == 4) lds_pass<T, 4, (E + 3) / 4, INV>(buf, M, Ns, tid, nt, tw);
@@ -215,6 +217,12 @@ AGN_DEV void lds_fft(cplx<T>* buf, int M, const FftPlan& plan, int tid, int nt, 
         else lds_pass<T, 2, (E + 1) / 2, INV>(buf, M, Ns, tid, nt, tw);
         Ns *= R;
     }
+}
+
+// Full transform.
+template <typename T, int E, bool INV>
+AGN_DEV void lds_fft(cplx<T>* buf, int M, const FftPlan& plan, int tid, int nt, const TwLds& tw) {
+    lds_fft_passes<T, E, INV>(buf, M, plan, 0, plan.npass, 1, tid, nt, tw);
 }
 
 // Modulus replacement keeping the phase; zero modulus takes phase 0.
@@ -235,34 +243,97 @@ AGN_DEV cplx<T> replace_modulus(cplx<T> X, T a) {
 //   Z'_k    = A + i conj(W_N^k) B,       Z'_{M-k} = conj(A) + i W_N^k conj(B)
 //   A       = Y_k + conj Y_{M-k},        B = Y_k - conj Y_{M-k}
 template <typename T>
+AGN_DEV void fold_pair(cplx<T> zk, cplx<T> zm, cplx<T> w, T amp_k, T amp_m, cplx<T>* yk, cplx<T>* ym) {
+    const cplx<T> Ev = cmk((zk.re + zm.re) * (T)0.5, (zk.im - zm.im) * (T)0.5);
+    const cplx<T> Ov = cmk((zk.im + zm.im) * (T)0.5, (zm.re - zk.re) * (T)0.5);
+    const cplx<T> wO = cmul(w, Ov);
+    const cplx<T> Xk = cadd(Ev, wO);
+    const cplx<T> Xm = cconj(csub(Ev, wO));
+    const cplx<T> Yk = replace_modulus(Xk, amp_k);
+    const cplx<T> Ym = replace_modulus(Xm, amp_m);
+    const cplx<T> A = cadd(Yk, cconj(Ym));
+    const cplx<T> B = csub(Yk, cconj(Ym));
+    const cplx<T> cwB = cmul(cconj(w), B);
+    *yk = cmk(A.re - cwB.im, A.im + cwB.re);  // A + i conj(w) B
+    const cplx<T> wcB = cmul(w, cconj(B));
+    *ym = cmk(A.re - wcB.im, -A.im + wcB.re);  // conj(A) + i w conj(B)
+}
+
+// DC and Nyquist (k = 0): Y_0 = 0, Y_M = amp_M sign(Re X_M).
+template <typename T>
+AGN_DEV cplx<T> fold_dc(cplx<T> z0, cplx<T> w0, T amp_n) {
+    const cplx<T> Ev = cmk((z0.re + z0.re) * (T)0.5, (z0.im - z0.im) * (T)0.5);
+    const cplx<T> Ov = cmk((z0.im + z0.im) * (T)0.5, (z0.re - z0.re) * (T)0.5);
+    const cplx<T> wO = cmul(w0, Ov);
+    const T xn = Ev.re - wO.re;  // X_M, real for real input
+    const T yn = (xn >= (T)0) ? amp_n : -amp_n;
+    return cmk(yn, -yn);
+}
+
+template <typename T>
 AGN_DEV void lds_fold_replace(cplx<T>* Z, int M, const T* __restrict__ amp, const TwLds& tw, int tid,
                               int nthreads) {
     const int half = M / 2;
     for (int k = tid; k <= half; k += nthreads) {
         const int mk = (k == 0) ? 0 : M - k;
         const cplx<T> zk = Z[cpad<T>(k)], zm = Z[cpad<T>(mk)];
-        const cplx<T> Ev = cmk((zk.re + zm.re) * (T)0.5, (zk.im - zm.im) * (T)0.5);
-        const cplx<T> Ov = cmk((zk.im + zm.im) * (T)0.5, (zm.re - zk.re) * (T)0.5);
         const cplx<T> w = twiddle<T, false>(tw, k);
-        const cplx<T> wO = cmul(w, Ov);
         if (k == 0) {
-            const T xn = Ev.re - wO.re;  // X_M, real for real input
-            const T yn = (xn >= (T)0) ? amp[M] : -amp[M];
-            Z[cpad<T>(0)] = cmk(yn, -yn);
+            Z[cpad<T>(0)] = fold_dc(zk, w, amp[M]);
         } else {
-            const cplx<T> Xk = cadd(Ev, wO);
-            const cplx<T> Xm = cconj(csub(Ev, wO));
-            const cplx<T> Yk = replace_modulus(Xk, amp[k]);
-            const cplx<T> Ym = replace_modulus(Xm, amp[M - k]);
-            const cplx<T> A = cadd(Yk, cconj(Ym));
-            const cplx<T> B = csub(Yk, cconj(Ym));
-            const cplx<T> cwB = cmul(cconj(w), B);
-            Z[cpad<T>(k)] = cmk(A.re - cwB.im, A.im + cwB.re);  // A + i conj(w) B
-            if (mk != k) {
-                const cplx<T> wcB = cmul(w, cconj(B));
-                Z[cpad<T>(mk)] = cmk(A.re - wcB.im, -A.im + wcB.re);  // conj(A) + i w conj(B)
-            }
+            cplx<T> yk, ym;
+            fold_pair(zk, zm, w, amp[k], amp[M - k], &yk, &ym);
+            Z[cpad<T>(k)] = yk;
+            if (mk != k) Z[cpad<T>(mk)] = ym;
         }
+    }
+    __syncthreads();
+}
+
+// The forward plan's last pass is radix 2 (stride M/2), here fused with the
+// fold / replacement.  On entry Z holds A = Z[0 .. M/2) and B = Z[M/2 .. M)
+// of that pass; on return the replaced spectrum, as lds_fold_replace leaves
+// it.  For k in [0, M/4] one thread takes the pairs (k, M - k) and
+// (M/2 - k, M/2 + k), whose four spectrum values come from A and B at k and
+// M/2 - k:  Z_k = A_k + W_M^k B_k,  Z_{M/2+k} = A_k - W_M^k B_k.  It reads and
+// writes the same four positions, so no other thread's data is touched and
+// no barrier is needed between the reads and the writes.  The operations are
+// those of the separate pass and fold (the compiler may fuse multiply-adds
+// differently, so results can differ in the last bit).  Needs M >= 16.
+template <typename T>
+AGN_DEV void lds_fold_replace_r2(cplx<T>* Z, int M, const T* __restrict__ amp, const TwLds& tw, int tid,
+                                 int nt) {
+    const int h = M / 2, q = M / 4;
+    for (int k = tid; k <= q; k += nt) {
+        const cplx<T> a0 = Z[cpad<T>(k)], b0 = Z[cpad<T>(k + h)];
+        // last forward pass (radix 2): W_M^k = W_N^{2k}
+        const cplx<T> t0 = cmul(b0, twiddle<T, false>(tw, 2 * k));
+        const cplx<T> zk = cadd(a0, t0), zhk = csub(a0, t0);  // Z_k, Z_{h+k}
+        if (k == 0) {
+            cplx<T> yh, unused;
+            fold_pair(zhk, zhk, twiddle<T, false>(tw, h), amp[h], amp[h], &yh, &unused);  // self pair h
+            Z[cpad<T>(0)] = fold_dc(zk, twiddle<T, false>(tw, 0), amp[M]);
+            Z[cpad<T>(h)] = yh;
+            continue;
+        }
+        if (k == q) {
+            // (q, 3q) is its own partner: Z_{3q} = Z_{h+q}
+            cplx<T> yq, y3q;
+            fold_pair(zk, zhk, twiddle<T, false>(tw, q), amp[q], amp[M - q], &yq, &y3q);
+            Z[cpad<T>(q)] = yq;
+            Z[cpad<T>(3 * q)] = y3q;
+            continue;
+        }
+        const cplx<T> a1 = Z[cpad<T>(h - k)], b1 = Z[cpad<T>(M - k)];
+        const cplx<T> t1 = cmul(b1, twiddle<T, false>(tw, 2 * (h - k)));  // W_M^{h-k}
+        const cplx<T> zh_k = cadd(a1, t1), zm_k = csub(a1, t1);          // Z_{h-k}, Z_{M-k}
+        cplx<T> y_k, y_mk, y_hk, y_hpk;
+        fold_pair(zk, zm_k, twiddle<T, false>(tw, k), amp[k], amp[M - k], &y_k, &y_mk);
+        fold_pair(zh_k, zhk, twiddle<T, false>(tw, h - k), amp[h - k], amp[h + k], &y_hk, &y_hpk);
+        Z[cpad<T>(k)] = y_k;
+        Z[cpad<T>(M - k)] = y_mk;
+        Z[cpad<T>(h - k)] = y_hk;
+        Z[cpad<T>(h + k)] = y_hpk;
     }
     __syncthreads();
 }

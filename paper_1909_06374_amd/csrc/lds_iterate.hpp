@@ -140,7 +140,9 @@ __global__ __launch_bounds__(1024) void k_lds_prep(const LcDesc* __restrict__ de
     if (tid == 0) *d.valid = bad ? 0 : 1;
 }
 
-template <typename T, int E>
+// FUSE2: the plan ends with radix 2 (the host checks), and the forward
+// transform's last pass is fused with the replacement (lds_fold_replace_r2).
+template <typename T, int E, bool FUSE2>
 __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__ descs) {
     typedef typename key_of<T>::type K;
     constexpr int IPT = 2 * E;
@@ -205,9 +207,16 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
     int done = 0;
 #pragma unroll 1
     for (int it = 0; it < d.iters; ++it) {
-        lds_fft<T, E, false>(Zc, M, plan, tid, nt, tw);
-        lds_fold_replace<T>(Zc, M, amp, tw, tid, nt);
-        lds_fft<T, E, true>(Zc, M, plan, tid, nt, tw);
+        if constexpr (FUSE2) {
+            // the last forward pass (radix 2) runs inside the replacement
+            lds_fft_passes<T, E, false>(Zc, M, plan, 0, plan.npass - 1, 1, tid, nt, tw);
+            lds_fold_replace_r2<T>(Zc, M, amp, tw, tid, nt);
+            lds_fft<T, E, true>(Zc, M, plan, tid, nt, tw);
+        } else {
+            lds_fft<T, E, false>(Zc, M, plan, tid, nt, tw);
+            lds_fold_replace<T>(Zc, M, amp, tw, tid, nt);
+            lds_fft<T, E, true>(Zc, M, plan, tid, nt, tw);
+        }
 
         {
             K key[IPT];

@@ -26,6 +26,11 @@ def _alone(ctx, r, prec):
 def test_mixed_equals_alone(gpu_ctx, prec):
     reqs = make_requests(rate_hz=400.0, duration_s=0.1, seed=8, k_lo=10, k_hi=16, iters_lo=4, iters_hi=12)
     assert len(reqs) >= 20
+    # the first half is queued at time zero, so that the first launch takes
+    # several of them together whatever the speed of the device; the rest
+    # arrive while batches are in flight
+    for r in reqs[:len(reqs) // 2]:
+        r.arrival = 0.0
     be = GpuBackend(gpu_ctx, n_slots=3, prec=prec, keep_outputs=True)
     srv = Server(be, budget_bytes=2**33, max_batch_samples=2**17)
     st = srv.run(reqs)
