@@ -11,6 +11,7 @@ library is not built, every call raises.
 from __future__ import annotations
 
 import ctypes as C
+import functools
 import os
 
 import numpy as np
@@ -140,14 +141,60 @@ def _check(rc):
         raise AgnError(rc, lib().agn_last_error().decode())
 
 
-def _ptr(t):
+_F64 = ("torch.float64",)
+_F32 = ("torch.float32",)
+_I32 = ("torch.int32", "torch.uint32")
+_I64 = ("torch.int64", "torch.uint64")
+
+
+def _buf(t, name="tensor", dtypes=None, need=0, device=None):
+    """Device pointer of t, after checking that it is a contiguous GPU tensor
+    (on `device` if given) of one of `dtypes` with at least `need` elements.
+    The C ABI takes plain pointers and cannot see a buffer's extent, so the
+    extents it will touch are checked here; None passes through as NULL."""
     if t is None:
         return None
     if not t.is_cuda:
-        raise ValueError("expected a GPU tensor")
+        raise AgnError(AGN_EINVAL, f"{name}: expected a GPU tensor")
     if not t.is_contiguous():
-        raise ValueError("expected a contiguous tensor")
+        raise AgnError(AGN_EINVAL, f"{name}: expected a contiguous tensor")
+    if device is not None and t.device.index != device:
+        raise AgnError(AGN_EINVAL, f"{name}: tensor on cuda:{t.device.index}, context on cuda:{device}")
+    if dtypes is not None and str(t.dtype) not in dtypes:
+        raise AgnError(AGN_EINVAL, f"{name}: dtype {t.dtype}, expected {' or '.join(dtypes)}")
+    if t.numel() < need:
+        raise AgnError(AGN_EINVAL, f"{name}: {t.numel()} elements, at least {need} needed")
     return C.c_void_p(t.data_ptr())
+
+
+def _wp(prec):
+    """Tensor dtype of the working precision (None for an unknown one: the
+    library rejects it)."""
+    return _F32 if prec == AGN_FP32 else _F64 if prec == AGN_FP64 else None
+
+
+def _extent(n, offset, per=None):
+    """Elements a batch touches: max over curves of offset + per(n) (curves
+    with a negative length or offset are left to the library to reject)."""
+    n = np.asarray(n, dtype=np.int64)
+    o = np.asarray(offset, dtype=np.int64)
+    if n.size == 0:
+        return 0
+    k = n if per is None else per(n)
+    return int(np.max(np.where((o >= 0) & (n >= 0), o + k, 0)))
+
+
+@functools.lru_cache(maxsize=256)
+def _nbins_one(n, dex):
+    if not (dex > 0.0) or not agn_supported_n(n) or n < 4:
+        return 0  # the library rejects the call
+    return agn_log_bin_count(n, dex)
+
+
+def _nbins(n, dex):
+    """Log-bin counts of an array of lengths."""
+    u, inv = np.unique(np.asarray(n, dtype=np.int64), return_inverse=True)
+    return np.array([_nbins_one(int(k), float(dex)) for k in u], dtype=np.int64)[inv.reshape(-1)]
 
 
 def _stream(stream, device):
@@ -218,25 +265,34 @@ def agn_batch_workspace_size(n, prec: int) -> int:
 
 
 def agn_psd_spectrum(ctx: Context, params, n, dt, seed, curve_id, prec, amp_out, ws, stream=None):
+    dv = ctx.device
     _check(lib().agn_psd_spectrum(ctx.handle, C.byref(params), int(n), float(dt), int(seed),
-                                  int(curve_id), int(prec), _ptr(amp_out), _ptr(ws),
+                                  int(curve_id), int(prec), _buf(amp_out, "amp_out", _wp(prec), int(n) // 2 + 1, dv),
+                                  _buf(ws, "ws", None, 0, dv),
                                   ws.numel() * ws.element_size(), _stream(stream, ctx.device)))
 
 
 def agn_lc_iterate(ctx: Context, amp, x0, n, iters, tol, prec, x_out, delta_out=None,
                    iters_done=None, rank_out=None, ws=None, stream=None):
-    _check(lib().agn_lc_iterate(ctx.handle, _ptr(amp), _ptr(x0), int(n), int(iters), float(tol),
-                                int(prec), _ptr(x_out), _ptr(delta_out), _ptr(iters_done),
-                                _ptr(rank_out), _ptr(ws),
+    dv, k = ctx.device, max(int(n), 0)
+    _check(lib().agn_lc_iterate(ctx.handle, _buf(amp, "amp", _wp(prec), k // 2 + 1, dv),
+                                _buf(x0, "x0", _F64, k, dv), int(n), int(iters), float(tol),
+                                int(prec), _buf(x_out, "x_out", _F64, k, dv),
+                                _buf(delta_out, "delta_out", _F64, max(int(iters), 0), dv),
+                                _buf(iters_done, "iters_done", _I32, 1, dv),
+                                _buf(rank_out, "rank_out", _I32, k, dv), _buf(ws, "ws", None, 0, dv),
                                 0 if ws is None else ws.numel() * ws.element_size(),
                                 _stream(stream, ctx.device)))
 
 
 def agn_lc_generate(ctx: Context, params, erdf, n, dt, iters, tol, seed, curve_id, prec, x_out,
                     delta_out=None, iters_done=None, ws=None, stream=None):
-    _check(lib().agn_lc_generate(ctx.handle, C.byref(params), _ptr(erdf), int(n), float(dt),
+    dv, k = ctx.device, max(int(n), 0)
+    _check(lib().agn_lc_generate(ctx.handle, C.byref(params), _buf(erdf, "erdf", _F64, k, dv), int(n), float(dt),
                                  int(iters), float(tol), int(seed), int(curve_id), int(prec),
-                                 _ptr(x_out), _ptr(delta_out), _ptr(iters_done), _ptr(ws),
+                                 _buf(x_out, "x_out", _F64, k, dv),
+                                 _buf(delta_out, "delta_out", _F64, max(int(iters), 0), dv),
+                                 _buf(iters_done, "iters_done", _I32, 1, dv), _buf(ws, "ws", None, 0, dv),
                                  0 if ws is None else ws.numel() * ws.element_size(),
                                  _stream(stream, ctx.device)))
 
@@ -257,9 +313,21 @@ def agn_lc_generate_batch(ctx: Context, n, offset, params, dt, iters, seed, curv
     _check(lib().agn_lc_generate_batch(
         ctx.handle, nc, n.ctypes.data_as(vp), offset.ctypes.data_as(vp), C.cast(parr, vp),
         dt.ctypes.data_as(vp), iters.ctypes.data_as(vp), seed.ctypes.data_as(vp),
-        curve_id.ctypes.data_as(vp), _ptr(erdf), float(tol), int(prec), _ptr(x_out),
-        _ptr(delta_out), _ptr(iters_done), _ptr(ws),
-        0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, ctx.device)))
+        curve_id.ctypes.data_as(vp), *_batch_bufs(ctx, n, offset, iters, erdf, x_out, delta_out, iters_done, tol,
+                                                  prec),
+        _buf(ws, "ws", None, 0, ctx.device), 0 if ws is None else ws.numel() * ws.element_size(),
+        _stream(stream, ctx.device)))
+
+
+def _batch_bufs(ctx, n, offset, iters, erdf, x_out, delta_out, iters_done, tol, prec, *extra):
+    """The device-buffer arguments shared by the batch entry points, checked
+    against the extents the batch touches."""
+    dv = ctx.device
+    ext = _extent(n, offset)
+    rows = len(n) * (int(np.max(iters)) if len(iters) else 0)
+    return (_buf(erdf, "erdf", _F64, ext, dv), float(tol), int(prec), _buf(x_out, "x_out", _F64, ext, dv),
+            _buf(delta_out, "delta_out", _F64, max(rows, 0), dv), _buf(iters_done, "iters_done", _I32, len(n), dv),
+            *[int(e) for e in extra])
 
 
 AGN_PLAN_GRAPH = 1
@@ -312,9 +380,10 @@ def agn_batch_plan_create(ctx: Context, n, offset, params, dt, iters, seed, curv
     _check(lib().agn_batch_plan_create(
         ctx.handle, nc, n.ctypes.data_as(vp), offset.ctypes.data_as(vp), C.cast(parr, vp),
         dt.ctypes.data_as(vp), iters.ctypes.data_as(vp), seed.ctypes.data_as(vp),
-        curve_id.ctypes.data_as(vp), _ptr(erdf), float(tol), int(prec), _ptr(x_out),
-        _ptr(delta_out), _ptr(iters_done), int(flags), int(branches), _ptr(ws),
-        0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, ctx.device), C.byref(out)))
+        curve_id.ctypes.data_as(vp), *_batch_bufs(ctx, n, offset, iters, erdf, x_out, delta_out, iters_done, tol,
+                                                  prec, flags, branches),
+        _buf(ws, "ws", None, 0, ctx.device), 0 if ws is None else ws.numel() * ws.element_size(),
+        _stream(stream, ctx.device), C.byref(out)))
     return BatchPlan(ctx, out, (erdf, x_out, delta_out, iters_done, ws))
 
 
@@ -346,9 +415,13 @@ def agn_periodogram_batch(ctx: Context, n, offset, x, p_offset, P_out, dex=0.0, 
     offset = np.ascontiguousarray(offset, dtype=np.int64)
     p_offset = np.ascontiguousarray(p_offset, dtype=np.int64)
     bo = None if b_offset is None else np.ascontiguousarray(b_offset, dtype=np.int64)
+    dv = ctx.device
     _check(lib().agn_periodogram_batch(
-        ctx.handle, nc, n.ctypes.data_as(vp), offset.ctypes.data_as(vp), _ptr(x), p_offset.ctypes.data_as(vp),
-        _ptr(P_out), float(dex), None if bo is None else bo.ctypes.data_as(vp), _ptr(bins_out), _ptr(ws),
+        ctx.handle, nc, n.ctypes.data_as(vp), offset.ctypes.data_as(vp), _buf(x, "x", _F64, _extent(n, offset), dv),
+        p_offset.ctypes.data_as(vp), _buf(P_out, "P_out", _F64, _extent(n, p_offset, lambda k: k // 2 + 1), dv),
+        float(dex), None if bo is None else bo.ctypes.data_as(vp),
+        _buf(bins_out, "bins_out", _F64, 0 if bo is None else _extent(n, bo, lambda k: _nbins(k, float(dex))), dv),
+        _buf(ws, "ws", None, 0, dv),
         0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, ctx.device)))
 
 
@@ -370,8 +443,11 @@ def agn_psd_fit_batch(ctx: Context, n, dt, params, dex, b_offset, bins, fit_out,
     dt = np.ascontiguousarray(dt, dtype=np.float64)
     bo = np.ascontiguousarray(b_offset, dtype=np.int64)
     parr = (agn_psd_params * max(nc, 1))(*params)
+    dv = ctx.device
     _check(lib().agn_psd_fit_batch(ctx.handle, nc, n.ctypes.data_as(vp), dt.ctypes.data_as(vp), parr, float(dex),
-                                   bo.ctypes.data_as(vp), _ptr(bins), _ptr(fit_out), _ptr(ws),
+                                   bo.ctypes.data_as(vp),
+                                   _buf(bins, "bins", _F64, _extent(n, bo, lambda k: _nbins(k, float(dex))), dv),
+                                   _buf(fit_out, "fit_out", _F64, 4 * nc, dv), _buf(ws, "ws", None, 0, dv),
                                    0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, ctx.device)))
 
 
@@ -393,29 +469,36 @@ def agn_lag_stats_batch(ctx: Context, n, offset, x, lags, units=AGN_SF_LINEAR, s
     offset = np.ascontiguousarray(offset, dtype=np.int64)
     lags = np.ascontiguousarray(lags, dtype=np.int64)
     dm = np.ascontiguousarray(dm_ref, dtype=np.float64)
+    dv, items = ctx.device, len(n) * len(lags)
     _check(lib().agn_lag_stats_batch(
-        ctx.handle, len(n), n.ctypes.data_as(vp), offset.ctypes.data_as(vp), _ptr(x), len(lags),
-        lags.ctypes.data_as(vp), int(units), _ptr(sf2_out), _ptr(rep_out), len(dm),
-        dm.ctypes.data_as(vp) if len(dm) else None, float(lam_cut), _ptr(exceed_out), _ptr(pairs_out), _ptr(ws),
+        ctx.handle, len(n), n.ctypes.data_as(vp), offset.ctypes.data_as(vp), _buf(x, "x", _F64, _extent(n, offset), dv),
+        len(lags), lags.ctypes.data_as(vp), int(units), _buf(sf2_out, "sf2_out", _F64, items, dv),
+        _buf(rep_out, "rep_out", _F64, len(lags), dv), len(dm), dm.ctypes.data_as(vp) if len(dm) else None,
+        float(lam_cut), _buf(exceed_out, "exceed_out", _I64, items * len(dm), dv),
+        _buf(pairs_out, "pairs_out", _I64, items, dv), _buf(ws, "ws", None, 0, dv),
         0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, ctx.device)))
 
 
 def agn_erdf_draw(ctx: Context, params, n, seed, curve_id, out, stream=None):
-    _check(lib().agn_erdf_draw(ctx.handle, C.byref(params), int(n), int(seed), int(curve_id), _ptr(out),
+    _check(lib().agn_erdf_draw(ctx.handle, C.byref(params), int(n), int(seed), int(curve_id),
+                               _buf(out, "out", _F64, max(int(n), 0), ctx.device),
                                _stream(stream, ctx.device)))
 
 
 def agn_pdf_draw(ctx: Context, params, n, seed, curve_id, out, stream=None):
-    _check(lib().agn_pdf_draw(ctx.handle, C.byref(params), int(n), int(seed), int(curve_id), _ptr(out),
+    _check(lib().agn_pdf_draw(ctx.handle, C.byref(params), int(n), int(seed), int(curve_id),
+                              _buf(out, "out", _F64, max(int(n), 0), ctx.device),
                               _stream(stream, ctx.device)))
 
 
 def agn_pdf_slice(ctx: Context, params, n, n_chains, burn, seed, curve_id, out, stream=None):
     _check(lib().agn_pdf_slice(ctx.handle, C.byref(params), int(n), int(n_chains), int(burn), int(seed),
-                               int(curve_id), _ptr(out), _stream(stream, ctx.device)))
+                               int(curve_id), _buf(out, "out", _F64, max(int(n), 0), ctx.device),
+                               _stream(stream, ctx.device)))
 
 
 def agn_test_philox(key0, key1, ctr0, n_blocks, out, stream=None, device=0):
     _check(lib().agn_test_philox(int(key0) & (2**64 - 1), int(key1) & (2**64 - 1),
-                                 int(ctr0) & (2**64 - 1), int(n_blocks), _ptr(out),
+                                 int(ctr0) & (2**64 - 1), int(n_blocks),
+                                 _buf(out, "out", _I64, 4 * max(int(n_blocks), 0), device),
                                  _stream(stream, device)))

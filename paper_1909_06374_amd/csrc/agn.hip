@@ -211,7 +211,10 @@ struct ProfScope {
         if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, st) == hipSuccess) {
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->prof_recs.push_back({name, a, b});
+            return;
         }
+        if (b) (void)hipEventDestroy(b);
+        (void)hipEventDestroy(a);
     }
 };
 
@@ -261,7 +264,11 @@ static int get_twiddles(agn_ctx* ctx, int64_t n, agn_precision prec, const void*
             t[2 * i] = (float)c;
             t[2 * i + 1] = (float)(-s);
         }
-        HIPCHK(hipMemcpy(dptr, t.data(), bytes, hipMemcpyHostToDevice));
+        const hipError_t e = hipMemcpy(dptr, t.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(dptr);
+            return fail(AGN_EDEVICE, "twiddle table upload: %s", hipGetErrorString(e));
+        }
     } else {
         std::vector<double> t(2 * h);
         for (int64_t i = 0; i < h; ++i) {
@@ -270,7 +277,11 @@ static int get_twiddles(agn_ctx* ctx, int64_t n, agn_precision prec, const void*
             t[2 * i] = c;
             t[2 * i + 1] = -s;
         }
-        HIPCHK(hipMemcpy(dptr, t.data(), bytes, hipMemcpyHostToDevice));
+        const hipError_t e = hipMemcpy(dptr, t.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(dptr);
+            return fail(AGN_EDEVICE, "twiddle table upload: %s", hipGetErrorString(e));
+        }
     }
     ctx->tw[key] = dptr;
     *out = dptr;
@@ -288,6 +299,7 @@ static int stage_upload(agn_ctx* ctx, void* dst, const void* src, size_t bytes, 
     if (s.cap < bytes) {
         if (s.host) HIPCHK(hipHostFree(s.host));
         s.host = nullptr;
+        s.cap = 0;  // stays empty if the allocation below fails
         const size_t cap = std::max(bytes, (size_t)4096);
         HIPCHK(hipHostMalloc(&s.host, cap, hipHostMallocDefault));
         s.cap = cap;
@@ -516,7 +528,11 @@ static int get_tw64(agn_ctx* ctx, int64_t n, TwTable* out) {
     const size_t bytes = t.size() * sizeof(double);
     if (hipMalloc(&dptr, bytes) != hipSuccess)
         return fail(AGN_ENOMEM, "twiddle table allocation of %zu bytes failed", bytes);
-    HIPCHK(hipMemcpy(dptr, t.data(), bytes, hipMemcpyHostToDevice));
+    const hipError_t e = hipMemcpy(dptr, t.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(dptr);
+        return fail(AGN_EDEVICE, "twiddle table upload: %s", hipGetErrorString(e));
+    }
     TwTable tb;
     tb.lo = (const cplx<double>*)dptr;
     tb.hi = (const cplx<double>*)dptr + nlo;

@@ -349,13 +349,19 @@ struct SortPass {
 };
 
 // grid: (ntiles, curves), block 256.  hist[d * ntiles + tile] = count of digit d.
-// All loads of a thread are issued before its counting; each wave counts into
-// its own LDS histogram (fewer colliding atomics when few digits dominate).
+// All loads of a thread are issued before its counting.  Each wave counts
+// into HIST_COPIES LDS histograms, lane l into copy l mod HIST_COPIES, rows
+// padded to 257 words so that equal digits of different copies fall in
+// different banks: when a few digits dominate (the exponent byte of the
+// keys), fewer lanes of one atomic instruction collide.
+constexpr int HIST_COPIES = 4;
+
 template <typename K, int TILE>
 __global__ __launch_bounds__(BIG_THREADS) void k_sort_hist(const BigCurve* __restrict__ cv, SortPass P,
                                                            int64_t ntiles) {
     constexpr int IPT = TILE / BIG_THREADS;
-    __shared__ uint32_t h[BIG_THREADS / 64][256];
+    constexpr int ROWS = BIG_THREADS / 64 * HIST_COPIES;
+    __shared__ uint32_t h[ROWS * 257];
     const BigCurve& d = cv[blockIdx.y];
     if (d.state[1] == 0) return;
     const int tid = threadIdx.x, wave = tid >> 6;
@@ -365,14 +371,15 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sort_hist(const BigCurve* __res
 #pragma unroll
     for (int i = 0; i < IPT; ++i) k[i] = keys[base + i * BIG_THREADS + tid];
 #pragma unroll
-    for (int w = 0; w < BIG_THREADS / 64; ++w) h[w][tid] = 0;
+    for (int w = 0; w < ROWS; ++w) h[w * 257 + tid] = 0;
     __syncthreads();
+    uint32_t* mine = h + (wave * HIST_COPIES + (tid & (HIST_COPIES - 1))) * 257;
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) atomicAdd(&h[wave][(uint32_t)(k[i] >> P.shift) & 255u], 1u);
+    for (int i = 0; i < IPT; ++i) atomicAdd(&mine[(uint32_t)(k[i] >> P.shift) & 255u], 1u);
     __syncthreads();
     uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < BIG_THREADS / 64; ++w) c += h[w][tid];
+    for (int w = 0; w < ROWS; ++w) c += h[w * 257 + tid];
     d.hist[(int64_t)tid * ntiles + blockIdx.x] = c;
 }
 
