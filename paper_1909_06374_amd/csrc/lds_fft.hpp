@@ -166,15 +166,16 @@ AGN_DEV void lds_pass(cplx<T>* buf, int M, int Ns, int tid, int nt, const TwLds&
             if (Ns > 1) {
                 const int jm = pow2 ? (j & (Ns - 1)) : (j % Ns);
                 // W^{t r} for r = 1..R-1 as powers of W^t, formed by double-precision
-                // products (at most R - 2 of them) and rounded once to T.
+                // products (R - 2 of them) and rounded once to T.  Power r is
+                // the product of the powers floor(r / 2) and r - floor(r / 2), so
+                // the chain of dependent products is log2(R) deep, not R - 2.
                 const int t1 = jm * tstep;
-                const cplx<double> w1 = cmul(tw.hi[t1 >> tw.bits], tw.lo[t1 & ((1 << tw.bits) - 1)]);
-                cplx<double> wr = w1;
+                cplx<double> wp[R];
+                wp[1] = cmul(tw.hi[t1 >> tw.bits], tw.lo[t1 & ((1 << tw.bits) - 1)]);
 #pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    w[b][r] = cmk((T)wr.re, (T)(INV ? -wr.im : wr.im));
-                    wr = cmul(wr, w1);
-                }
+                for (int r = 2; r < R; ++r) wp[r] = cmul(wp[r / 2], wp[r - r / 2]);
+#pragma unroll
+                for (int r = 1; r < R; ++r) w[b][r] = cmk((T)wp[r].re, (T)(INV ? -wp[r].im : wp[r].im));
             }
         }
     }

@@ -274,7 +274,9 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
             for (int j = 0; j < IPT / 2; ++j)
                 idx2[j] = (uint32_t)(tk * IPT + 2 * j) | ((uint32_t)(tk * IPT + 2 * j + 1) << 16);
             __syncthreads();
-            block_radix_sort<K, IPT, true, sizeof(T) == 4 ? 30 : 8 * (int)sizeof(K)>(key, idx2, smem, ibuf, scratch);
+            // FP32 form: indices < N <= 2^14 ride in the key word for the last passes
+            block_radix_sort<K, IPT, true, sizeof(T) == 4 ? 30 : 8 * (int)sizeof(K), sizeof(T) == 4 ? 14 : 0>(
+                key, idx2, smem, ibuf, scratch);
         }
 
         // x_i[t] = s[k]; Eq. 4 terms from the log10 table.  The exact

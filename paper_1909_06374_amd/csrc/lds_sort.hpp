@@ -13,6 +13,11 @@
 // (digit, thread) order; adding the low-half total to every high half puts
 // digits 16..31 after digits 0..15.  Every pass is therefore stable, and so is
 // the whole sort.
+//
+// Packed tail (IB > 0, 32-bit keys): once the key bits still to be sorted and
+// an IB-bit index fit in one word, each key is replaced by
+// (remaining key bits) << IB | index, and the later passes move that single
+// word instead of a key and a separate 16-bit index.
 #pragma once
 #include "common.hpp"
 
@@ -97,13 +102,31 @@ __host__ __device__ inline size_t sort_ibuf_bytes(int n) {
 // when IPT divides the pad period, the read-back addresses of a thread's
 // IPT keys and IPT/2 index words are a per-thread base plus i (or j).  The
 // addresses are the same as the padded formulas, with fewer instructions.
-template <typename K, int IPT, bool SEP, bool ALIGNED, int KBITS>
+// Passes after which a 32-bit key and an IB-bit index are packed into one
+// word (NPASS: never).
+template <typename K, int KBITS, int IB>
+constexpr int sort_pack_at() {
+    constexpr int NPASS = (KBITS + SORT_RB - 1) / SORT_RB;
+    if (IB <= 0 || sizeof(K) != 4) return NPASS;
+    for (int j = 1; j < NPASS; ++j)
+        if (KBITS - SORT_RB * j + IB <= 32) return j;
+    return NPASS;
+}
+
+template <typename K, int IPT, bool SEP, bool ALIGNED, int KBITS, int IB>
 AGN_DEV void block_radix_sort_impl(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned char* work,
                                    uint16_t* ibuf, uint32_t* scratch) {
     static_assert(IPT % 2 == 0, "IPT must be even");
     static_assert(KBITS >= 1 && KBITS <= 8 * (int)sizeof(K), "key bits out of range");
     const int T = blockDim.x;
     constexpr int NPASS = (KBITS + SORT_RB - 1) / SORT_RB;
+    constexpr int PACK_AT = sort_pack_at<K, KBITS, IB>();
+    static_assert(PACK_AT == NPASS || SEP, "the packed tail is built for separate key and index regions");
+    static_assert(IB >= 0 && IB <= 16, "indices are 16-bit");
+    constexpr bool PACK = PACK_AT < NPASS;
+    constexpr int PSH = PACK ? SORT_RB * PACK_AT : 0;  // key bits already sorted when packing
+    constexpr int PIB = PACK ? IB : 0;
+    constexpr uint32_t IMASK = PACK ? (1u << IB) - 1u : 0u;
     constexpr int KPER = sizeof(K) == 4 ? 32 : 16;  // key pad period
     constexpr bool KFAST = (KPER % IPT) == 0;
     constexpr bool IFAST = (32 % (IPT / 2)) == 0;
@@ -116,7 +139,8 @@ AGN_DEV void block_radix_sort_impl(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], uns
     for (int pass = 0; pass < NPASS; ++pass) {
         const int t = opaque((int)threadIdx.x);
         const int tb = t + (t >> 5);
-        const int shift = pass * SORT_RB;
+        // packed words hold the key bits from SORT_RB * PACK_AT up, above the index
+        const int shift = pass < PACK_AT ? pass * SORT_RB : PIB + (pass - PACK_AT) * SORT_RB;
 #pragma unroll
         for (int l = 0; l < SORT_LANES; ++l) cnt[ALIGNED ? l * Tp + tb : wpad(l * T + t)] = 0u;
         // pos[i]: bits 0..15 running position, bits 16..20 the digit.
@@ -166,7 +190,22 @@ AGN_DEV void block_radix_sort_impl(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], uns
         const int kbase = KFAST ? t * IPT + (t * IPT) / KPER : 0;
         const int ibase = IFAST ? t * (IPT / 2) + (t * (IPT / 2)) / 32 : 0;
         if (SEP) {
-            if (!last) {
+            if (PACK && pass >= PACK_AT) {
+                // packed word in, packed word out (the last pass keeps the index)
+                if (!last) {
+#pragma unroll
+                    for (int i = 0; i < IPT; ++i) kb[kpad<K>((int)pos[i])] = key[i];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < IPT; ++i) ibuf[hpad((int)pos[i])] = (uint16_t)((uint32_t)key[i] & IMASK);
+                }
+            } else if (PACK && pass + 1 == PACK_AT) {
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) {
+                    const uint32_t ix = (i & 1) ? (idx2[i / 2] >> 16) : (idx2[i / 2] & 0xFFFFu);
+                    kb[kpad<K>((int)pos[i])] = (K)((((uint32_t)key[i] >> PSH) << PIB) | ix);
+                }
+            } else if (!last) {
 #pragma unroll
                 for (int i = 0; i < IPT; ++i) {
                     kb[kpad<K>((int)pos[i])] = key[i];
@@ -181,8 +220,11 @@ AGN_DEV void block_radix_sort_impl(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], uns
             if (!last) {
 #pragma unroll
                 for (int i = 0; i < IPT; ++i) key[i] = kb[KFAST ? kbase + i : kpad<K>(t * IPT + i)];
+                if (!PACK || pass + 1 < PACK_AT) {
 #pragma unroll
-                for (int j = 0; j < IPT / 2; ++j) idx2[j] = ibuf32[IFAST ? ibase + j : wpad((t * IPT) / 2 + j)];
+                    for (int j = 0; j < IPT / 2; ++j)
+                        idx2[j] = ibuf32[IFAST ? ibase + j : wpad((t * IPT) / 2 + j)];
+                }
                 __syncthreads();
             }
         } else {
@@ -209,19 +251,22 @@ AGN_DEV void block_radix_sort_impl(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], uns
 
 // IPT 16 is used only with 1024-thread blocks (the host checks that the
 // block size is a multiple of 32 for it), so only the aligned form is built.
-// Keys use their low KBITS bits (all others must be zero).
-template <typename K, int IPT, bool SEP, int KBITS = 8 * (int)sizeof(K)>
+// Keys use their low KBITS bits (all others must be zero).  IB > 0: every
+// index is below 2^IB, and the tail passes move packed words (32-bit keys).
+template <typename K, int IPT, bool SEP, int KBITS = 8 * (int)sizeof(K), int IB = 0>
 AGN_DEV void block_radix_sort(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned char* work,
                               uint16_t* ibuf, uint32_t* scratch) {
     if constexpr (IPT >= 16) {
-        block_radix_sort_impl<K, IPT, SEP, true, KBITS>(key, idx2, work, ibuf, scratch);
+        block_radix_sort_impl<K, IPT, SEP, true, KBITS, IB>(key, idx2, work, ibuf, scratch);
     } else if constexpr (sizeof(K) == 8) {
         // 64-bit keys (one-time draw sort, FP64 path): one general form keeps
         // register pressure low
-        block_radix_sort_impl<K, IPT, SEP, false, KBITS>(key, idx2, work, ibuf, scratch);
+        block_radix_sort_impl<K, IPT, SEP, false, KBITS, IB>(key, idx2, work, ibuf, scratch);
     } else {
-        if ((blockDim.x & 31) == 0) block_radix_sort_impl<K, IPT, SEP, true, KBITS>(key, idx2, work, ibuf, scratch);
-        else block_radix_sort_impl<K, IPT, SEP, false, KBITS>(key, idx2, work, ibuf, scratch);
+        if ((blockDim.x & 31) == 0)
+            block_radix_sort_impl<K, IPT, SEP, true, KBITS, IB>(key, idx2, work, ibuf, scratch);
+        else
+            block_radix_sort_impl<K, IPT, SEP, false, KBITS, IB>(key, idx2, work, ibuf, scratch);
     }
 }
 
