@@ -143,7 +143,7 @@ def fp32_expected_agreement(amp, xin, n, c=2.0):
     return 1.0 - 2.0 * np.sum(0.5 * erfc(g / (2 * s))) / n
 
 
-@pytest.mark.parametrize("n", [1024, 4096, 8192, 2**14, 12288])
+@pytest.mark.parametrize("n", [2, 6, 8, 24, 96, 384, 1536, 1024, 4096, 8192, 2**14, 12288])
 def test_fp32_one_step_rank_agreement(gpu_ctx, n):
     """Both paths fed the same x_{i-1}: exact-rank agreement of one iteration,
     >= 99.9%, or the FP32 round-off model's expectation where the gaps between
