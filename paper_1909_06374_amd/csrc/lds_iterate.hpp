@@ -72,6 +72,15 @@ __host__ __device__ inline size_t lds_prep_layout(int N, int nt, size_t* scratch
     return work + 128 * 4;
 }
 
+// Value of x in lane l (l uniform over the wave).
+AGN_DEV uint32_t read_lane(uint32_t x, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)x, l); }
+AGN_DEV double read_lane(double x, int l) {
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // Deterministic block sum (fixed butterfly + fixed wave order).
 template <typename V>
 AGN_DEV V block_sum(V v, V* scratch /* >= 64 */) {
@@ -91,8 +100,13 @@ AGN_DEV V block_sum(V v, V* scratch /* >= 64 */) {
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     if (lane == 0) scratch[wave] = v;
     __syncthreads();
-    V t = scratch[0];
-    for (int w = 1; w < nw; ++w) t += scratch[w];
+    // lane w loads wave w's partial (one load per lane, no waits in a loop);
+    // the partials are then added in wave order from the lanes
+    const V s = lane < nw ? scratch[lane] : V(0);
+    V t = read_lane(s, 0);
+#pragma unroll
+    for (int w = 1; w < 16; ++w)
+        if (w < nw) t += read_lane(s, w);
     __syncthreads();
     return t;
 }
@@ -252,14 +266,21 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
                         mn = fminf(mn, __shfl_xor(mn, o, 64));
                         mx = fmaxf(mx, __shfl_xor(mx, o, 64));
                     }
+                    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: no VGPR to keep
                     if ((tid & 63) == 0) {
-                        fs[tid >> 6] = mn;
-                        fs[32 + (tid >> 6)] = mx;
+                        fs[wv] = mn;
+                        fs[32 + wv] = mx;
                     }
                     __syncthreads();
-                    for (int w = 0; w < (nt >> 6); ++w) {
-                        mn = fminf(mn, fs[w]);
-                        mx = fmaxf(mx, fs[32 + w]);
+                    // lane w loads wave w's extremes (lanes past the last wave
+                    // repeat wave 0's), then the same butterfly across lanes
+                    const int l = (tid & 63) < (nt >> 6) ? (tid & 63) : 0;
+                    mn = fs[l];
+                    mx = fs[32 + l];
+#pragma unroll
+                    for (int o = 32; o >= 1; o >>= 1) {
+                        mn = fminf(mn, __shfl_xor(mn, o, 64));
+                        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
                     }
                 }
                 const double lo = (double)mn, rng = (double)mx - lo;

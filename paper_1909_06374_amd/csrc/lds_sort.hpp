@@ -39,9 +39,13 @@ AGN_DEV uint32_t wave_inclusive_scan(uint32_t x) {
 }
 
 // Exclusive scan of one uint32 per thread over the block (fixed order).
-// One barrier: every wave publishes its total, then every thread adds the
-// totals of the waves before its own.  The caller must not overwrite
-// scratch[0 .. nw) until every thread has returned (a later barrier).
+// One barrier: every wave publishes its total; then lane l of every wave
+// loads the total of wave l, and a scan across the lanes gives each wave the
+// sum of the totals before it (read from lane wave - 1) and the block total
+// (lane nw - 1).  One load per lane instead of a loop that waits for each
+// word in turn: right after the barrier every wave is here, so such waits
+// would leave the SIMDs idle.  The caller must not overwrite scratch[0 .. nw)
+// until every thread has returned (a later barrier).
 AGN_DEV uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= nw words */,
                                       uint32_t* total) {
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -50,13 +54,9 @@ AGN_DEV uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= nw wor
     const int last = (nt - (wave << 6) < 64) ? (nt - (wave << 6) - 1) : 63;
     if (lane == last) scratch[wave] = inc;
     __syncthreads();
-    uint32_t pre = 0, tot = 0;
-    for (int w = 0; w < nw; ++w) {
-        const uint32_t t = scratch[w];
-        pre += (w < wave) ? t : 0u;
-        tot += t;
-    }
-    if (total) *total = tot;
+    const uint32_t ti = wave_inclusive_scan(lane < nw ? scratch[lane] : 0u);
+    const uint32_t pre = wave > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)ti, wave - 1) : 0u;
+    if (total) *total = (uint32_t)__builtin_amdgcn_readlane((int)ti, nw - 1);
     return pre + inc - v;
 }
 
