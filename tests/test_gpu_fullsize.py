@@ -1,0 +1,115 @@
+"""GPU checks at the full sizes of the two batch workloads, in the launch
+configurations the benchmark times:
+
+- the PTF-like batch: 1024 curves x 2^14, per-curve Eq. 3 parameters,
+  100 iterations in the FP32 form, one agn_lc_generate_batch call;
+- the uneven batch: 8192 curves of lengths 2^10 .. 2^20 (powers of two and
+  3 * 2^k), PDF draws made on the device, 100 FP32 iterations, one graph
+  plan with the autotuner.
+
+The oracle cannot run these whole.  Properties that hold at any size are
+checked on every curve (each output is an exact permutation of its own
+draw, every curve ran all its iterations, every delta is finite), and
+sampled curves are compared with the FP64 oracle: the FP32 trajectories part
+from FP64 after enough iterations (sample pairs swap at the FP32 round-off),
+so the comparison is the log-binned periodogram of the final curve, to the
+same bar as the 2^14 end-to-end test.  The plan's graph replay must also
+equal a plain batch call bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_06374_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def agn():
+    import paper_1909_06374_amd as m
+    return m
+
+
+def test_ptf_batch_full_size(gpu_ctx):
+    m = agn()
+    n_curves, n, iters = 1024, 2**14, 100
+    w = synth.ptf_batch(n_curves=n_curves, n=n, seed=1)
+    params = [m.psd_params(0.0, w["f_br"][c], w["a_low"][c], w["a_high"][c]) for c in range(n_curves)]
+    ns = [n] * n_curves
+    offs = [c * n for c in range(n_curves)]
+    seeds = [1000 + c for c in range(n_curves)]
+    ids = list(range(n_curves))
+    e = torch.as_tensor(w["erdf"].reshape(-1)).to("cuda:0")
+    x = torch.empty(n_curves * n, dtype=torch.float64, device="cuda:0")
+    d = torch.full((n_curves * iters,), float("nan"), dtype=torch.float64, device="cuda:0")
+    done = torch.full((n_curves,), -1, dtype=torch.int32, device="cuda:0")
+    ws = torch.empty(m.agn_batch_workspace_size(ns, m.AGN_FP32), dtype=torch.uint8, device="cuda:0")
+    print(f"full size: PTF-like batch {n_curves} x {n}, {iters} iterations, FP32", flush=True)
+    m.agn_lc_generate_batch(gpu_ctx, ns, offs, params, [1.0] * n_curves, [iters] * n_curves, seeds, ids, e,
+                            -1.0, m.AGN_FP32, x, d, done, ws)
+    torch.cuda.synchronize()
+    xh = x.cpu().numpy().reshape(n_curves, n)
+    dh = d.cpu().numpy().reshape(n_curves, iters)
+    assert np.array_equal(np.sort(xh, axis=1), np.sort(w["erdf"], axis=1))
+    assert np.all(done.cpu().numpy() == iters)
+    assert np.all(np.isfinite(dh)) and np.all(dh >= 0)
+    for c in (0, 517, n_curves - 1):
+        pp = oracle.psd_params(0.0, w["f_br"][c], w["a_low"][c], w["a_high"][c])
+        xr, dr, _, _ = oracle.generate(pp, w["erdf"][c], 1.0, iters, seeds[c], ids[c])
+        _, a = oracle.log_binned(oracle.periodogram(xr), n, 1.0)
+        _, b = oracle.log_binned(oracle.periodogram(xh[c]), n, 1.0)
+        assert np.all(np.abs(np.log10(b / a)) < 0.1), (c, np.max(np.abs(np.log10(b / a))))
+
+
+def test_uneven_batch_full_size_plan(gpu_ctx):
+    m = agn()
+    torch.cuda.empty_cache()  # about 120 GB of device memory below
+    n_curves, iters, seed = 8192, 100, 3
+    ns = [int(v) for v in synth.uneven_sizes(n_curves, seed)]
+    a_low, a_high, f_b = synth.curve_params(n_curves, seed)
+    params = [m.psd_params(0.0, f_b[c], a_low[c], a_high[c]) for c in range(n_curves)]
+    offs = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
+    total = int(np.sum(ns))
+    seeds = [1000 + c for c in range(n_curves)]
+    ids = list(range(n_curves))
+    print(f"full size: uneven batch {n_curves} curves, sum N = {total}, {iters} iterations, FP32 graph plan",
+          flush=True)
+    e = torch.empty(total, dtype=torch.float64, device="cuda:0")
+    ep = m.erdf_params()
+    for c in range(n_curves):
+        m.agn_erdf_draw(gpu_ctx, ep, ns[c], seed, c, e[int(offs[c]):int(offs[c]) + ns[c]])
+    x = torch.empty(total, dtype=torch.float64, device="cuda:0")
+    d = torch.full((n_curves * iters,), float("nan"), dtype=torch.float64, device="cuda:0")
+    done = torch.full((n_curves,), -1, dtype=torch.int32, device="cuda:0")
+    ws = torch.empty(m.agn_batch_workspace_size(ns, m.AGN_FP32), dtype=torch.uint8, device="cuda:0")
+    plan = m.agn_batch_plan_create(gpu_ctx, ns, offs, params, [1.0] * n_curves, [iters] * n_curves, seeds, ids,
+                                   e, -1.0, m.AGN_FP32, x, d, done,
+                                   flags=m.AGN_PLAN_GRAPH | m.AGN_PLAN_AUTOTUNE, ws=ws)
+    m.agn_batch_plan_launch(plan)
+    torch.cuda.synchronize()
+    assert np.all(done.cpu().numpy() == iters)
+    dh = d.cpu().numpy()
+    assert np.all(np.isfinite(dh)) and np.all(dh >= 0)
+    # sampled curves: every length once (the first curve of each), plus random ones
+    rng = np.random.default_rng(8)
+    first = {}
+    for c, nn in enumerate(ns):
+        first.setdefault(nn, c)
+    sample = sorted(set(first.values()) | set(rng.integers(0, n_curves, 24).tolist()))
+    for c in sample:
+        lo, hi = int(offs[c]), int(offs[c]) + ns[c]
+        xs = np.sort(x[lo:hi].cpu().numpy())
+        es = np.sort(e[lo:hi].cpu().numpy())
+        assert np.array_equal(xs, es), (c, ns[c])
+    # the graph replay equals one plain batch call, bit for bit
+    x2 = torch.empty_like(x)
+    d2 = torch.empty_like(d)
+    done2 = torch.empty_like(done)
+    plan.close()
+    m.agn_lc_generate_batch(gpu_ctx, ns, offs, params, [1.0] * n_curves, [iters] * n_curves, seeds, ids, e,
+                            -1.0, m.AGN_FP32, x2, d2, done2, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(x, x2)
+    assert torch.equal(d, d2)
