@@ -113,3 +113,60 @@ def test_uneven_batch_full_size_plan(gpu_ctx):
     torch.cuda.synchronize()
     assert torch.equal(x, x2)
     assert torch.equal(d, d2)
+
+
+def test_observables_full_size(gpu_ctx):
+    """The observables workload as benchmarked: periodograms with 0.1-dex bins
+    and lag statistics in magnitudes (40 log-spaced lags, 6 thresholds, the
+    detection cut) of the PTF-like batch's output; sampled curves against the
+    oracle to the bars of the periodogram and lag-statistics tests, and the
+    Eq. 6 mean against the mean of the device's own per-curve values."""
+    from test_gpu_lag_stats import check_sf
+    from test_gpu_observables import _bound
+    m = agn()
+    n_curves, n, iters = 1024, 2**14, 100
+    w = synth.ptf_batch(n_curves=n_curves, n=n, seed=1)
+    params = [m.psd_params(0.0, w["f_br"][c], w["a_low"][c], w["a_high"][c]) for c in range(n_curves)]
+    ns = [n] * n_curves
+    offs = [c * n for c in range(n_curves)]
+    e = torch.as_tensor(w["erdf"].reshape(-1)).to("cuda:0")
+    x = torch.empty(n_curves * n, dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(m.agn_batch_workspace_size(ns, m.AGN_FP32), dtype=torch.uint8, device="cuda:0")
+    print(f"full size: observables of the PTF-like batch ({n_curves} x {n})", flush=True)
+    m.agn_lc_generate_batch(gpu_ctx, ns, offs, params, [1.0] * n_curves, [iters] * n_curves,
+                            [1000 + c for c in range(n_curves)], list(range(n_curves)), e, -1.0, m.AGN_FP32, x,
+                            None, None, ws)
+    dex, h = 0.1, n // 2 + 1
+    nb = m.agn_log_bin_count(n, dex)
+    P = torch.full((n_curves * h,), float("nan"), dtype=torch.float64, device="cuda:0")
+    B = torch.full((n_curves * nb,), float("nan"), dtype=torch.float64, device="cuda:0")
+    pws = torch.empty(m.agn_periodogram_workspace_size(ns, dex), dtype=torch.uint8, device="cuda:0")
+    m.agn_periodogram_batch(gpu_ctx, ns, offs, x, [c * h for c in range(n_curves)], P, dex,
+                            [c * nb for c in range(n_curves)], B, pws)
+    lags = np.unique(np.round(np.logspace(0, np.log10(n // 2), 40)).astype(np.int64))
+    dm = [0.1, 0.25, 0.5, 1.0, 2.5, 5.0]
+    cut = 10.0 ** -1.2
+    K, J = len(lags), len(dm)
+    sf2 = torch.full((n_curves * K,), float("nan"), dtype=torch.float64, device="cuda:0")
+    rep = torch.full((K,), float("nan"), dtype=torch.float64, device="cuda:0")
+    ex = torch.full((n_curves * K * J,), -1, dtype=torch.int64, device="cuda:0")
+    pairs = torch.full((n_curves * K,), -1, dtype=torch.int64, device="cuda:0")
+    lws = torch.empty(m.agn_lag_stats_workspace_size(ns, lags, J, m.AGN_SF_MAGNITUDE), dtype=torch.uint8,
+                      device="cuda:0")
+    m.agn_lag_stats_batch(gpu_ctx, ns, offs, x, lags, m.AGN_SF_MAGNITUDE, sf2, rep, dm, cut, ex, pairs, lws)
+    torch.cuda.synchronize()
+    xh = x.cpu().numpy().reshape(n_curves, n)
+    Ph, Bh = P.cpu().numpy().reshape(n_curves, h), B.cpu().numpy().reshape(n_curves, nb)
+    sfh, exh = sf2.cpu().numpy().reshape(n_curves, K), ex.cpu().numpy().reshape(n_curves, K, J)
+    prh = pairs.cpu().numpy().reshape(n_curves, K)
+    for c in (0, 333, n_curves - 1):
+        pr = oracle.periodogram(xh[c])
+        tol = _bound(xh[c], pr)
+        assert np.all(np.abs(Ph[c] - pr) <= tol), c
+        _, br = oracle.log_binned(pr, n, 1.0, dex)
+        assert np.all(np.abs(Bh[c] - br) <= tol.max()), c
+        r_sf, r_ex, r_pr = oracle.lag_stats(xh[c], lags, 1, dm, cut)
+        assert np.array_equal(exh[c], r_ex.astype(np.int64)), c
+        assert np.array_equal(prh[c], r_pr.astype(np.int64)), c
+        check_sf(1, sfh[c], r_sf, xh[c])
+    assert np.allclose(rep.cpu().numpy(), np.mean(sfh, axis=0), rtol=1e-12, atol=0)
