@@ -170,3 +170,51 @@ def test_observables_full_size(gpu_ctx):
         assert np.array_equal(prh[c], r_pr.astype(np.int64)), c
         check_sf(1, sfh[c], r_sf, xh[c])
     assert np.allclose(rep.cpu().numpy(), np.mean(sfh, axis=0), rtol=1e-12, atol=0)
+
+
+def test_convergence_workload_full_size(gpu_ctx):
+    """The convergence workload's launch pattern at its size (32 curves x
+    2^16, FP64, Table 2's Eq. 1 PDF drawn on the device, iterations in
+    segments restarted from the previous output, periodogram + 0.1-dex bins +
+    Eq. 3 fit at each checkpoint), cut to checkpoints 1, 2, 5: sampled curves
+    equal the oracle's uninterrupted run bit for bit, and their fits meet the
+    fit bar against the oracle's fit of the oracle's bins."""
+    from test_gpu_psd_fit import bound
+    m = agn()
+    n, nc, dex, fb = 2**16, 32, 0.1, 1.0 / 1000.0
+    ns, offs = [n] * nc, [c * n for c in range(nc)]
+    params = [m.psd_params(0.0, fb, 1.0, 2.0)] * nc
+    nb = m.agn_log_bin_count(n, dex)
+    xa = torch.empty(nc * n, dtype=torch.float64, device="cuda:0")
+    xb = torch.empty_like(xa)
+    pdf = m.pdf_params(m.AGN_PDF_EQ1)
+    for c in range(nc):
+        m.agn_pdf_draw(gpu_ctx, pdf, n, 77, c, xa[c * n:(c + 1) * n])
+    x0 = xa.cpu().numpy().reshape(nc, n).copy()
+    gws = torch.empty(m.agn_batch_workspace_size(ns, m.AGN_FP64), dtype=torch.uint8, device="cuda:0")
+    P = torch.empty(nc * (n // 2 + 1), dtype=torch.float64, device="cuda:0")
+    bins = torch.empty(nc * nb, dtype=torch.float64, device="cuda:0")
+    fit = torch.empty(nc * 4, dtype=torch.float64, device="cuda:0")
+    pws = torch.empty(m.agn_periodogram_workspace_size(ns, dex), dtype=torch.uint8, device="cuda:0")
+    fws = torch.empty(m.agn_psd_fit_workspace_size(ns, dex), dtype=torch.uint8, device="cuda:0")
+    print(f"full size: convergence workload {nc} x {n}, FP64, checkpoints 1, 2, 5", flush=True)
+    it = 0
+    for cp in (1, 2, 5):
+        m.agn_lc_generate_batch(gpu_ctx, ns, offs, params, [1.0] * nc, [cp - it] * nc, [500 + c for c in range(nc)],
+                                list(range(nc)), xa, -1.0, m.AGN_FP64, xb, None, None, gws)
+        xa, xb = xb, xa
+        it = cp
+    m.agn_periodogram_batch(gpu_ctx, ns, offs, xa, [c * (n // 2 + 1) for c in range(nc)], P, dex,
+                            [c * nb for c in range(nc)], bins, pws)
+    m.agn_psd_fit_batch(gpu_ctx, ns, [1.0] * nc, params, dex, [c * nb for c in range(nc)], bins, fit, fws)
+    torch.cuda.synchronize()
+    xg = xa.cpu().numpy().reshape(nc, n)
+    fg = fit.cpu().numpy().reshape(nc, 4)
+    for c in (0, nc - 1):
+        xr, _, _, _ = oracle.generate(oracle.psd_params(0.0, fb, 1.0, 2.0), x0[c], 1.0, 5, 500 + c, c)
+        assert np.array_equal(xg[c], xr), c
+        fm, pm = oracle.log_binned_mean_f(oracle.periodogram(xr), n, 1.0, dex)
+        ref = oracle.psd_fit(fm, pm, fb, 1.0, 2.0)
+        tol = bound(fm, pm, fb, ref) + 1e-9  # plus the periodograms' own rounding difference
+        assert np.all(np.abs(fg[c, :3] - ref[:3]) <= tol), (c, fg[c], ref, tol)
+        assert fg[c, 3] == pytest.approx(ref[3], rel=1e-8)
