@@ -169,8 +169,21 @@ static int dft_rec(const double* x, int64_t stride, int64_t n, int sign, double*
     for (int64_t k = 0; k < n; ++k) {
         double re = 0.0, im = 0.0;
         for (int64_t r = 0; r < p; ++r) {
-            double ang = (double)sign * 2.0 * M_PI * (double)((r * k) % n) / (double)n;
-            double wr = cos(ang), wi = sin(ang);
+            /* W = exp(sign 2 pi i t / n); the quarter turns are exact
+             * (1, sign i, -1, -sign i), as the roots of unity they are, so
+             * that a bin whose exact value is zero comes out as zero and
+             * takes the zero-modulus phase of the replacement */
+            const int64_t t = (r * k) % n;
+            double wr, wi;
+            if ((4 * t) % n == 0) {
+                const int64_t q = 4 * t / n;
+                wr = q == 0 ? 1.0 : q == 2 ? -1.0 : 0.0;
+                wi = q == 1 ? (double)sign : q == 3 ? -(double)sign : 0.0;
+            } else {
+                double ang = (double)sign * 2.0 * M_PI * (double)t / (double)n;
+                wr = cos(ang);
+                wi = sin(ang);
+            }
             double fr = F[2 * (m * r + k % m)], fi = F[2 * (m * r + k % m) + 1];
             re += wr * fr - wi * fi;
             im += wr * fi + wi * fr;
