@@ -4,10 +4,11 @@ A step is one agn_lc_generate_batch call over the whole workload: Timmer-
 Koenig moduli for every curve, the one-time sort of every PDF draw, and all
 iterations of the Emmanoulopoulos-style loop, with inputs resident in HBM.
 
-Default workload (PTF-like batch): 1024 curves of N = 2^14 samples, dt = 1 d,
-per-curve Eq. 3 slopes a_low ~ U(0.8, 1.2), a_high ~ U(2, 3) and break
-log-uniform in [1/1000, 1/50] per day, broken-power-law PDF draws of N values
-per curve, 100 iterations in the FP32 form.
+Default workload (long LSST-style curves): 4 curves of N = 2^26 samples,
+dt = 7 d, Eq. 3 slopes (1, 2) with the break at 1/(10 yr), broken-power-law
+PDF draws of N values per curve, 100 iterations in the FP32 form (FP64
+twiddles and Eq. 4 sums); the same curves also run through the plain FP64
+method, one curve per call, and the line reports both.
 
 Prints one JSON line.  `value` = light-curve samples per second (curves x N
 per step time).
@@ -28,6 +29,10 @@ METRIC = "light-curve samples/s through full iteration (FP32 batched vs FP64 pla
 HBM_PEAK_GBS = 8000.0
 LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
 FP32_PEAK_TFLOPS = 157.3        # FP32 vector, packed FMA
+
+# What the FP64 GPU path used as the reference here has been shown to equal.
+REF_LABEL = ("FP64 GPU path: its permutation equals the FP64 oracle's for every length tested up to 2^16 and "
+             "at sampled positions after one step at 2^20, 2^26 and 2^27")
 
 
 def source_hash():
@@ -139,11 +144,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ptf_batch",
+    ap.add_argument("--workload", default="lsst_long",
                     choices=["ptf_batch", "single_curve", "lsst_long", "lsst_long_fp64", "uneven_batch", "serving",
                              "paper_scale", "observables", "convergence", "pdf_draw"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the FP32-vs-FP64 accuracy report")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 run beside the FP32 form")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -176,7 +182,6 @@ def main():
     import paper_1909_06374_amd as agn
     from paper_1909_06374_amd import synth
 
-    dev = "cuda:0"
     if args.workload == "uneven_batch":
         print(json.dumps(run_uneven(args, agn, synth, np, torch)))
         return
@@ -192,6 +197,47 @@ def main():
     if args.workload == "pdf_draw":
         print(json.dumps(run_pdf_draw(args, agn, np, torch)))
         return
+    print(json.dumps(run_standard(args, agn, synth, np, torch)))
+
+
+def cpu_info():
+    """The host as the oracle baseline sees it: logical CPUs, the CPUs this
+    process may run on, and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
+
+
+def oracle_pool(jobs, threads):
+    """Runs oracle calls (functions of no arguments) on `threads` host threads
+    (the oracle's C calls release the GIL).  Returns the seconds each job took
+    on its thread and the wall time of the whole pool."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def timed(f):
+        t = time.perf_counter()
+        f()
+        return time.perf_counter() - t
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        secs = list(ex.map(timed, jobs))
+    return secs, time.perf_counter() - t0
+
+
+def workload_setup(args, agn, synth, np):
+    """(n_curves, n, iters, precision, PSD params, host draw or None, description, dt)."""
     if args.workload == "ptf_batch":
         n_curves, n, iters, prec = 1024, 2**14, 100, agn.AGN_FP32
         w = synth.ptf_batch(n_curves=n_curves, n=n, seed=1)
@@ -199,28 +245,36 @@ def main():
         erdf = w["erdf"].reshape(-1)
         desc = (f"ptf_batch: {n_curves} curves x N={n}, dt=1 d, per-curve Eq.3 slopes/break, "
                 f"broken-power-law PDF draws, {iters} iterations, FP32 form")
-    elif args.workload == "paper_scale":
+        return n_curves, n, iters, prec, params, erdf, desc, 1.0
+    if args.workload == "paper_scale":
         n_curves, n, iters, prec = 1, 2**27, 200, agn.AGN_FP64
         params = [agn.psd_params(0.0, 1.0 / (10 * synth.YEAR), 1.0, 2.0)]
-        erdf = None
         desc = ("paper_scale: 1 curve x N=2^27 (the paper's largest run), dt=7 d, Eq.3 slopes (1, 2), break "
                 "1/(10 yr), broken-power-law PDF drawn on the device, 200 iterations, FP64")
-    elif args.workload.startswith("lsst_long"):
+        return n_curves, n, iters, prec, params, None, desc, 7.0
+    if args.workload.startswith("lsst_long"):
         n_curves, n, iters = 4, 2**26, 100
         prec = agn.AGN_FP64 if args.workload.endswith("fp64") else agn.AGN_FP32
         params = [agn.psd_params(0.0, 1.0 / (10 * synth.YEAR), 1.0, 2.0)] * n_curves
         erdf = np.concatenate([synth.erdf_draw(n, seed=2, curve_id=c) for c in range(n_curves)])
         desc = (f"lsst_long: {n_curves} curves x N=2^26, dt=7 d (~1.29 Myr), Eq.3 slopes (1, 2), "
                 f"break 1/(10 yr), broken-power-law PDF draws, {iters} iterations, "
-                f"{'FP64' if prec == agn.AGN_FP64 else 'FP32 form'}")
-    else:
-        n_curves, n, iters, prec = 1, 1024, 50, agn.AGN_FP64
-        w = synth.single_curve(n=n, seed=0)
-        params = [agn.psd_params(**w["params"])]
-        erdf = w["erdf"]
-        desc = "single_curve: 1 curve x N=1024, dt=1 d, bending power law, 50 iterations, FP64"
-    dt_days = 7.0 if (args.workload.startswith("lsst_long") or args.workload == "paper_scale") else 1.0
+                f"{'FP64' if prec == agn.AGN_FP64 else 'FP32 form (FP64 twiddles and Eq. 4 sums)'}")
+        return n_curves, n, iters, prec, params, erdf, desc, 7.0
+    n_curves, n, iters, prec = 1, 1024, 50, agn.AGN_FP64
+    w = synth.single_curve(n=n, seed=0)
+    params = [agn.psd_params(**w["params"])]
+    desc = "single_curve: 1 curve x N=1024, dt=1 d, bending power law, 50 iterations, FP64"
+    return n_curves, n, iters, prec, params, w["erdf"], desc, 1.0
 
+
+def run_standard(args, agn, synth, np, torch):
+    """One agn_lc_generate_batch call over the whole workload per step, timed
+    without kernel instrumentation; per-kernel times come from one profiled
+    repeat after the timed steps.  For the long-curve FP32 workload the same
+    curves also run through the plain FP64 method, one curve per call."""
+    dev = "cuda:0"
+    n_curves, n, iters, prec, params, erdf, desc, dt_days = workload_setup(args, agn, synth, np)
     ns = [n] * n_curves
     offs = [c * n for c in range(n_curves)]
     seeds = [1000 + c for c in range(n_curves)]
@@ -245,23 +299,26 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ctx.kernel_times(reset=True)
-    ctx.set_profiling(True)
     stream = torch.cuda.current_stream(dev)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
     t0.record(stream)
     for _ in range(args.steps):
         step()
     t1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ctx.set_profiling(False)
     ms = t0.elapsed_time(t1) / args.steps
-    kt = ctx.kernel_times(reset=True)
     assert int(done.min().item()) == iters, "a curve did not complete its iterations"
+
+    # per-kernel times: one profiled repeat (events around every launch), kept
+    # out of the timed steps
+    ctx.kernel_times(reset=True)
+    ctx.set_profiling(True)
+    step()
+    torch.cuda.synchronize()
+    ctx.set_profiling(False)
+    kt = ctx.kernel_times(reset=True)
+    kt = {k: v for k, v in kt.items() if v[1]}
 
     samples = n_curves * n
     value = samples / (ms / 1000.0)
@@ -295,7 +352,16 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": recorded_traffic(args.workload, dom),
                 "bytes_per_sample_per_launch": per, "avg_launch_ms": round(dom_ms, 4)}
-
+        # whole step against the algorithmic bytes of one sample-iteration
+        # (B_alg: 42 B in the FP32 form, 76 B in FP64)
+        b_alg = 42 if prec == agn.AGN_FP32 else 76
+        step_gbs = b_alg * samples * iters / (ms / 1000.0) / 1e9
+        roof["step_view"] = {"bytes_per_sample_iter": b_alg, "achieved_gbs": round(step_gbs, 1),
+                             "frac": round(step_gbs / HBM_PEAK_GBS, 4)}
+    roof["traffic_source"] = ("recorded rocprofv3 FETCH_SIZE + WRITE_SIZE per launch (profiles/traffic.txt, "
+                              "copy-calibrated) for these kernel sources" if roof["traffic"] is not None
+                              else "no counter run recorded for these kernel sources")
+    total_k = sum(v[0] for v in kt.values())
     out = {
         "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -304,46 +370,104 @@ def main():
                    "precision": "fp32" if prec == agn.AGN_FP32 else "fp64"},
         "sample_iterations_per_s": value * iters,
         "hbm_bytes_alloc_gib": round((ws.numel() + x.numel() * 8 + erdf_t.numel() * 8) / 2**30, 2),
-        "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]},
+        "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items()},
+        "kernel_time_share": {k: round(v[0] / total_k, 4) for k, v in kt.items()},
+        "kernel_times_from": "one profiled repeat of the step after the timed steps",
         "roofline": roof,
     }
 
-    if args.workload == "ptf_batch" and prec == agn.AGN_FP32 and not args.no_accuracy:
+    x64 = None
+    if args.workload == "lsst_long" and not args.no_fp64:
+        # the plain method on the same curves: FP64, one agn_lc_generate call per curve
+        ws64 = torch.empty(agn.agn_workspace_size(n, agn.AGN_FP64), dtype=torch.uint8, device=dev)
+        x64 = torch.empty(n_curves * n, dtype=torch.float64, device=dev)
+        done64 = torch.empty(n_curves, dtype=torch.int32, device=dev)
+
+        def step64():
+            for c in range(n_curves):
+                agn.agn_lc_generate(ctx, params[c], erdf_t[c * n:(c + 1) * n], n, dt_days, iters, -1.0, seeds[c],
+                                    ids[c], agn.AGN_FP64, x64[c * n:(c + 1) * n], None, done64[c:c + 1], ws64)
+
+        step64()
+        torch.cuda.synchronize()
+        k64 = max(1, min(args.steps, 2))
+        t0.record(stream)
+        for _ in range(k64):
+            step64()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms64 = t0.elapsed_time(t1) / k64
+        assert int(done64.min().item()) == iters
+        del ws64
+        out["fp64_plain"] = {"ms_per_step": ms64, "value": samples / (ms64 / 1000.0), "unit": "samples/s",
+                             "steps": k64, "warmup": 1,
+                             "how": "the same curves in FP64, one agn_lc_generate call per curve"}
+        out["speedup_fp32_vs_fp64_plain"] = ms64 / ms
+
+    if prec == agn.AGN_FP32 and not args.no_accuracy and args.workload in ("ptf_batch", "lsst_long"):
+        k = 8 if args.workload == "ptf_batch" else 1
         out["accuracy_vs_fp64"] = fp32_accuracy(agn, np, torch, ctx, x, ns, offs, params, dt_days, iters,
-                                                seeds, ids, erdf_t, k=8)
+                                                seeds, ids, erdf_t, k=k, x64_all=x64)
 
     if not args.no_cpu_baseline:
-        import oracle
-        if erdf is None:
-            erdf = erdf_t[:2**20].cpu().numpy()
-        if args.workload.startswith("lsst_long") or args.workload == "paper_scale":
-            # bounded sample: one 2^20-sample piece of the first curve, 3 iterations,
-            # scaled per sample-iteration to the full 100-iteration run
-            k, ns_, it_ = 1, 2**20, 3
-            t = time.perf_counter()
-            op = oracle.psd_params(params[0].norm, params[0].f_br, params[0].a_low, params[0].a_high)
-            oracle.generate(op, erdf[:ns_], dt_days, it_, seeds[0], ids[0])
-            el = time.perf_counter() - t
-            rate = ns_ * it_ / el / iters
-            out["cpu_baseline"] = {"value": rate, "unit": "samples/s", "cores": 1, "kind": "oracle",
-                                   "sample": f"N=2^20 x {it_} iterations of the single-threaded FP64 oracle "
-                                             f"({el:.1f} s), scaled per sample-iteration to {iters} iterations"}
-        else:
-            k = 4 if args.workload == "ptf_batch" else 1
-            t = time.perf_counter()
-            reps = 0
-            while True:  # at least one pass; repeated up to about 5 s of oracle work
-                for c in range(k):
-                    op = oracle.psd_params(params[c].norm, params[c].f_br, params[c].a_low, params[c].a_high)
-                    oracle.generate(op, erdf[c * n:(c + 1) * n], dt_days, iters, seeds[c], ids[c])
-                reps += 1
-                if time.perf_counter() - t >= 5.0:
-                    break
-            el = time.perf_counter() - t
-            out["cpu_baseline"] = {"value": reps * k * n / el, "unit": "samples/s", "cores": 1, "kind": "oracle",
-                                   "sample": f"first {k} curve(s) of the workload, all {iters} iterations, "
-                                             f"{reps} pass(es), single-threaded FP64 oracle ({el:.1f} s)"}
-    print(json.dumps(out))
+        out["cpu_baseline"] = oracle_baseline(args, np, params, erdf, erdf_t, n, n_curves, dt_days, iters,
+                                              seeds, ids)
+    return out
+
+
+def oracle_baseline(args, np, params, erdf, erdf_t, n, n_curves, dt_days, iters, seeds, ids):
+    """The FP64 oracle on the host cores, parallel across curves only (one
+    curve per thread; the per-curve code is the oracle as it stands).  Short
+    curves run whole; long curves run a bounded piece: the first 2^21 samples
+    of each curve at 1 and at 3 iterations, which separates the one-time work
+    from the per-iteration cost; both are scaled to the full length by
+    N log2 N and the step is extrapolated to all iterations."""
+    import oracle
+    info = cpu_info()
+    if erdf is None:
+        erdf = erdf_t[:min(erdf_t.numel(), n_curves * n)].cpu().numpy()
+    op = [oracle.psd_params(p.norm, p.f_br, p.a_low, p.a_high) for p in params]
+    if n > 2**20:
+        ns_ = 2**21
+        threads = max(1, min(n_curves, info["usable_cpus"] or 1))
+
+        def job(c, it):
+            return lambda: oracle.generate(op[c], erdf[c * n:c * n + ns_], dt_days, it, seeds[c], ids[c])
+
+        jobs = [job(c, 1) for c in range(n_curves)] + [job(c, 3) for c in range(n_curves)]
+        secs, wall = oracle_pool(jobs, threads)
+        t1 = np.array(secs[:n_curves])
+        t3 = np.array(secs[n_curves:])
+        t_it = np.maximum((t3 - t1) / 2.0, 1e-9)
+        t_once = np.maximum(t1 - t_it, 0.0)
+        scale = (n / ns_) * (math.log2(n) / math.log2(ns_))
+        step_s = float(np.max((t_once + iters * t_it) * scale)) * math.ceil(n_curves / threads)
+        return {"value": n_curves * n / step_s, "unit": "samples/s", "cores": threads, "kind": "oracle",
+                "extrapolated": True,
+                "sample": f"first 2^21 samples of each of the {n_curves} curves at 1 and 3 iterations, one curve "
+                          f"per thread ({wall:.1f} s wall); per-iteration and one-time costs scaled by N log2 N to "
+                          f"N=2^{int(math.log2(n))} and to {iters} iterations",
+                "oracle_step_s_extrapolated": round(step_s, 1),
+                "single_thread_sample_iterations_per_s": float(np.mean(ns_ / t_it)),
+                **info}
+    k = min(n_curves, 8, info["usable_cpus"] or 1)
+    threads = k
+
+    def job(c):
+        return lambda: oracle.generate(op[c], erdf[c * n:(c + 1) * n], dt_days, iters, seeds[c], ids[c])
+
+    reps, secs_all, wall_all = 0, [], 0.0
+    while True:  # at least one pass; repeated up to about 10 s of wall time
+        secs, wall = oracle_pool([job(c) for c in range(k)], threads)
+        secs_all += secs
+        wall_all += wall
+        reps += 1
+        if wall_all >= 10.0:
+            break
+    return {"value": reps * k * n / wall_all, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {k} curve(s) of the workload, all {iters} iterations, one curve per thread, "
+                      f"{reps} pass(es) ({wall_all:.1f} s wall)",
+            "single_thread_samples_per_s": float(n / np.mean(secs_all)), **info}
 
 
 def log_binned_periodogram(np, x, dex=0.1):
@@ -359,18 +483,23 @@ def log_binned_periodogram(np, x, dex=0.1):
     return sums[keep] / cnt[keep]
 
 
-def fp32_accuracy(agn, np, torch, ctx, x32_all, ns, offs, params, dt_days, iters, seeds, ids, erdf_t, k):
-    """FP32 form against the FP64 path (bit-identical to the oracle) on the
-    first k curves: value multiset, end-to-end and one-step rank agreement,
-    |rank difference| quantiles, log-binned periodogram difference after all
-    iterations and after one step from the same input."""
+def fp32_accuracy(agn, np, torch, ctx, x32_all, ns, offs, params, dt_days, iters, seeds, ids, erdf_t, k,
+                  x64_all=None):
+    """FP32 form against the FP64 path on the first k curves: value multiset,
+    end-to-end and one-step rank agreement, |rank difference| quantiles,
+    log-binned periodogram difference after all iterations and after one step
+    from the same input.  x64_all: the FP64 run of the same curves, if made."""
     dev = "cuda:0"
     ns_k, offs_k = ns[:k], offs[:k]
     tot = int(sum(ns_k))
-    x64 = torch.empty(tot, dtype=torch.float64, device=dev)
-    ws = torch.empty(agn.agn_batch_workspace_size(ns_k, agn.AGN_FP64), dtype=torch.uint8, device=dev)
-    agn.agn_lc_generate_batch(ctx, ns_k, offs_k, params[:k], [dt_days] * k, [iters] * k, seeds[:k], ids[:k],
-                              erdf_t[:tot], -1.0, agn.AGN_FP64, x64, None, None, ws)
+    if x64_all is not None:
+        x64 = x64_all[:tot]
+    else:
+        x64 = torch.empty(tot, dtype=torch.float64, device=dev)
+        ws = torch.empty(agn.agn_batch_workspace_size(ns_k, agn.AGN_FP64), dtype=torch.uint8, device=dev)
+        agn.agn_lc_generate_batch(ctx, ns_k, offs_k, params[:k], [dt_days] * k, [iters] * k, seeds[:k], ids[:k],
+                                  erdf_t[:tot], -1.0, agn.AGN_FP64, x64, None, None, ws)
+        del ws
     torch.cuda.synchronize()
     a64 = x64.cpu().numpy()
     a32 = x32_all[:tot].cpu().numpy()
@@ -406,7 +535,7 @@ def fp32_accuracy(agn, np, torch, ctx, x32_all, ns, offs, params, dt_days, iters
     dr = np.concatenate(drank)
     pd = np.concatenate(pdiff)
     pd1 = np.concatenate(pdiff1)
-    return {"curves": k, "reference": "FP64 GPU path (bit-identical to the FP64 oracle)",
+    return {"curves": k, "reference": REF_LABEL,
             "value_multiset_exact": multiset,
             "one_step_rank_agreement": round(float(np.mean(one)), 6),
             "end_to_end_agreement": round(float(np.mean(e2e)), 6),
