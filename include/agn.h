@@ -360,6 +360,54 @@ int agn_test_philox(uint64_t key0, uint64_t key1, uint64_t ctr0, int64_t n_block
                     uint64_t* out, void* stream);
 
 /*
+ * The iteration's transforms and ranking on their own, run by the same
+ * kernels as agn_lc_iterate (the Stockham passes, the real-spectrum fold of
+ * the replacement step, the radix sorts), so that each step can be checked
+ * against its definition.  path selects the kernels:
+ *   AGN_TEST_PATH_LDS  the LDS-resident kernels: one workgroup, the block
+ *                      shape and LDS layout of the iteration; n must be a
+ *                      length that agn_lc_iterate runs there (FP32:
+ *                      n <= 2^14, or 3 * 2^a <= 12288; FP64: n <= 2^13, or
+ *                      3 * 2^a <= 12288).
+ *   AGN_TEST_PATH_HBM  the multi-pass kernels with the iteration's pass plan
+ *                      for n (any supported n that is a multiple of 8192).
+ * Arithmetic is in the working precision of prec: inputs are rounded to it
+ * on load (as the iteration rounds x_i), outputs widened to double.  All
+ * arrays are device memory; ws is a device workspace of
+ * agn_test_workspace_size(n, prec, path) bytes.  Errors: AGN_EINVAL (NULL
+ * pointers, small workspace, unknown path or precision, an x that is not
+ * 16-byte aligned for the multi-pass transform), AGN_EUNSUPPORTED_N (n not of
+ * the supported form or not on the chosen path); nothing is enqueued on
+ * error.  Stream-ordered.
+ *
+ * agn_test_rfft   X_out[j] = sum_t x[t] exp(-2 pi i j t / n), j = 0 .. n/2, as
+ *                 interleaved (re, im) doubles: the real DFT of App. A (Eq. A1,
+ *                 taken with the negative exponent forward; the sign does not
+ *                 change the iteration's output).
+ * agn_test_irfft  y_out[t] = sum_j Y_j exp(+2 pi i j t / n) over the full
+ *                 Hermitian spectrum built from the n/2 + 1 values Y
+ *                 (interleaved re, im), unnormalised; the imaginary parts of
+ *                 Y_0 and Y_{n/2} are ignored (the iteration's are zero).
+ * agn_test_argsort  rank_out[t] = position of sample t in the stable ascending
+ *                 order of y (ties by index, -0 == +0): the ranking of Sec.
+ *                 2.1.  Keys: the order-preserving integer image of y rounded
+ *                 to the working precision, except in the FP32 form on the
+ *                 LDS path, where y (rounded to float) is mapped in double
+ *                 precision onto 2^30 levels over [min y, max y],
+ *                 key = trunc((y - min) * ((2^30 - 1) / (max - min))), so that
+ *                 values closer than (max - min) 2^-30 can share a key and
+ *                 are then ordered by index.
+ */
+enum { AGN_TEST_PATH_LDS = 0, AGN_TEST_PATH_HBM = 1 };
+int agn_test_workspace_size(int64_t n, agn_precision prec, int32_t path, size_t* bytes);
+int agn_test_rfft(agn_ctx* ctx, const double* x, int64_t n, agn_precision prec, int32_t path,
+                  double* X_out, void* ws, size_t ws_bytes, void* stream);
+int agn_test_irfft(agn_ctx* ctx, const double* Y, int64_t n, agn_precision prec, int32_t path,
+                   double* y_out, void* ws, size_t ws_bytes, void* stream);
+int agn_test_argsort(agn_ctx* ctx, const double* y, int64_t n, agn_precision prec, int32_t path,
+                     uint32_t* rank_out, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * agn_psd_fit_batch -- the convergence test of Sec. 3.2.2: Eq. 3 fitted to
  * each curve's log-binned periodogram, as written by agn_periodogram_batch
  * with the same dex (bins_out at b_offset[c], agn_log_bin_count(n[c], dex)

@@ -95,6 +95,9 @@ def _declare(lib):
     lib.agn_lc_generate_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_int,
                                           vp, vp, vp, vp, sz, vp]
     lib.agn_test_philox.argtypes = [u64, u64, u64, i64, vp, vp]
+    lib.agn_test_workspace_size.argtypes = [i64, C.c_int, i32, C.POINTER(sz)]
+    for f in ("agn_test_rfft", "agn_test_irfft", "agn_test_argsort"):
+        getattr(lib, f).argtypes = [vp, vp, i64, C.c_int, i32, vp, vp, sz, vp]
     lib.agn_erdf_draw.argtypes = [vp, C.POINTER(agn_erdf_params), i64, u64, u32, vp, vp]
     lib.agn_pdf_draw.argtypes = [vp, C.POINTER(agn_pdf_params), i64, u64, u32, vp, vp]
     lib.agn_lag_stats_workspace_size.argtypes = [i32, vp, i32, vp, i32, i32, C.POINTER(sz)]
@@ -121,7 +124,8 @@ def _declare(lib):
               "agn_ctx_set_profiling", "agn_ctx_kernel_time", "agn_erdf_draw", "agn_pdf_draw", "agn_pdf_slice", "agn_batch_plan_create",
               "agn_batch_plan_launch", "agn_batch_plan_info", "agn_batch_plan_tuning", "agn_batch_plan_destroy", "agn_log_bin_count",
               "agn_periodogram_workspace_size", "agn_periodogram_batch", "agn_lag_stats_workspace_size",
-              "agn_lag_stats_batch", "agn_psd_fit_workspace_size", "agn_psd_fit_batch"):
+              "agn_lag_stats_batch", "agn_psd_fit_workspace_size", "agn_psd_fit_batch",
+              "agn_test_workspace_size", "agn_test_rfft", "agn_test_irfft", "agn_test_argsort"):
         getattr(lib, f).restype = C.c_int
 
 
@@ -502,3 +506,35 @@ def agn_test_philox(key0, key1, ctr0, n_blocks, out, stream=None, device=0):
                                  int(ctr0) & (2**64 - 1), int(n_blocks),
                                  _buf(out, "out", _I64, 4 * max(int(n_blocks), 0), device),
                                  _stream(stream, device)))
+
+
+AGN_TEST_PATH_LDS, AGN_TEST_PATH_HBM = 0, 1
+
+
+def agn_test_workspace_size(n: int, prec: int, path: int) -> int:
+    b = C.c_size_t()
+    _check(lib().agn_test_workspace_size(int(n), int(prec), int(path), C.byref(b)))
+    return b.value
+
+
+def agn_test_rfft(ctx: Context, x, n, prec, path, X_out, ws, stream=None):
+    """X_out: float64 tensor of 2 (n/2 + 1) values, (re, im) interleaved."""
+    dv, k = ctx.device, max(int(n), 0)
+    _check(lib().agn_test_rfft(ctx.handle, _buf(x, "x", _F64, k, dv), int(n), int(prec), int(path),
+                               _buf(X_out, "X_out", _F64, 2 * (k // 2 + 1), dv), _buf(ws, "ws", None, 0, dv),
+                               0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, dv)))
+
+
+def agn_test_irfft(ctx: Context, Y, n, prec, path, y_out, ws, stream=None):
+    """Y: float64 tensor of 2 (n/2 + 1) values, (re, im) interleaved."""
+    dv, k = ctx.device, max(int(n), 0)
+    _check(lib().agn_test_irfft(ctx.handle, _buf(Y, "Y", _F64, 2 * (k // 2 + 1), dv), int(n), int(prec),
+                                int(path), _buf(y_out, "y_out", _F64, k, dv), _buf(ws, "ws", None, 0, dv),
+                                0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, dv)))
+
+
+def agn_test_argsort(ctx: Context, y, n, prec, path, rank_out, ws, stream=None):
+    dv, k = ctx.device, max(int(n), 0)
+    _check(lib().agn_test_argsort(ctx.handle, _buf(y, "y", _F64, k, dv), int(n), int(prec), int(path),
+                                  _buf(rank_out, "rank_out", _I32, k, dv), _buf(ws, "ws", None, 0, dv),
+                                  0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, dv)))

@@ -24,6 +24,7 @@
 #include "lds_iterate.hpp"
 #include "philox.hpp"
 #include "spectrum.hpp"
+#include "test_kernels.hpp"
 
 using namespace agn;
 
@@ -575,11 +576,13 @@ static std::vector<int> big_radices(int64_t M, agn_precision prec) {
 // Tile of one FFT workgroup: R x cols complex values = 64 KB.
 static int fft_tile(agn_precision prec) { return prec == AGN_FP32 ? 8192 : 4096; }
 
-// Butterflies per workgroup of a pass: the largest power of two <= 64 with
-// R * cols within the tile and dividing M / R (0 if none >= 16).
-static int fft_cols(int64_t M, int R, agn_precision prec) {
+// Butterflies per workgroup of a pass over stride Ns: the largest power of
+// two <= 64 with R * cols within the tile, dividing M / R and, after the first
+// pass, dividing Ns (a workgroup's columns then share one j mod Ns offset
+// run); 0 if none >= 16.  The column count does not change the arithmetic.
+static int fft_cols(int64_t M, int R, int64_t Ns, agn_precision prec) {
     for (int c = FFT_COLS_MAX; c >= FFT_COLS_MIN; c >>= 1)
-        if ((int64_t)R * c <= fft_tile(prec) && (M / R) % c == 0) return c;
+        if ((int64_t)R * c <= fft_tile(prec) && (M / R) % c == 0 && (Ns == 1 || Ns % c == 0)) return c;
     return 0;
 }
 
@@ -659,7 +662,7 @@ static int big_group_setup(agn_ctx* ctx, int64_t n, agn_precision prec, TwTable*
     if (rad->empty()) return fail(AGN_EUNSUPPORTED_N, "internal: no FFT plan for n=%lld", (long long)n);
     int64_t ns = 1;
     for (int r : *rad) {
-        const int c = fft_cols(M, r, prec);
+        const int c = fft_cols(M, r, ns, prec);
         if (c == 0 || r > 512 || (ns > 1 && ns % c != 0) || (ns == 1 && r < 64) || r < 16)
             return fail(AGN_EUNSUPPORTED_N, "internal: no FFT plan for n=%lld", (long long)n);
         ns *= r;
@@ -694,7 +697,7 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
     const int np = (int)rad.size();
     const int prec_bits = sizeof(T) == 4 ? 1 : 0;
     const agn_precision prec = prec_bits ? AGN_FP32 : AGN_FP64;
-    const int64_t npart0 = M / rad[0] / fft_cols(M, rad[0], prec);  // blocks of the first FFT pass
+    const int64_t npart0 = M / rad[0] / fft_cols(M, rad[0], 1, prec);  // blocks of the first FFT pass
     for (int it = 0; it < max_iters; ++it) {
         const int cur = it & 1;  // x_it lives in X0 (even) or X1 (odd)
         int sel = 0;             // region written by the next FFT pass
@@ -702,7 +705,7 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
         for (int p = 0; p < np; ++p) {
             FftPass P;
             memset(&P, 0, sizeof(P));
-            P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], prec); P.nthreads = rad[p] * P.cols / 16;
+            P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, prec); P.nthreads = rad[p] * P.cols / 16;
             P.Ns = Ns;
             P.in_mode = p == 0 ? 1 : 0; P.out_mode = 0; P.inverse = 0;
             P.x_sel = cur; P.with_delta = (p == 0 && it > 0) ? 1 : 0;
@@ -726,7 +729,7 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
         for (int p = 0; p < np; ++p) {
             FftPass P;
             memset(&P, 0, sizeof(P));
-            P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], prec); P.nthreads = rad[p] * P.cols / 16;
+            P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, prec); P.nthreads = rad[p] * P.cols / 16;
             P.Ns = Ns;
             P.in_mode = 0; P.out_mode = (p == np - 1) ? 1 : 0; P.inverse = 1;
             P.src_sel = 1 - sel; P.dst_sel = sel; P.sub = make_plan(rad[p]);
@@ -1575,7 +1578,7 @@ extern "C" int agn_periodogram_batch(agn_ctx* ctx, int32_t n_curves, const int64
             for (size_t p = 0; p < rad.size(); ++p) {
                 FftPass P;
                 memset(&P, 0, sizeof(P));
-                P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], AGN_FP64); P.nthreads = rad[p] * P.cols / 16;
+                P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, AGN_FP64); P.nthreads = rad[p] * P.cols / 16;
                 P.Ns = Ns;
                 P.in_mode = p == 0 ? 1 : 0; P.out_mode = 0; P.inverse = 0;
                 P.x_sel = 0; P.with_delta = 0;
@@ -1958,4 +1961,187 @@ extern "C" int agn_test_philox(uint64_t key0, uint64_t key1, uint64_t ctr0, int6
                        key1, ctr0, n_blocks, out);
     HIPCHK(hipGetLastError());
     return AGN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The iteration's transforms and ranking on their own (test exports)
+// ---------------------------------------------------------------------------
+static int test_check(int64_t n, agn_precision prec, int32_t path) {
+    if (check_prec(prec)) return AGN_EINVAL;
+    if (!n_supported(n)) return fail(AGN_EUNSUPPORTED_N, "n=%lld is not 2^a or 3*2^a in [2, 2^27]", (long long)n);
+    if (path == AGN_TEST_PATH_LDS) {
+        if (!lds_path(n, prec))
+            return fail(AGN_EUNSUPPORTED_N, "n=%lld does not run on the LDS-resident path in this precision",
+                        (long long)n);
+    } else if (path == AGN_TEST_PATH_HBM) {
+        if (n % BIG_TILE != 0)
+            return fail(AGN_EUNSUPPORTED_N, "the multi-pass kernels need n to be a multiple of %d", BIG_TILE);
+    } else {
+        return fail(AGN_EINVAL, "path %d is neither AGN_TEST_PATH_LDS nor AGN_TEST_PATH_HBM", path);
+    }
+    return AGN_OK;
+}
+
+static size_t test_ws_bytes(int64_t n, agn_precision prec, int32_t path) {
+    if (path == AGN_TEST_PATH_LDS) return align256(sizeof(TestLds));
+    return align256(sizeof(BigCurve)) + big_curve_ws(n, prec);
+}
+
+extern "C" int agn_test_workspace_size(int64_t n, agn_precision prec, int32_t path, size_t* bytes) {
+    if (!bytes) return fail(AGN_EINVAL, "bytes is NULL");
+    const int rc = test_check(n, prec, path);
+    if (rc) return rc;
+    *bytes = test_ws_bytes(n, prec, path);
+    return AGN_OK;
+}
+
+template <typename T>
+static int test_run_lds(agn_ctx* ctx, int mode, int64_t n, agn_precision prec, const double* in, double* out,
+                        uint32_t* rank_out, void* ws, hipStream_t st) {
+    TestLds d;
+    memset(&d, 0, sizeof(d));
+    d.n = (int32_t)n;
+    d.mode = mode;
+    d.in = in;
+    d.out = out;
+    d.rank_out = rank_out;
+    const void* tw = nullptr;
+    int rc = get_twiddles(ctx, n, AGN_FP64, &tw);
+    if (rc) return rc;
+    d.tw = tw;
+    d.plan = make_plan(n / 2);
+    const int ipt = lds_ipt(n), E = ipt / 2, nt = (int)(n / ipt);
+    const size_t lds = lds_iter_bytes(n, prec);
+    if (lds > ctx->lds_max)
+        return fail(AGN_EUNSUPPORTED_N, "n=%lld needs %zu bytes of LDS; the device allows %zu", (long long)n, lds,
+                    ctx->lds_max);
+    if (E >= 8 && nt % 32 != 0) return fail(AGN_EINVAL, "internal: %d-thread block for E=%d", nt, E);
+    rc = stage_upload(ctx, ws, &d, sizeof(d), st);
+    if (rc) return rc;
+    const TestLds* dp = (const TestLds*)ws;
+    switch (E) {
+        case 1: hipLaunchKernelGGL((k_test_lds<T, 1>), dim3(1), dim3(nt), lds, st, dp); break;
+        case 2: hipLaunchKernelGGL((k_test_lds<T, 2>), dim3(1), dim3(nt), lds, st, dp); break;
+        case 3: hipLaunchKernelGGL((k_test_lds<T, 3>), dim3(1), dim3(nt), lds, st, dp); break;
+        case 4: hipLaunchKernelGGL((k_test_lds<T, 4>), dim3(1), dim3(nt), lds, st, dp); break;
+        case 6: hipLaunchKernelGGL((k_test_lds<T, 6>), dim3(1), dim3(nt), lds, st, dp); break;
+        case 8: hipLaunchKernelGGL((k_test_lds<T, 8>), dim3(1), dim3(nt), lds, st, dp); break;
+        default: return fail(AGN_EINVAL, "internal: no kernel for E=%d", E);
+    }
+    return AGN_OK;
+}
+
+template <typename T>
+static int test_run_big(agn_ctx* ctx, int mode, int64_t n, agn_precision prec, const double* in, double* out,
+                        uint32_t* rank_out, void* ws, hipStream_t st) {
+    typedef typename key_of<T>::type K;
+    TwTable tb;
+    std::vector<int> rad;
+    int rc = big_group_setup(ctx, n, prec, &tb, &rad);
+    if (rc) return rc;
+    const int64_t M = n / 2, ntiles = n / BIG_TILE;
+    unsigned char* base = (unsigned char*)ws;
+    BigCurve d;
+    memset(&d, 0, sizeof(d));
+    size_t off = align256(sizeof(BigCurve));
+    d.n = n;
+    d.iters = 1;
+    d.tol = -1.0;
+    d.s64 = (double*)(base + off); off += align256((size_t)n * 8);
+    d.X0 = (double*)(base + off); off += align256((size_t)n * 8);
+    d.X1 = (double*)(base + off); off += align256((size_t)n * 8);
+    d.rankA = (uint32_t*)(base + off); off += align256((size_t)n * 4);
+    d.rankB = (uint32_t*)(base + off); off += align256((size_t)n * 4);
+    d.sortA = base + off; off += align256((size_t)n * 12);
+    d.sortB = base + off; off += align256((size_t)n * 12);
+    d.hist = (uint32_t*)(base + off); off += align256((size_t)ntiles * 256 * 4);
+    d.dstart = (uint32_t*)(base + off); off += align256(256 * 4);
+    d.dpart = (double*)(base + off); off += align256((size_t)big_npart(n) * 8);
+    d.cpart = (uint32_t*)(base + off); off += align256((size_t)big_npart(n) * 4);
+    d.state = (int32_t*)(base + off); off += align256(16);
+    if (mode == TEST_RFFT) d.X0 = const_cast<double*>(in);  // read as x_i by the first forward pass
+    if (mode == TEST_RANK) {
+        d.rankB = rank_out;  // the last pass writes rank[sample] = sorted position here
+        d.rank_out = rank_out;
+    }
+    rc = stage_upload(ctx, ws, &d, sizeof(d), st);
+    if (rc) return rc;
+    const BigCurve* dv = (const BigCurve*)ws;
+    hipLaunchKernelGGL(k_big_init, dim3(1), dim3(64), 0, st, dv);
+    const int np = (int)rad.size();
+    const unsigned hb = (unsigned)((M / 2 + 1 + 255) / 256), nb = (unsigned)((n + 255) / 256);
+    if (mode == TEST_RANK) {
+        hipLaunchKernelGGL((k_test_big_keys<T>), dim3(nb), dim3(256), 0, st, dv, n, in);
+        int src = 0;
+        const int npass = (int)sizeof(K);
+        for (int p = 0; p < npass; ++p) {
+            SortPass P;
+            P.shift = 8 * p;
+            P.first = p == 0;
+            P.src_sel = src;
+            P.mode = p == npass - 1 ? SORT_MODE_RANK : SORT_MODE_MOVE;
+            P.rank_sel = 1;
+            launch_sort_pass<K, T>(ctx, dv, 1, n, P, BIG_TILE, st);
+            src = 1 - src;
+        }
+        return AGN_OK;
+    }
+    const bool inv = mode == TEST_IRFFT;
+    int sel = inv ? 1 : 0;  // region written by the next pass
+    if (inv) hipLaunchKernelGGL((k_test_big_unfold<T>), dim3(hb), dim3(256), 0, st, dv, M, 0, tb, in);
+    int64_t Ns = 1;
+    for (int p = 0; p < np; ++p) {
+        FftPass P;
+        memset(&P, 0, sizeof(P));
+        P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, prec); P.nthreads = rad[p] * P.cols / 16;
+        P.Ns = Ns;
+        P.in_mode = (!inv && p == 0) ? 1 : 0; P.out_mode = 0; P.inverse = inv ? 1 : 0;
+        P.x_sel = 0; P.with_delta = 0;
+        P.src_sel = 1 - sel; P.dst_sel = sel; P.sub = make_plan(rad[p]);
+        launch_fft_pass<T>(ctx, dv, 1, P, tb, st);
+        Ns *= rad[p];
+        sel = 1 - sel;
+    }
+    if (inv) hipLaunchKernelGGL((k_test_big_real<T>), dim3(nb), dim3(256), 0, st, dv, n, 1 - sel, out);
+    else hipLaunchKernelGGL((k_test_big_spectrum<T>), dim3(hb), dim3(256), 0, st, dv, M, 1 - sel, tb, out);
+    return AGN_OK;
+}
+
+static int test_dispatch(agn_ctx* ctx, int mode, const double* in, int64_t n, agn_precision prec, int32_t path,
+                         double* out, uint32_t* rank_out, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx) return fail(AGN_EINVAL, "ctx is NULL");
+    if (!in || (mode == TEST_RANK ? !rank_out : !out)) return fail(AGN_EINVAL, "NULL input or output");
+    int rc = test_check(n, prec, path);
+    if (rc) return rc;
+    const size_t need = test_ws_bytes(n, prec, path);
+    if (!ws || ws_bytes < need)
+        return fail(AGN_EINVAL, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+    if (path == AGN_TEST_PATH_HBM && mode == TEST_RFFT && ((uintptr_t)in & 15) != 0)
+        return fail(AGN_EINVAL, "the multi-pass transform reads x in 16-byte pairs: x must be 16-byte aligned");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (path == AGN_TEST_PATH_LDS)
+        rc = prec == AGN_FP32 ? test_run_lds<float>(ctx, mode, n, prec, in, out, rank_out, ws, st)
+                              : test_run_lds<double>(ctx, mode, n, prec, in, out, rank_out, ws, st);
+    else
+        rc = prec == AGN_FP32 ? test_run_big<float>(ctx, mode, n, prec, in, out, rank_out, ws, st)
+                              : test_run_big<double>(ctx, mode, n, prec, in, out, rank_out, ws, st);
+    if (rc) return rc;
+    HIPCHK(hipGetLastError());
+    return AGN_OK;
+}
+
+extern "C" int agn_test_rfft(agn_ctx* ctx, const double* x, int64_t n, agn_precision prec, int32_t path,
+                             double* X_out, void* ws, size_t ws_bytes, void* stream) {
+    return test_dispatch(ctx, TEST_RFFT, x, n, prec, path, X_out, nullptr, ws, ws_bytes, stream);
+}
+
+extern "C" int agn_test_irfft(agn_ctx* ctx, const double* Y, int64_t n, agn_precision prec, int32_t path,
+                              double* y_out, void* ws, size_t ws_bytes, void* stream) {
+    return test_dispatch(ctx, TEST_IRFFT, Y, n, prec, path, y_out, nullptr, ws, ws_bytes, stream);
+}
+
+extern "C" int agn_test_argsort(agn_ctx* ctx, const double* y, int64_t n, agn_precision prec, int32_t path,
+                                uint32_t* rank_out, void* ws, size_t ws_bytes, void* stream) {
+    return test_dispatch(ctx, TEST_RANK, y, n, prec, path, nullptr, rank_out, ws, ws_bytes, stream);
 }

@@ -308,28 +308,15 @@ __global__ __launch_bounds__(256) void k_big_fold(const BigCurve* __restrict__ c
     const T* amp = (const T*)d.amp;
     const int64_t mk = (k == 0) ? 0 : M - k;
     const cplx<T> zk = Z[k], zm = Z[mk];
-    const cplx<T> Ev = cmk((zk.re + zm.re) * (T)0.5, (zk.im - zm.im) * (T)0.5);
-    const cplx<T> Ov = cmk((zk.im + zm.im) * (T)0.5, (zm.re - zk.re) * (T)0.5);
     const cplx<T> w = to_T<T>(tw64(tb, k));
-    const cplx<T> wO = cmul(w, Ov);
     if (k == 0) {
-        const T xn = Ev.re - wO.re;
-        const T yn = (xn >= (T)0) ? amp[M] : -amp[M];
-        Z[0] = cmk(yn, -yn);
+        Z[0] = fold_dc(zk, w, amp[M]);
         return;
     }
-    const cplx<T> Xk = cadd(Ev, wO);
-    const cplx<T> Xm = cconj(csub(Ev, wO));
-    const cplx<T> Yk = replace_modulus(Xk, amp[k]);
-    const cplx<T> Ym = replace_modulus(Xm, amp[M - k]);
-    const cplx<T> A = cadd(Yk, cconj(Ym));
-    const cplx<T> B = csub(Yk, cconj(Ym));
-    const cplx<T> cwB = cmul(cconj(w), B);
-    Z[k] = cmk(A.re - cwB.im, A.im + cwB.re);
-    if (mk != k) {
-        const cplx<T> wcB = cmul(w, cconj(B));
-        Z[mk] = cmk(A.re - wcB.im, -A.im + wcB.re);
-    }
+    cplx<T> yk, ym;
+    fold_pair(zk, zm, w, amp[k], amp[M - k], &yk, &ym);
+    Z[k] = yk;
+    if (mk != k) Z[mk] = ym;
 }
 
 // ----------------------------------------------------------------------------

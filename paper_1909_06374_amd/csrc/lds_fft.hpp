@@ -243,21 +243,34 @@ AGN_DEV cplx<T> replace_modulus(cplx<T> X, T a) {
 //   E_k     = (Z_k + conj Z_{M-k}) / 2,  O_k = (Z_k - conj Z_{M-k}) / 2i
 //   Z'_k    = A + i conj(W_N^k) B,       Z'_{M-k} = conj(A) + i W_N^k conj(B)
 //   A       = Y_k + conj Y_{M-k},        B = Y_k - conj Y_{M-k}
+// The two halves of fold_pair: the real-input spectrum of a Hermitian pair
+// from the half-length transform (w = W_N^k) ...
 template <typename T>
-AGN_DEV void fold_pair(cplx<T> zk, cplx<T> zm, cplx<T> w, T amp_k, T amp_m, cplx<T>* yk, cplx<T>* ym) {
+AGN_DEV void fold_spectrum(cplx<T> zk, cplx<T> zm, cplx<T> w, cplx<T>* Xk, cplx<T>* Xm) {
     const cplx<T> Ev = cmk((zk.re + zm.re) * (T)0.5, (zk.im - zm.im) * (T)0.5);
     const cplx<T> Ov = cmk((zk.im + zm.im) * (T)0.5, (zm.re - zk.re) * (T)0.5);
     const cplx<T> wO = cmul(w, Ov);
-    const cplx<T> Xk = cadd(Ev, wO);
-    const cplx<T> Xm = cconj(csub(Ev, wO));
-    const cplx<T> Yk = replace_modulus(Xk, amp_k);
-    const cplx<T> Ym = replace_modulus(Xm, amp_m);
+    *Xk = cadd(Ev, wO);
+    *Xm = cconj(csub(Ev, wO));
+}
+
+// ... and the half-length spectrum whose inverse transform is the real series
+// with half spectrum Y (Y_k, Y_{M-k} of one pair).
+template <typename T>
+AGN_DEV void unfold_pair(cplx<T> Yk, cplx<T> Ym, cplx<T> w, cplx<T>* yk, cplx<T>* ym) {
     const cplx<T> A = cadd(Yk, cconj(Ym));
     const cplx<T> B = csub(Yk, cconj(Ym));
     const cplx<T> cwB = cmul(cconj(w), B);
     *yk = cmk(A.re - cwB.im, A.im + cwB.re);  // A + i conj(w) B
     const cplx<T> wcB = cmul(w, cconj(B));
     *ym = cmk(A.re - wcB.im, -A.im + wcB.re);  // conj(A) + i w conj(B)
+}
+
+template <typename T>
+AGN_DEV void fold_pair(cplx<T> zk, cplx<T> zm, cplx<T> w, T amp_k, T amp_m, cplx<T>* yk, cplx<T>* ym) {
+    cplx<T> Xk, Xm;
+    fold_spectrum(zk, zm, w, &Xk, &Xm);
+    unfold_pair(replace_modulus(Xk, amp_k), replace_modulus(Xm, amp_m), w, yk, ym);
 }
 
 // DC and Nyquist (k = 0): Y_0 = 0, Y_M = amp_M sign(Re X_M).

@@ -111,6 +111,111 @@ AGN_DEV V block_sum(V v, V* scratch /* >= 64 */) {
     return t;
 }
 
+// Two-level FP64 twiddle table of length N in LDS at `at` (tw_lds_entries(N)
+// entries), filled from the half table tg[t] = W_N^t, t <= N/2.  All threads
+// of the block take part; the caller's next barrier publishes the table.
+AGN_DEV TwLds lds_load_twiddles(unsigned char* at, const cplx<double>* __restrict__ tg, int N, int tid, int nt) {
+    const int M = N / 2;
+    TwLds tw;
+    tw.bits = tw_lds_bits(N);
+    cplx<double>* lo = (cplx<double>*)at;
+    cplx<double>* hi = lo + (1 << tw.bits);
+    const int nlo = 1 << tw.bits, nhi = (N + nlo - 1) / nlo;
+    for (int u = tid; u < nlo + nhi; u += nt) {
+        int t = u < nlo ? u : (u - nlo) * nlo;
+        // nlo <= N/2 + 1 entries of the half table exist for every N >= 2
+        cplx<double> w;
+        if (t <= M) {
+            w = tg[t];
+        } else {
+            const cplx<double> v = tg[t - M];  // W_N^{t} = -W_N^{t - N/2}
+            w = cmk(-v.re, -v.im);
+        }
+        if (u < nlo) lo[u] = w;
+        else hi[u - nlo] = w;
+    }
+    tw.lo = lo;
+    tw.hi = hi;
+    return tw;
+}
+
+// Stable ascending ranking of the N = IPT * blockDim.x real values y held in
+// LDS at Zf[rpad(p)] (the inverse transform's output): on return
+// ibuf[hpad(k)] is the sample index at sorted position k, ties by index.
+// FP64: keys are the order-preserving integer images of y.  FP32 form: keys
+// are y mapped in FP64 onto 2^30 levels over [min y, max y] (rounded toward
+// zero).  The map is non-decreasing, not strictly increasing: two values
+// closer than its step, range * 2^-30, can share a key and are then ordered
+// by index.  That step lies far below the FP32 round-off of the transforms,
+// and 30-bit keys take 6 radix passes instead of 7.  Every thread of the
+// block calls this; it overwrites the LDS work region from `smem` on.
+template <typename T, int IPT>
+AGN_DEV void lds_rank_series(const T* Zf, unsigned char* smem, uint16_t* ibuf, uint32_t* scratch) {
+    typedef typename key_of<T>::type K;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    K key[IPT];
+    uint32_t idx2[IPT / 2];
+    const int tk = opaque(tid);
+    if constexpr (sizeof(T) == 4) {
+        float y[IPT];
+        float mn = Zf[rpad<T>(tk * IPT)], mx = mn;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            y[i] = Zf[rpad<T>(tk * IPT + i)];
+            mn = fminf(mn, y[i]);
+            mx = fmaxf(mx, y[i]);
+        }
+        // block min / max (the block is a power of two: one partial
+        // wave, or whole waves)
+        float* fs = (float*)scratch;  // free until the sort below (barrier before it)
+        if (nt < 64) {
+            fs[tid] = mn;
+            fs[32 + tid] = mx;
+            __syncthreads();
+            for (int w = 0; w < nt; ++w) {
+                mn = fminf(mn, fs[w]);
+                mx = fmaxf(mx, fs[32 + w]);
+            }
+        } else {
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                mn = fminf(mn, __shfl_xor(mn, o, 64));
+                mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+            }
+            const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: no VGPR to keep
+            if ((tid & 63) == 0) {
+                fs[wv] = mn;
+                fs[32 + wv] = mx;
+            }
+            __syncthreads();
+            // lane w loads wave w's extremes (lanes past the last wave
+            // repeat wave 0's), then the same butterfly across lanes
+            const int l = (tid & 63) < (nt >> 6) ? (tid & 63) : 0;
+            mn = fs[l];
+            mx = fs[32 + l];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                mn = fminf(mn, __shfl_xor(mn, o, 64));
+                mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+            }
+        }
+        const double lo = (double)mn, rng = (double)mx - lo;
+        const double sc = rng > 0.0 ? 1073741823.0 / rng : 0.0;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) key[i] = (K)fmin(((double)y[i] - lo) * sc, 1073741823.0);
+    } else {
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) key[i] = ord_key(Zf[rpad<T>(tk * IPT + i)]);
+    }
+#pragma unroll
+    for (int j = 0; j < IPT / 2; ++j)
+        idx2[j] = (uint32_t)(tk * IPT + 2 * j) | ((uint32_t)(tk * IPT + 2 * j + 1) << 16);
+    __syncthreads();
+    // FP32 form: indices < N <= 2^14 ride in the key word for the last passes
+    block_radix_sort<K, IPT, true, sizeof(T) == 4 ? 30 : 8 * (int)sizeof(K), sizeof(T) == 4 ? 14 : 0>(
+        key, idx2, smem, ibuf, scratch);
+}
+
 // One-time preparation: stable argsort of the draw (64-bit keys), sorted
 // tables and starting ranks.  Same block shape as the iteration kernel.
 template <typename T, int E>
@@ -158,7 +263,6 @@ __global__ __launch_bounds__(1024) void k_lds_prep(const LcDesc* __restrict__ de
 // transform's last pass is fused with the replacement (lds_fold_replace_r2).
 template <typename T, int E, bool FUSE2>
 __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__ descs) {
-    typedef typename key_of<T>::type K;
     constexpr int IPT = 2 * E;
     extern __shared__ __align__(16) unsigned char smem[];
     const LcDesc& d = descs[blockIdx.x];
@@ -183,30 +287,7 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
     const T* __restrict__ sT = (const T*)d.sT;
     const double* __restrict__ s64 = d.s64;
     const double* __restrict__ L = d.L;
-    // two-level twiddle table (double) in LDS, from the half table W_N^t, t <= N/2
-    TwLds tw;
-    tw.bits = tw_lds_bits(N);
-    {
-        cplx<double>* lo = (cplx<double>*)(smem + tw_off);
-        cplx<double>* hi = lo + (1 << tw.bits);
-        const cplx<double>* __restrict__ tg = (const cplx<double>*)d.tw;
-        const int nlo = 1 << tw.bits, nhi = (N + nlo - 1) / nlo;
-        for (int u = tid; u < nlo + nhi; u += nt) {
-            int t = u < nlo ? u : (u - nlo) * nlo;
-            // nlo <= N/2 + 1 entries of the half table exist for every N >= 2
-            cplx<double> w;
-            if (t <= M) {
-                w = tg[t];
-            } else {
-                const cplx<double> v = tg[t - M];  // W_N^{t} = -W_N^{t - N/2}
-                w = cmk(-v.re, -v.im);
-            }
-            if (u < nlo) lo[u] = w;
-            else hi[u - nlo] = w;
-        }
-        tw.lo = lo;
-        tw.hi = hi;
-    }
+    const TwLds tw = lds_load_twiddles(smem + tw_off, (const cplx<double>*)d.tw, N, tid, nt);
     const FftPlan& plan = d.plan;  // read in place (uniform loads), not copied to private memory
 
 #pragma unroll 4
@@ -232,73 +313,7 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
             lds_fft<T, E, true>(Zc, M, plan, tid, nt, tw);
         }
 
-        {
-            K key[IPT];
-            uint32_t idx2[IPT / 2];
-            const int tk = opaque(tid);
-            if constexpr (sizeof(T) == 4) {
-                // FP32 form: keys are y mapped in FP64 onto 2^30 levels over
-                // [min y, max y].  The map is monotone, so order is kept; its
-                // step, range * 2^-30, lies far below the FP32 round-off of the
-                // transforms, and 30-bit keys take 6 radix passes instead of 7.
-                float y[IPT];
-                float mn = Zf[rpad<T>(tk * IPT)], mx = mn;
-#pragma unroll
-                for (int i = 0; i < IPT; ++i) {
-                    y[i] = Zf[rpad<T>(tk * IPT + i)];
-                    mn = fminf(mn, y[i]);
-                    mx = fmaxf(mx, y[i]);
-                }
-                // block min / max (the block is a power of two: one partial
-                // wave, or whole waves)
-                float* fs = (float*)scratch;  // free until the sort below (barrier before it)
-                if (nt < 64) {
-                    fs[tid] = mn;
-                    fs[32 + tid] = mx;
-                    __syncthreads();
-                    for (int w = 0; w < nt; ++w) {
-                        mn = fminf(mn, fs[w]);
-                        mx = fmaxf(mx, fs[32 + w]);
-                    }
-                } else {
-#pragma unroll
-                    for (int o = 32; o >= 1; o >>= 1) {
-                        mn = fminf(mn, __shfl_xor(mn, o, 64));
-                        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-                    }
-                    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: no VGPR to keep
-                    if ((tid & 63) == 0) {
-                        fs[wv] = mn;
-                        fs[32 + wv] = mx;
-                    }
-                    __syncthreads();
-                    // lane w loads wave w's extremes (lanes past the last wave
-                    // repeat wave 0's), then the same butterfly across lanes
-                    const int l = (tid & 63) < (nt >> 6) ? (tid & 63) : 0;
-                    mn = fs[l];
-                    mx = fs[32 + l];
-#pragma unroll
-                    for (int o = 32; o >= 1; o >>= 1) {
-                        mn = fminf(mn, __shfl_xor(mn, o, 64));
-                        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-                    }
-                }
-                const double lo = (double)mn, rng = (double)mx - lo;
-                const double sc = rng > 0.0 ? 1073741823.0 / rng : 0.0;
-#pragma unroll
-                for (int i = 0; i < IPT; ++i) key[i] = (K)fmin(((double)y[i] - lo) * sc, 1073741823.0);
-            } else {
-#pragma unroll
-                for (int i = 0; i < IPT; ++i) key[i] = ord_key(Zf[rpad<T>(tk * IPT + i)]);
-            }
-#pragma unroll
-            for (int j = 0; j < IPT / 2; ++j)
-                idx2[j] = (uint32_t)(tk * IPT + 2 * j) | ((uint32_t)(tk * IPT + 2 * j + 1) << 16);
-            __syncthreads();
-            // FP32 form: indices < N <= 2^14 ride in the key word for the last passes
-            block_radix_sort<K, IPT, true, sizeof(T) == 4 ? 30 : 8 * (int)sizeof(K), sizeof(T) == 4 ? 14 : 0>(
-                key, idx2, smem, ibuf, scratch);
-        }
+        lds_rank_series<T, IPT>(Zf, smem, ibuf, scratch);
 
         // x_i[t] = s[k]; Eq. 4 terms from the log10 table.  The exact
         // fixed-point test (values equal, not only ranks) matters only to the

@@ -1,0 +1,183 @@
+"""GPU parity of the iteration's transforms and ranking, each on its own.
+
+The C ABI's test exports run the iteration's own FFT passes, real-spectrum
+fold and radix sorts (LDS-resident and multi-pass kernels) on given inputs;
+here they meet the oracle's plain definitions: the real DFT of App. A (Eq. A1,
+negative exponent forward), its unnormalised inverse, and the stable argsort
+of Sec. 2.1.
+
+Bars.  Transforms: both sides get the same input in the working precision
+(the FP32 form rounds x to float on load; the oracle is given the same rounded
+values), so the difference is the transform's own round-off.  A fast
+transform with correctly rounded twiddles has a relative rms error of
+c eps sqrt(log2 N) with c of order one (eps = 2^-53 in FP64, 2^-24 in FP32;
+the oracle's FP64 error is negligible against FP32); the test measures c per
+length and asks c <= 3, and every element within 8 eps log2(N) ||x||_2
+(the worst-case bound, constant 8 for both transforms together).  A wrong
+twiddle, sign or index gives errors of order one.  Ranking: bit-exact against
+the oracle's stable argsort of the keys the path sorts (FP64 values; FP32
+values; in the FP32 form on the LDS path the 2^30-level image of y, whose
+formula the header states and this file restates).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+LDS_POW2 = [2**a for a in range(1, 15)]
+LDS_THREE = [3 * 2**a for a in range(1, 13)]
+HBM = [8192, 16384, 32768, 65536, 2**17, 24576, 49152, 98304, 196608]
+EPS = {0: 2.0**-53, 1: 2.0**-24}
+
+
+def agn():
+    import paper_1909_06374_amd as m
+    return m
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def lds_ok(n, prec):
+    return (n <= 12288) if n % 3 == 0 else (n <= (16384 if prec == 1 else 8192))
+
+
+def cases(prec):
+    out = [(n, 0) for n in LDS_POW2 + LDS_THREE if lds_ok(n, prec)]
+    return out + [(n, 1) for n in HBM]
+
+
+ALL = [(n, path, prec) for prec in (0, 1) for (n, path) in cases(prec)]
+IDS = [f"n{n}-{'lds' if path == 0 else 'hbm'}-{'fp32' if prec else 'fp64'}" for n, path, prec in ALL]
+
+
+def series(n, seed):
+    """Red-noise-like test input: a random walk plus white noise (both the
+    smooth and the rough part of the spectrum are populated)."""
+    g = np.random.Generator(np.random.Philox(seed))
+    return np.cumsum(g.standard_normal(n)) * 0.05 + g.standard_normal(n)
+
+
+def in_prec(x, prec):
+    return x.astype(np.float32).astype(np.float64) if prec == 1 else x
+
+
+def run(fn, ctx, inp, n, prec, path, out):
+    m = agn()
+    ws = torch.empty(m.agn_test_workspace_size(n, prec, path), dtype=torch.uint8, device="cuda:0")
+    getattr(m, fn)(ctx, torch.as_tensor(inp).to("cuda:0"), n, prec, path, out, ws)
+    return host(out)
+
+
+def c_of(err, ref, n, prec):
+    rel = np.sqrt(np.mean(np.abs(err) ** 2)) / np.sqrt(np.mean(np.abs(ref) ** 2))
+    return rel / (EPS[prec] * math.sqrt(max(math.log2(n), 1.0)))
+
+
+@pytest.mark.parametrize("n,path,prec", ALL, ids=IDS)
+def test_rfft_matches_oracle(gpu_ctx, n, path, prec):
+    x = in_prec(series(n, 1000 + n), prec)
+    X = run("agn_test_rfft", gpu_ctx, x, n, prec, path,
+            torch.full((2 * (n // 2 + 1),), float("nan"), dtype=torch.float64, device="cuda:0"))
+    Xg = X[0::2] + 1j * X[1::2]
+    Xr = oracle.rfft(x)
+    err = Xg - Xr
+    bound = 8 * EPS[prec] * max(math.log2(n), 1.0) * np.linalg.norm(x)
+    assert np.all(np.isfinite(Xg))
+    assert np.max(np.abs(err)) <= bound, (np.max(np.abs(err)), bound)
+    c = c_of(err, Xr, n, prec)
+    print(f"rfft n={n} path={path} prec={prec}: c = {c:.3f}")
+    assert c <= 3.0
+
+
+@pytest.mark.parametrize("n,path,prec", ALL, ids=IDS)
+def test_irfft_matches_oracle(gpu_ctx, n, path, prec):
+    g = np.random.Generator(np.random.Philox(2000 + n))
+    h = n // 2 + 1
+    Y = g.standard_normal(h) + 1j * g.standard_normal(h)
+    Y /= np.sqrt(1.0 + np.arange(h))  # red spectrum
+    Y[0] = Y[0].real
+    Y[-1] = Y[-1].real
+    if prec == 1:
+        Y = Y.real.astype(np.float32).astype(np.float64) + 1j * Y.imag.astype(np.float32).astype(np.float64)
+    Yi = np.empty(2 * h)
+    Yi[0::2], Yi[1::2] = Y.real, Y.imag
+    y = run("agn_test_irfft", gpu_ctx, Yi, n, prec, path,
+            torch.full((n,), float("nan"), dtype=torch.float64, device="cuda:0"))
+    yr = oracle.irfft(Y, n)
+    err = y - yr
+    # ||y||_2 = sqrt(n) ||Y_full||_2 for the unnormalised inverse
+    yfull = np.sqrt(n) * np.sqrt(np.abs(Y[0]) ** 2 + np.abs(Y[-1]) ** 2 + 2 * np.sum(np.abs(Y[1:-1]) ** 2)) \
+        if n > 2 else np.linalg.norm(yr)
+    bound = 8 * EPS[prec] * max(math.log2(n), 1.0) * yfull
+    assert np.all(np.isfinite(y))
+    assert np.max(np.abs(err)) <= bound, (np.max(np.abs(err)), bound)
+    c = c_of(err, yr, n, prec)
+    print(f"irfft n={n} path={path} prec={prec}: c = {c:.3f}")
+    assert c <= 3.0
+
+
+def lds_fp32_keys(y):
+    """The FP32 form's LDS ranking keys (as the header states): y rounded to
+    float, mapped in double onto 2^30 levels over [min, max], truncated."""
+    y32 = y.astype(np.float32)
+    lo = np.float64(y32.min())
+    rng = np.float64(y32.max()) - lo
+    sc = (2.0**30 - 1.0) / rng if rng > 0 else 0.0
+    return np.floor(np.minimum((y32.astype(np.float64) - lo) * sc, 2.0**30 - 1.0))
+
+
+def sort_inputs(n, seed):
+    g = np.random.Generator(np.random.Philox(seed))
+    out = {"noise": series(n, seed)}
+    v = g.integers(-3, 4, n).astype(np.float64) * 0.5  # many ties, both zeros
+    v[v == 0.0] = np.where(g.random(np.sum(v == 0.0)) < 0.5, -0.0, 0.0)
+    out["ties_and_signed_zeros"] = v
+    out["all_equal"] = np.full(n, 0.25)
+    out["descending"] = -np.arange(n, dtype=np.float64)
+    return out
+
+
+@pytest.mark.parametrize("n,path,prec", ALL, ids=IDS)
+def test_argsort_matches_oracle(gpu_ctx, n, path, prec):
+    for name, y in sort_inputs(n, 3000 + n).items():
+        r = run("agn_test_argsort", gpu_ctx, y, n, prec, path,
+                torch.full((n,), -1, dtype=torch.int32, device="cuda:0")).view(np.uint32)
+        if prec == 0:
+            keys = y
+        elif path == 0:
+            keys = lds_fp32_keys(y)
+        else:
+            keys = in_prec(y, 1)
+        perm = oracle.argsort(keys)
+        ref = np.empty(n, dtype=np.uint32)
+        ref[perm] = np.arange(n, dtype=np.uint32)
+        assert np.array_equal(r, ref), (name, np.sum(r != ref))
+
+
+@pytest.mark.parametrize("n", [1024, 4096, 8192, 12288, 16384])
+def test_lds_fp32_key_collisions_are_counted(gpu_ctx, n):
+    """The FP32 form's 2^30-level keys on the LDS path merge distinct float
+    values closer than (max - min) 2^-30; such values are then ordered by
+    index.  On a red-noise series of the iteration's kind, count how many
+    ranks differ from the exact argsort of the float values."""
+    y = series(n, 4000 + n)
+    r = run("agn_test_argsort", gpu_ctx, y, n, 1, 0,
+            torch.full((n,), -1, dtype=torch.int32, device="cuda:0")).view(np.uint32)
+    perm = oracle.argsort(in_prec(y, 1))
+    exact = np.empty(n, dtype=np.uint32)
+    exact[perm] = np.arange(n, dtype=np.uint32)
+    k = lds_fp32_keys(y)
+    ks = np.sort(k)
+    collisions = int(np.sum(ks[1:] == ks[:-1]))
+    differ = int(np.sum(r != exact))
+    print(f"n={n}: key collisions {collisions}, ranks differing from the float argsort {differ}")
+    assert differ <= 2 * collisions
