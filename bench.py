@@ -134,7 +134,8 @@ def hbm_bytes_per_sample(kernel, prec_bytes):
         return 2 * (prec_bytes + 4)
     if kernel == "sort_hist":
         return prec_bytes
-    if kernel == "fold":
+    if kernel in ("fold", "fft_mid"):
+        # read and write the complex buffer, read the target moduli
         return 2 * prec_bytes + prec_bytes // 2
     return 8
 
@@ -406,8 +407,18 @@ def run_standard(args, agn, synth, np, torch):
 
     if prec == agn.AGN_FP32 and not args.no_accuracy and args.workload in ("ptf_batch", "lsst_long"):
         k = 8 if args.workload == "ptf_batch" else 1
+        if args.workload == "ptf_batch":
+            # the whole batch in FP64 for the ensemble statistic
+            x64 = torch.empty_like(x)
+            ws64 = torch.empty(agn.agn_batch_workspace_size(ns, agn.AGN_FP64), dtype=torch.uint8, device=dev)
+            agn.agn_lc_generate_batch(ctx, ns, offs, params, [dt_days] * n_curves, [iters] * n_curves, seeds, ids,
+                                      erdf_t, -1.0, agn.AGN_FP64, x64, None, None, ws64)
+            del ws64
         out["accuracy_vs_fp64"] = fp32_accuracy(agn, np, torch, ctx, x, ns, offs, params, dt_days, iters,
                                                 seeds, ids, erdf_t, k=k, x64_all=x64)
+        if x64 is not None:
+            out["accuracy_vs_fp64"]["ensemble_log_binned_periodogram_rel_diff_median_max"] = \
+                ensemble_periodogram_diff(agn, np, torch, ctx, x, x64, ns, offs)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = oracle_baseline(args, np, params, erdf, erdf_t, n, n_curves, dt_days, iters,
@@ -468,6 +479,25 @@ def oracle_baseline(args, np, params, erdf, erdf_t, n, n_curves, dt_days, iters,
             "sample": f"first {k} curve(s) of the workload, all {iters} iterations, one curve per thread, "
                       f"{reps} pass(es) ({wall_all:.1f} s wall)",
             "single_thread_samples_per_s": float(n / np.mean(secs_all)), **info}
+
+
+def ensemble_periodogram_diff(agn, np, torch, ctx, x32, x64, ns, offs, dex=0.1):
+    """Relative difference, bin by bin, of the mean 0.1-dex log-binned
+    periodogram (Eq. A2) over all curves: FP32 form against FP64 (the
+    ensemble statistic of Sec. 3.2.5).  Curves of one length only."""
+    n, nc = ns[0], len(ns)
+    nb = agn.agn_log_bin_count(n, dex)
+    h = n // 2 + 1
+    pws = torch.empty(agn.agn_periodogram_workspace_size(ns, dex), dtype=torch.uint8, device="cuda:0")
+    P = torch.empty(nc * h, dtype=torch.float64, device="cuda:0")
+    means = []
+    for xx in (x32, x64):
+        b = torch.empty(nc * nb, dtype=torch.float64, device="cuda:0")
+        agn.agn_periodogram_batch(ctx, ns, offs, xx, [c * h for c in range(nc)], P, dex,
+                                  [c * nb for c in range(nc)], b, pws)
+        means.append(b.cpu().numpy().reshape(nc, nb).mean(axis=0))
+    rel = np.abs(means[0] / means[1] - 1.0)
+    return [float(np.median(rel)), float(rel.max())]
 
 
 def log_binned_periodogram(np, x, dex=0.1):

@@ -194,7 +194,7 @@ struct agn_ctx {
 };
 
 static const char* KERNEL_NAMES =
-    "spectrum_partial,spectrum_norm,spectrum_amp,lds_prep,lds_iterate,big_prep,fft_pass,fold,"
+    "spectrum_partial,spectrum_norm,spectrum_amp,lds_prep,lds_iterate,big_prep,fft_pass,fft_mid,"
     "sort_hist,sort_scan,sort_scatter,delta,big_output,erdf_draw,batch_graph,periodogram,log_bins,lag_stats,psd_fit";
 
 // Kernel timing: events recorded on the launch stream around each launch.
@@ -611,6 +611,40 @@ static void launch_fft_pass(agn_ctx* ctx, const BigCurve* d, int nc, const FftPa
     }
 }
 
+// Column pairs per workgroup of the middle pass: the largest of 32, 16, 8 with
+// the 2 * cols columns of R values within the tile and dividing M / R.
+static int mid_cols(int64_t M, int R, agn_precision prec) {
+    for (int c = 32; c >= 8; c >>= 1)
+        if ((int64_t)R * 2 * c <= fft_tile(prec) && (M / R) % (2 * c) == 0) return c;
+    return 0;
+}
+
+static MidPass make_mid(int64_t M, int R, int src_sel, int dst_sel, agn_precision prec) {
+    MidPass P;
+    memset(&P, 0, sizeof(P));
+    P.M = M;
+    P.R = R;
+    P.cols = mid_cols(M, R, prec);
+    P.nthreads = R * 2 * P.cols / 16;
+    P.src_sel = src_sel;
+    P.dst_sel = dst_sel;
+    P.sub = make_plan(R);
+    return P;
+}
+
+template <typename T, int MODE>
+static void launch_fft_mid(agn_ctx* ctx, const BigCurve* d, int nc, const MidPass& P, const TwTable& tb,
+                           hipStream_t st) {
+    const int C2 = 2 * P.cols;
+    const size_t lds = (size_t)(P.R * C2 + 1 + ((P.R * C2 + 1) >> (sizeof(T) == 4 ? 5 : 4))) * sizeof(cplx<T>) +
+                       16 + (size_t)P.R * sizeof(cplx<T>);
+    const dim3 grid((unsigned)(P.M / P.R / C2), (unsigned)nc);
+    ProfScope ps(ctx, "fft_mid", st);
+    if (P.cols == 32) hipLaunchKernelGGL((k_fft_mid<T, 16, 32, MODE>), grid, dim3(P.nthreads), lds, st, d, P, tb);
+    else if (P.cols == 16) hipLaunchKernelGGL((k_fft_mid<T, 16, 16, MODE>), grid, dim3(P.nthreads), lds, st, d, P, tb);
+    else hipLaunchKernelGGL((k_fft_mid<T, 16, 8, MODE>), grid, dim3(P.nthreads), lds, st, d, P, tb);
+}
+
 template <typename K, int TILE>
 static void launch_sort_pass_t(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, const SortPass& P,
                                hipStream_t st) {
@@ -660,13 +694,23 @@ static int big_group_setup(agn_ctx* ctx, int64_t n, agn_precision prec, TwTable*
     if (rc) return rc;
     *rad = big_radices(M, prec);
     if (rad->empty()) return fail(AGN_EUNSUPPORTED_N, "internal: no FFT plan for n=%lld", (long long)n);
+    // forward passes 0 .. np-2, the middle pass (radix rad[np-1]), then the
+    // inverse passes in the reverse radix order
+    const int np = (int)rad->size();
+    bool ok = np >= 2 && mid_cols(M, rad->back(), prec) != 0 && rad->back() >= 16 && rad->back() <= 512;
     int64_t ns = 1;
-    for (int r : *rad) {
+    for (int p = 0; ok && p < np - 1; ++p) {
+        const int r = (*rad)[p];
         const int c = fft_cols(M, r, ns, prec);
-        if (c == 0 || r > 512 || (ns > 1 && ns % c != 0) || (ns == 1 && r < 64) || r < 16)
-            return fail(AGN_EUNSUPPORTED_N, "internal: no FFT plan for n=%lld", (long long)n);
+        ok = c != 0 && r <= 512 && r >= 16 && !(ns == 1 && r < 64);
         ns *= r;
     }
+    ns = rad->back();
+    for (int p = np - 2; ok && p >= 0; --p) {
+        ok = fft_cols(M, (*rad)[p], ns, prec) != 0;
+        ns *= (*rad)[p];
+    }
+    if (!ok) return fail(AGN_EUNSUPPORTED_N, "internal: no FFT plan for n=%lld", (long long)n);
     return AGN_OK;
 }
 
@@ -702,7 +746,7 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
         const int cur = it & 1;  // x_it lives in X0 (even) or X1 (odd)
         int sel = 0;             // region written by the next FFT pass
         int64_t Ns = 1;
-        for (int p = 0; p < np; ++p) {
+        for (int p = 0; p < np - 1; ++p) {
             FftPass P;
             memset(&P, 0, sizeof(P));
             P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, prec); P.nthreads = rad[p] * P.cols / 16;
@@ -720,18 +764,16 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
             Ns *= rad[p];
             sel = 1 - sel;
         }
-        {
-            ProfScope ps(ctx, "fold", st);
-            hipLaunchKernelGGL(k_big_fold<T>, dim3((unsigned)((M / 2 + 1 + 255) / 256), (unsigned)nc), dim3(256),
-                               0, st, d, M, 1 - sel, tb);
-        }
-        Ns = 1;
-        for (int p = 0; p < np; ++p) {
+        // last forward pass + fold / replacement + first inverse pass
+        launch_fft_mid<T, MID_REPLACE>(ctx, d, nc, make_mid(M, rad[np - 1], 1 - sel, sel, prec), tb, st);
+        sel = 1 - sel;
+        Ns = rad[np - 1];
+        for (int p = np - 2; p >= 0; --p) {
             FftPass P;
             memset(&P, 0, sizeof(P));
             P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, prec); P.nthreads = rad[p] * P.cols / 16;
             P.Ns = Ns;
-            P.in_mode = 0; P.out_mode = (p == np - 1) ? 1 : 0; P.inverse = 1;
+            P.in_mode = 0; P.out_mode = (p == 0) ? 1 : 0; P.inverse = 1;
             P.src_sel = 1 - sel; P.dst_sel = sel; P.sub = make_plan(rad[p]);
             launch_fft_pass<T>(ctx, d, nc, P, tb, st);
             Ns *= rad[p];
@@ -2069,7 +2111,7 @@ static int test_run_big(agn_ctx* ctx, int mode, int64_t n, agn_precision prec, c
     const BigCurve* dv = (const BigCurve*)ws;
     hipLaunchKernelGGL(k_big_init, dim3(1), dim3(64), 0, st, dv);
     const int np = (int)rad.size();
-    const unsigned hb = (unsigned)((M / 2 + 1 + 255) / 256), nb = (unsigned)((n + 255) / 256);
+    const unsigned nb = (unsigned)((n + 255) / 256);
     if (mode == TEST_RANK) {
         hipLaunchKernelGGL((k_test_big_keys<T>), dim3(nb), dim3(256), 0, st, dv, n, in);
         int src = 0;
@@ -2086,24 +2128,47 @@ static int test_run_big(agn_ctx* ctx, int mode, int64_t n, agn_precision prec, c
         }
         return AGN_OK;
     }
-    const bool inv = mode == TEST_IRFFT;
-    int sel = inv ? 1 : 0;  // region written by the next pass
-    if (inv) hipLaunchKernelGGL((k_test_big_unfold<T>), dim3(hb), dim3(256), 0, st, dv, M, 0, tb, in);
+    // The iteration's transforms: forward passes 0 .. np-2, then the middle
+    // pass, whose fold writes the spectrum (rfft); or the middle pass started
+    // from the given half spectrum, then the inverse passes in reverse radix
+    // order (irfft).
+    int sel = 0;  // region written by the next pass
     int64_t Ns = 1;
-    for (int p = 0; p < np; ++p) {
+    if (mode == TEST_RFFT) {
+        for (int p = 0; p < np - 1; ++p) {
+            FftPass P;
+            memset(&P, 0, sizeof(P));
+            P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, prec); P.nthreads = rad[p] * P.cols / 16;
+            P.Ns = Ns;
+            P.in_mode = p == 0 ? 1 : 0; P.out_mode = 0; P.inverse = 0;
+            P.x_sel = 0; P.with_delta = 0;
+            P.src_sel = 1 - sel; P.dst_sel = sel; P.sub = make_plan(rad[p]);
+            launch_fft_pass<T>(ctx, dv, 1, P, tb, st);
+            Ns *= rad[p];
+            sel = 1 - sel;
+        }
+        MidPass P = make_mid(M, rad[np - 1], 1 - sel, sel, prec);
+        P.X_out = out;
+        launch_fft_mid<T, MID_SPECTRUM>(ctx, dv, 1, P, tb, st);
+        return AGN_OK;
+    }
+    MidPass Pm = make_mid(M, rad[np - 1], 1, 0, prec);
+    Pm.Y_in = in;
+    launch_fft_mid<T, MID_UNFOLD>(ctx, dv, 1, Pm, tb, st);
+    sel = 1;
+    Ns = rad[np - 1];
+    for (int p = np - 2; p >= 0; --p) {
         FftPass P;
         memset(&P, 0, sizeof(P));
         P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, prec); P.nthreads = rad[p] * P.cols / 16;
         P.Ns = Ns;
-        P.in_mode = (!inv && p == 0) ? 1 : 0; P.out_mode = 0; P.inverse = inv ? 1 : 0;
-        P.x_sel = 0; P.with_delta = 0;
+        P.in_mode = 0; P.out_mode = 0; P.inverse = 1;
         P.src_sel = 1 - sel; P.dst_sel = sel; P.sub = make_plan(rad[p]);
         launch_fft_pass<T>(ctx, dv, 1, P, tb, st);
         Ns *= rad[p];
         sel = 1 - sel;
     }
-    if (inv) hipLaunchKernelGGL((k_test_big_real<T>), dim3(nb), dim3(256), 0, st, dv, n, 1 - sel, out);
-    else hipLaunchKernelGGL((k_test_big_spectrum<T>), dim3(hb), dim3(256), 0, st, dv, M, 1 - sel, tb, out);
+    hipLaunchKernelGGL((k_test_big_real<T>), dim3(nb), dim3(256), 0, st, dv, n, 1 - sel, out);
     return AGN_OK;
 }
 

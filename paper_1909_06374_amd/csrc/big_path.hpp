@@ -6,8 +6,11 @@
 //   FFT passes   the first pass reads x_i and x_{i-1} in time order, adds the
 //                Eq. 4 terms log10(x_i / x_{i-1})^2 of the previous iteration to
 //                per-block partials, and feeds z[m] = x[2m] + i x[2m+1]
-//   fold pass    real-spectrum fold, modulus replacement, unfold (pairs k, M-k)
-//   IFFT passes  ... -> y, written as order-preserving integer keys
+//   middle pass  the forward transform's last pass, the real-spectrum fold
+//                with the modulus replacement (pairs k, M-k), and the inverse
+//                transform's first pass (k_fft_mid)
+//   IFFT passes  the remaining radices in reverse order ... -> y, written as
+//                order-preserving integer keys
 //   sort passes  LSD radix sort of (key, sample index), 8-bit digits: per tile
 //                histogram -> per-curve scan -> stable scatter staged through
 //                LDS in digit order, so global writes are contiguous runs; the
@@ -295,28 +298,165 @@ __global__ __launch_bounds__(512) void k_fft_pass(const BigCurve* __restrict__ c
     }
 }
 
-// Fold to the real spectrum, replace moduli, unfold (same algebra as the LDS
-// path; see lds_fold_replace).  grid: (ceil((M/2 + 1) / 256), curves).
-template <typename T>
-__global__ __launch_bounds__(256) void k_big_fold(const BigCurve* __restrict__ cv, int64_t M, int sel,
-                                                  TwTable tb) {
+// ----------------------------------------------------------------------------
+// Middle pass: the forward transform's last radix-R pass, the real-spectrum
+// fold with the modulus replacement, and the inverse transform's first
+// radix-R pass, in one trip through HBM.
+//
+// The last forward pass (stride Ns = M/R) maps column j -- the R values
+// z[j + r M/R] -- onto itself: output q is Z[j + q M/R].  The Hermitian
+// partner of Z[j + q M/R] is Z[(M/R - j) + (R - 1 - q) M/R] for j >= 1, i.e.
+// in the mirror column M/R - j; columns 0 and M/R/2 pair with themselves.
+// The inverse transform runs its radices in the reverse order, so its first
+// pass (radix R, stride 1) again reads whole columns and writes column j's
+// outputs to z[j R .. j R + R).  A workgroup therefore takes C columns
+// j0 .. j0+C-1 and their C mirrors (slot C + m holds column M/R - j0 - m;
+// in block 0, slot C holds the self-paired column M/R/2, as column M/R does
+// not exist), and needs no data from any other workgroup.
+// Modes (compile time): MID_REPLACE is the iteration; MID_SPECTRUM writes the
+// real-input spectrum X (double) instead of continuing; MID_UNFOLD starts from
+// a given half spectrum Y (double) instead of the forward pass.  The last two
+// serve the test exports.
+// ----------------------------------------------------------------------------
+enum { MID_REPLACE = 0, MID_SPECTRUM = 1, MID_UNFOLD = 2 };
+
+struct MidPass {
+    int64_t M;           // complex length
+    int32_t R;           // radix of the last forward / first inverse pass (<= 512)
+    int32_t nthreads;    // R * 2 * cols / E
+    int32_t cols;        // column pairs per workgroup (C)
+    int32_t src_sel;     // complex input region (sortA 0 / sortB 1)
+    int32_t dst_sel;     // complex output region
+    FftPlan sub;         // radices of the in-LDS length-R DFT
+    double* X_out;       // MID_SPECTRUM: n/2 + 1 complex doubles
+    const double* Y_in;  // MID_UNFOLD: n/2 + 1 complex doubles
+};
+
+// grid: (M / R / (2 C), curves), block P.nthreads (E = 2 R C / nthreads).
+template <typename T, int E, int C, int MODE>
+__global__ __launch_bounds__(512) void k_fft_mid(const BigCurve* __restrict__ cv, MidPass P, TwTable tb) {
+    constexpr int C2 = 2 * C;
+    extern __shared__ __align__(16) unsigned char smem[];
     const BigCurve& d = cv[blockIdx.y];
     if (d.state[1] == 0) return;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > M / 2) return;
-    cplx<T>* Z = (cplx<T>*)(sel ? d.sortB : d.sortA);
-    const T* amp = (const T*)d.amp;
-    const int64_t mk = (k == 0) ? 0 : M - k;
-    const cplx<T> zk = Z[k], zm = Z[mk];
-    const cplx<T> w = to_T<T>(tw64(tb, k));
-    if (k == 0) {
-        Z[0] = fold_dc(zk, w, amp[M]);
-        return;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int R = P.R;
+    const int64_t M = P.M, N = 2 * M, MR = M / R;
+    const int64_t j0 = (int64_t)blockIdx.x * C;
+    cplx<T>* buf = (cplx<T>*)smem;
+    cplx<T>* wr = (cplx<T>*)(smem + (size_t)tpad<T>(R * C2 + 1) * sizeof(cplx<T>) + 16);
+    for (int u = tid; u < R; u += nt) wr[u] = to_T<T>(tw64(tb, (int64_t)u * (N / R)));
+    // column of slot sl
+    auto col_of = [&](int sl) -> int64_t {
+        if (sl < C) return j0 + sl;
+        const int m = sl - C;
+        return (j0 == 0 && m == 0) ? MR / 2 : MR - j0 - m;
+    };
+
+    if constexpr (MODE != MID_UNFOLD) {
+        // Load the columns; element (r, slot) takes the last forward pass's
+        // twiddle W_M^{j r} = W_N^{2 j r}, formed in FP64 as in k_fft_pass.
+        const cplx<T>* src = (const cplx<T>*)(P.src_sel ? d.sortB : d.sortA);
+        const int c_t = tid % C2, r_t = tid / C2, dr = nt / C2;
+        const int64_t jc = col_of(c_t);
+        cplx<double> wk = tw64(tb, 2 * jc * r_t);
+        const cplx<double> wstep = tw64(tb, 2 * jc * dr);
+        static_assert(E % 2 == 0, "E must be even");
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            cplx<T> v[E / 2];
+#pragma unroll
+            for (int u = 0; u < E / 2; ++u) {
+                const int r = r_t + (h * (E / 2) + u) * dr;
+                v[u] = src[jc + (int64_t)r * MR];
+            }
+#pragma unroll
+            for (int u = 0; u < E / 2; ++u) {
+                const int e = tid + (h * (E / 2) + u) * nt;
+                buf[tpad<T>(e)] = cmul(v[u], to_T<T>(wk));
+                wk = cmul(wk, wstep);
+            }
+        }
+        __syncthreads();
+        col_fft<T, E, false, C2>(buf, wr, R, P.sub, tid, nt);
     }
-    cplx<T> yk, ym;
-    fold_pair(zk, zm, w, amp[k], amp[M - k], &yk, &ym);
-    Z[k] = yk;
-    if (mk != k) Z[mk] = ym;
+
+    // Hermitian pairs.  Item e < R C: primary element (q, s); block 0 adds
+    // R/2 items for the self-paired column M/R/2 in slot C.  Each pair is
+    // taken once, with ka = its index <= M/2 (the fold's convention).
+    const T* amp = (const T*)d.amp;
+    const int items = R * C + (j0 == 0 ? R / 2 : 0);
+    for (int e = tid; e < items; e += nt) {
+        int qa, sa, qb, sb;
+        int64_t ka;
+        bool dc = false, self = false;
+        if (e < R * C) {
+            const int sl = e % C, q = e / C;
+            const int64_t j = j0 + sl, k = j + (int64_t)q * MR;
+            if (j == 0) {
+                if (2 * q > R) continue;  // taken as the partner of row R - q
+                dc = q == 0;
+                self = 2 * q == R;
+                ka = k; qa = q; sa = 0; qb = (R - q) % R; sb = 0;
+            } else if (2 * k <= M) {
+                ka = k; qa = q; sa = sl; qb = R - 1 - q; sb = C + sl;
+            } else {
+                ka = M - k; qa = R - 1 - q; sa = C + sl; qb = q; sb = sl;
+            }
+        } else {
+            const int q = e - R * C;
+            ka = MR / 2 + (int64_t)q * MR; qa = q; sa = C; qb = R - 1 - q; sb = C;
+        }
+        const cplx<T> w = to_T<T>(tw64(tb, ka));
+        cplx<T>& za = buf[tpad<T>(qa * C2 + sa)];
+        cplx<T>& zb = buf[tpad<T>(qb * C2 + sb)];
+        if constexpr (MODE == MID_REPLACE) {
+            if (dc) {
+                za = fold_dc(za, w, amp[M]);
+            } else if (self) {
+                cplx<T> ya, unused;
+                fold_pair(za, za, w, amp[ka], amp[ka], &ya, &unused);
+                za = ya;
+            } else {
+                cplx<T> ya, yb;
+                fold_pair(za, zb, w, amp[ka], amp[M - ka], &ya, &yb);
+                za = ya;
+                zb = yb;
+            }
+        } else if constexpr (MODE == MID_SPECTRUM) {
+            cplx<T> Xa, Xb;
+            fold_spectrum(za, (dc || self) ? za : zb, w, &Xa, &Xb);
+            P.X_out[2 * ka] = (double)Xa.re;
+            P.X_out[2 * ka + 1] = (double)Xa.im;
+            if (!self) {
+                P.X_out[2 * (M - ka)] = (double)Xb.re;
+                P.X_out[2 * (M - ka) + 1] = (double)Xb.im;
+            }
+        } else {
+            const double* Y = P.Y_in;
+            if (dc) {
+                const T y0 = (T)Y[0], yM = (T)Y[2 * M];
+                za = cmk(y0 + yM, y0 - yM);
+            } else {
+                const cplx<T> Ya = cmk((T)Y[2 * ka], (T)Y[2 * ka + 1]);
+                const cplx<T> Yb = cmk((T)Y[2 * (M - ka)], (T)Y[2 * (M - ka) + 1]);
+                cplx<T> ya, yb;
+                unfold_pair(Ya, Yb, w, &ya, &yb);
+                za = ya;
+                if (!self) zb = yb;
+            }
+        }
+    }
+    if constexpr (MODE == MID_SPECTRUM) return;
+    __syncthreads();
+    // The inverse transform's first pass: length-R DFTs of the columns (no
+    // twiddles), column j's outputs to z[j R + q].
+    col_fft<T, E, true, C2>(buf, wr, R, P.sub, tid, nt);
+    cplx<T>* dst = (cplx<T>*)(P.dst_sel ? d.sortB : d.sortA);
+    for (int e = tid; e < R * C2; e += nt) {
+        const int sl = e / R, q = e % R;
+        dst[col_of(sl) * R + q] = buf[tpad<T>(q * C2 + sl)];
+    }
 }
 
 // ----------------------------------------------------------------------------

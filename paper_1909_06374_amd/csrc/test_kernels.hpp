@@ -5,7 +5,8 @@
 // Sec. 2.1.  The transforms and the sort are the path's own device code (the
 // Stockham passes, the real-spectrum fold, the radix sorts); only the loads
 // and stores at the ends differ, because the path never materialises the
-// spectrum it replaces.
+// spectrum it replaces (on the multi-pass path the middle pass's spectrum and
+// unfold modes, k_fft_mid, take the place of its replacement).
 #pragma once
 #include "common.hpp"
 #include "lds_fft.hpp"
@@ -88,48 +89,6 @@ __global__ __launch_bounds__(1024) void k_test_lds(const TestLds* __restrict__ d
 }
 
 // Multi-pass path, one curve (descriptor cv[0]).
-// The real-input spectrum of every Hermitian pair from the half-length
-// transform in region `sel`.  grid: ceil((M/2 + 1) / 256), block 256.
-template <typename T>
-__global__ __launch_bounds__(256) void k_test_big_spectrum(const BigCurve* __restrict__ cv, int64_t M, int sel,
-                                                           TwTable tb, double* __restrict__ X) {
-    const BigCurve& d = cv[0];
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > M / 2) return;
-    const cplx<T>* Z = (const cplx<T>*)(sel ? d.sortB : d.sortA);
-    const int64_t mk = (k == 0) ? 0 : M - k;
-    cplx<T> Xk, Xm;
-    fold_spectrum(Z[k], Z[mk], to_T<T>(tw64(tb, k)), &Xk, &Xm);
-    X[2 * k] = (double)Xk.re;
-    X[2 * k + 1] = (double)Xk.im;
-    if (M - k != k) {
-        X[2 * (M - k)] = (double)Xm.re;
-        X[2 * (M - k) + 1] = (double)Xm.im;
-    }
-}
-
-// The half-length spectrum whose inverse transform is the real series with
-// half spectrum Y, into region `sel`.  grid: ceil((M/2 + 1) / 256), block 256.
-template <typename T>
-__global__ __launch_bounds__(256) void k_test_big_unfold(const BigCurve* __restrict__ cv, int64_t M, int sel,
-                                                         TwTable tb, const double* __restrict__ Y) {
-    const BigCurve& d = cv[0];
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > M / 2) return;
-    cplx<T>* Z = (cplx<T>*)(sel ? d.sortB : d.sortA);
-    if (k == 0) {
-        const T y0 = (T)Y[0], yM = (T)Y[2 * M];
-        Z[0] = cmk(y0 + yM, y0 - yM);
-        return;
-    }
-    const cplx<T> Yk = cmk((T)Y[2 * k], (T)Y[2 * k + 1]);
-    const cplx<T> Ym = cmk((T)Y[2 * (M - k)], (T)Y[2 * (M - k) + 1]);
-    cplx<T> yk, ym;
-    unfold_pair(Yk, Ym, to_T<T>(tw64(tb, k)), &yk, &ym);
-    Z[k] = yk;
-    if (M - k != k) Z[M - k] = ym;
-}
-
 // y[p] = the real view of the complex buffer in region `sel`.  grid: ceil(n / 256), block 256.
 template <typename T>
 __global__ __launch_bounds__(256) void k_test_big_real(const BigCurve* __restrict__ cv, int64_t n, int sel,

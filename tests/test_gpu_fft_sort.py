@@ -8,12 +8,15 @@ of Sec. 2.1.
 
 Bars.  Transforms: both sides get the same input in the working precision
 (the FP32 form rounds x to float on load; the oracle is given the same rounded
-values), so the difference is the transform's own round-off.  A fast
+values), so the difference is the transforms' own round-off.  A fast
 transform with correctly rounded twiddles has a relative rms error of
-c eps sqrt(log2 N) with c of order one (eps = 2^-53 in FP64, 2^-24 in FP32;
-the oracle's FP64 error is negligible against FP32); the test measures c per
-length and asks c <= 3, and every element within 8 eps log2(N) ||x||_2
-(the worst-case bound, constant 8 for both transforms together).  A wrong
+c eps sqrt(log2 N) with c of order one (eps = 2^-53 in FP64, 2^-24 in FP32).
+The test measures c per length: in FP32 the kernel's error dominates
+(measured 0.3-0.8, bar 2); in FP64 the difference holds both
+implementations' errors (measured 1.5-3.1, bar 4).  The whole error vector
+must also lie within the norm-wise worst-case bound
+||X_gpu - X_ref||_2 <= 8 eps log2(N) ||X||_2, ||X||_2 = sqrt(N) ||x||_2 over
+the full spectrum (constant 8 for both transforms together).  A wrong
 twiddle, sign or index gives errors of order one.  Ranking: bit-exact against
 the oracle's stable argsort of the keys the path sorts (FP64 values; FP32
 values; in the FP32 form on the LDS path the 2^30-level image of y, whose
@@ -34,6 +37,7 @@ LDS_POW2 = [2**a for a in range(1, 15)]
 LDS_THREE = [3 * 2**a for a in range(1, 13)]
 HBM = [8192, 16384, 32768, 65536, 2**17, 24576, 49152, 98304, 196608]
 EPS = {0: 2.0**-53, 1: 2.0**-24}
+C_BAR = {0: 4.0, 1: 2.0}
 
 
 def agn():
@@ -90,12 +94,12 @@ def test_rfft_matches_oracle(gpu_ctx, n, path, prec):
     Xg = X[0::2] + 1j * X[1::2]
     Xr = oracle.rfft(x)
     err = Xg - Xr
-    bound = 8 * EPS[prec] * max(math.log2(n), 1.0) * np.linalg.norm(x)
+    bound = 8 * EPS[prec] * max(math.log2(n), 1.0) * math.sqrt(n) * np.linalg.norm(x)
     assert np.all(np.isfinite(Xg))
-    assert np.max(np.abs(err)) <= bound, (np.max(np.abs(err)), bound)
+    assert np.linalg.norm(err) <= bound, (np.linalg.norm(err), bound)
     c = c_of(err, Xr, n, prec)
     print(f"rfft n={n} path={path} prec={prec}: c = {c:.3f}")
-    assert c <= 3.0
+    assert c <= C_BAR[prec]
 
 
 @pytest.mark.parametrize("n,path,prec", ALL, ids=IDS)
@@ -115,14 +119,13 @@ def test_irfft_matches_oracle(gpu_ctx, n, path, prec):
     yr = oracle.irfft(Y, n)
     err = y - yr
     # ||y||_2 = sqrt(n) ||Y_full||_2 for the unnormalised inverse
-    yfull = np.sqrt(n) * np.sqrt(np.abs(Y[0]) ** 2 + np.abs(Y[-1]) ** 2 + 2 * np.sum(np.abs(Y[1:-1]) ** 2)) \
-        if n > 2 else np.linalg.norm(yr)
+    yfull = np.sqrt(n) * np.sqrt(np.abs(Y[0]) ** 2 + np.abs(Y[-1]) ** 2 + 2 * np.sum(np.abs(Y[1:-1]) ** 2))
     bound = 8 * EPS[prec] * max(math.log2(n), 1.0) * yfull
     assert np.all(np.isfinite(y))
-    assert np.max(np.abs(err)) <= bound, (np.max(np.abs(err)), bound)
+    assert np.linalg.norm(err) <= bound, (np.linalg.norm(err), bound)
     c = c_of(err, yr, n, prec)
     print(f"irfft n={n} path={path} prec={prec}: c = {c:.3f}")
-    assert c <= 3.0
+    assert c <= C_BAR[prec]
 
 
 def lds_fp32_keys(y):

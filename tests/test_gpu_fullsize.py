@@ -10,11 +10,12 @@ configurations the benchmark times:
 The oracle cannot run these whole.  Properties that hold at any size are
 checked on every curve (each output is an exact permutation of its own
 draw, every curve ran all its iterations, every delta is finite), and
-sampled curves are compared with the FP64 oracle: the FP32 trajectories part
-from FP64 after enough iterations (sample pairs swap at the FP32 round-off),
-so the comparison is the log-binned periodogram of the final curve, to the
-same bar as the 2^14 end-to-end test.  The plan's graph replay must also
-equal a plain batch call bit for bit.
+the same batch runs in FP64, whose sampled curves must equal the FP64 oracle
+bit for bit; the FP32 trajectories part from FP64 after enough iterations
+(sample pairs swap at the FP32 round-off), so FP32 is compared with FP64
+through the 0.1-dex log-binned periodogram of the final curves, averaged
+over the batch.  The plan's graph replay must also equal a plain batch call
+bit for bit.
 """
 import numpy as np
 import pytest
@@ -55,12 +56,40 @@ def test_ptf_batch_full_size(gpu_ctx):
     assert np.array_equal(np.sort(xh, axis=1), np.sort(w["erdf"], axis=1))
     assert np.all(done.cpu().numpy() == iters)
     assert np.all(np.isfinite(dh)) and np.all(dh >= 0)
+    # The same batch in FP64; sampled curves equal the oracle's run bit for bit.
+    x64 = torch.empty_like(x)
+    ws64 = torch.empty(m.agn_batch_workspace_size(ns, m.AGN_FP64), dtype=torch.uint8, device="cuda:0")
+    m.agn_lc_generate_batch(gpu_ctx, ns, offs, params, [1.0] * n_curves, [iters] * n_curves, seeds, ids, e,
+                            -1.0, m.AGN_FP64, x64, None, None, ws64)
+    del ws64
+    x64h = x64.cpu().numpy().reshape(n_curves, n)
     for c in (0, 517, n_curves - 1):
         pp = oracle.psd_params(0.0, w["f_br"][c], w["a_low"][c], w["a_high"][c])
         xr, dr, _, _ = oracle.generate(pp, w["erdf"][c], 1.0, iters, seeds[c], ids[c])
-        _, a = oracle.log_binned(oracle.periodogram(xr), n, 1.0)
-        _, b = oracle.log_binned(oracle.periodogram(xh[c]), n, 1.0)
-        assert np.all(np.abs(np.log10(b / a)) < 0.1), (c, np.max(np.abs(np.log10(b / a))))
+        assert np.array_equal(x64h[c], xr)
+    # FP32 form against FP64 after all iterations: 0.1-dex log-binned
+    # periodograms (Eq. A2).  The two trajectories part once any pair of
+    # samples swaps, so single curves differ by realisation scatter in the
+    # bins that hold one or two Fourier frequencies; the bar applies to the
+    # ensemble mean over the 1024 curves, bin by bin (the statistic of Sec.
+    # 3.2.5), within 1e-3 relative.
+    dex = 0.1
+    nb = m.agn_log_bin_count(n, dex)
+    h = n // 2 + 1
+    pws = torch.empty(m.agn_periodogram_workspace_size(ns, dex), dtype=torch.uint8, device="cuda:0")
+    P = torch.empty(n_curves * h, dtype=torch.float64, device="cuda:0")
+    bins = {}
+    for key, xx in (("fp32", x), ("fp64", x64)):
+        b = torch.empty(n_curves * nb, dtype=torch.float64, device="cuda:0")
+        m.agn_periodogram_batch(gpu_ctx, ns, offs, xx, [c * h for c in range(n_curves)], P, dex,
+                                [c * nb for c in range(n_curves)], b, pws)
+        bins[key] = b.cpu().numpy().reshape(n_curves, nb)
+    per_curve = np.abs(bins["fp32"] / bins["fp64"] - 1.0)
+    ens = np.abs(bins["fp32"].mean(axis=0) / bins["fp64"].mean(axis=0) - 1.0)
+    print(f"PTF-like batch, FP32 vs FP64 after {iters} iterations: single-curve log-binned periodogram rel. diff "
+          f"median {np.median(per_curve):.2e} max {per_curve.max():.2e}; ensemble mean over {n_curves} curves "
+          f"rel. diff median {np.median(ens):.2e} max {ens.max():.2e}")
+    assert ens.max() <= 1e-3, ens
 
 
 def test_uneven_batch_full_size_plan(gpu_ctx):

@@ -214,6 +214,16 @@ def test_fp32_one_step_rank_agreement(gpu_ctx, n):
 
 @pytest.mark.parametrize("n", [2**14, 12288])
 def test_fp32_end_to_end_multiset_and_delta(gpu_ctx, n):
+    """One curve, 100 iterations in the FP32 form against the FP64 oracle.
+    Exact: the value multiset and x = s[rank].  The trajectories part once any
+    pair of samples swaps at the FP32 round-off, so after 100 iterations the two
+    outputs are different realisations near the same target moduli; their
+    0.1-dex log-binned periodograms then differ by realisation scatter, largest
+    in the lowest bins, which hold one or two Fourier frequencies (measured up
+    to 0.07 relative).  The single-curve bar is therefore a sanity bound of
+    0.1 dex in every bin, not the 1e-3 target, which applies to the ensemble
+    mean over a batch (tests/test_gpu_fullsize.py) and holds per curve at
+    2^26 (bins of many frequencies)."""
     x0 = synth.erdf_draw(n, seed=5)
     amp = oracle.psd_spectrum(oracle.psd_params(**PSD), n, 1.0, seed=5)
     xg, dg, doneg, rg = run_iterate(gpu_ctx, amp, x0, 100, 1)
