@@ -121,6 +121,26 @@ int agn_psd_spectrum(agn_ctx* ctx, const agn_psd_params* p, int64_t n, double dt
                      void* amp_out, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * agn_psd_spectrum_noalloc -- agn_psd_spectrum for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and bit-identical
+ * moduli, but the workspace is a library-owned device array of 512 KiB
+ * (enough for every supported n; each device holds its own copy until the
+ * process ends) instead of a caller's ws, and the descriptor is written by a
+ * kernel instead of through a pinned staging buffer.  The call allocates
+ * nothing, host or device, and records no kernel timing.
+ *   Arguments, layout and errors as agn_psd_spectrum (no ws); AGN_EDEVICE if
+ *   the array's device address could not be resolved when ctx was created.
+ *   All calls on one device share the array: calls that overlap in time on
+ *   one device (different streams, or different contexts) race and give
+ *   undefined moduli; serialise them.  Nothing in the array needs to start
+ *   at zero: each call writes what it reads.
+ */
+int agn_psd_spectrum_noalloc(agn_ctx* ctx, const agn_psd_params* p, int64_t n, double dt,
+                             uint64_t seed, uint32_t curve_id, agn_precision prec,
+                             void* amp_out, void* stream);
+
+/*
  * agn_lc_iterate -- the iteration of Sec. 2.1 / Sec. 3.2.2 from a given start.
  *   amp        device, n/2 + 1 target moduli (float for AGN_FP32, double for
  *              AGN_FP64), as produced by agn_psd_spectrum.

@@ -89,6 +89,7 @@ def _declare(lib):
     lib.agn_workspace_size.argtypes = [i64, C.c_int, C.POINTER(sz)]
     lib.agn_batch_workspace_size.argtypes = [i32, vp, C.c_int, C.POINTER(sz)]
     lib.agn_psd_spectrum.argtypes = [vp, pp, i64, d, u64, u32, C.c_int, vp, vp, sz, vp]
+    lib.agn_psd_spectrum_noalloc.argtypes = [vp, pp, i64, d, u64, u32, C.c_int, vp, vp]
     lib.agn_lc_iterate.argtypes = [vp, vp, vp, i64, i32, d, C.c_int, vp, vp, vp, vp, vp, sz, vp]
     lib.agn_lc_generate.argtypes = [vp, pp, vp, i64, d, i32, d, u64, u32, C.c_int, vp, vp, vp,
                                     vp, sz, vp]
@@ -119,7 +120,7 @@ def _declare(lib):
     lib.agn_ctx_kernel_names.argtypes = []
     lib.agn_ctx_kernel_names.restype = C.c_char_p
     for f in ("agn_ctx_create", "agn_ctx_destroy", "agn_supported_n", "agn_spectrum_workspace_size",
-              "agn_workspace_size", "agn_batch_workspace_size", "agn_psd_spectrum",
+              "agn_workspace_size", "agn_batch_workspace_size", "agn_psd_spectrum", "agn_psd_spectrum_noalloc",
               "agn_lc_iterate", "agn_lc_generate", "agn_lc_generate_batch", "agn_test_philox",
               "agn_ctx_set_profiling", "agn_ctx_kernel_time", "agn_erdf_draw", "agn_pdf_draw", "agn_pdf_slice", "agn_batch_plan_create",
               "agn_batch_plan_launch", "agn_batch_plan_info", "agn_batch_plan_tuning", "agn_batch_plan_destroy", "agn_log_bin_count",
@@ -274,6 +275,15 @@ def agn_psd_spectrum(ctx: Context, params, n, dt, seed, curve_id, prec, amp_out,
                                   int(curve_id), int(prec), _buf(amp_out, "amp_out", _wp(prec), int(n) // 2 + 1, dv),
                                   _buf(ws, "ws", None, 0, dv),
                                   ws.numel() * ws.element_size(), _stream(stream, ctx.device)))
+
+
+def agn_psd_spectrum_noalloc(ctx: Context, params, n, dt, seed, curve_id, prec, amp_out, stream=None):
+    """agn_psd_spectrum on the library's own device array (no workspace, no allocation)."""
+    dv = ctx.device
+    _check(lib().agn_psd_spectrum_noalloc(ctx.handle, C.byref(params), int(n), float(dt), int(seed),
+                                          int(curve_id), int(prec),
+                                          _buf(amp_out, "amp_out", _wp(prec), int(n) // 2 + 1, dv),
+                                          _stream(stream, ctx.device)))
 
 
 def agn_lc_iterate(ctx: Context, amp, x0, n, iters, tol, prec, x_out, delta_out=None,

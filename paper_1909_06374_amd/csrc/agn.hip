@@ -179,8 +179,17 @@ struct ProfRec {
     hipEvent_t a, b;
 };
 
+// Device memory of the allocation-free entry point (agn_psd_spectrum_noalloc):
+// the curve's descriptor and the normalisation's partial sums.  Every device
+// the library runs on holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns on that
+// device (agn_ctx::scratch_dev), never through this name.
+static constexpr size_t NOALLOC_SCRATCH_BYTES = 512 * 1024;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
 struct agn_ctx {
     int device = 0;
+    void* scratch_dev = nullptr;  // this device's copy of `scratch` (null if the lookup failed)
     size_t lds_max = 65536;  // LDS bytes one workgroup may allocate
     bool prof = false;
     std::vector<ProfRec> prof_recs;
@@ -320,9 +329,13 @@ extern "C" int agn_ctx_create(int device, agn_ctx** out) {
     HIPCHK(hipSetDevice(device));
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, device));
+    // this device's copy of the allocation-free entry point's scratch array
+    void* sp = nullptr;
+    if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess) sp = nullptr;
     agn_ctx* c = new agn_ctx();
     c->device = device;
     c->lds_max = prop.sharedMemPerBlock;
+    c->scratch_dev = sp;
     *out = c;
     return AGN_OK;
 }
@@ -1133,6 +1146,43 @@ extern "C" int agn_psd_spectrum(agn_ctx* ctx, const agn_psd_params* p, int64_t n
     SpecDesc* d_sp = (SpecDesc*)base;
     if ((rc = stage_upload(ctx, d_sp, &s, sizeof(s), st))) return rc;
     launch_spectrum(ctx, d_sp, 1, s.nchunk, st);
+    HIPCHK(hipGetLastError());
+    return AGN_OK;
+}
+
+// The descriptor of a spectrum launch, written from a kernel argument into
+// device memory (no host staging buffer).  grid 1, block 64.
+__global__ void k_put_spec_desc(SpecDesc s, SpecDesc* __restrict__ dst) {
+    if (threadIdx.x == 0) *dst = s;
+}
+
+extern "C" int agn_psd_spectrum_noalloc(agn_ctx* ctx, const agn_psd_params* p, int64_t n, double dt,
+                                        uint64_t seed, uint32_t curve_id, agn_precision prec, void* amp_out,
+                                        void* stream) {
+    if (!ctx || !p || !amp_out) return fail(AGN_EINVAL, "NULL argument");
+    int rc = check_prec(prec);
+    if (rc) return rc;
+    if (!n_supported(n)) return fail(AGN_EUNSUPPORTED_N, "n=%lld is not 2^a or 3*2^a in [2, 2^27]", (long long)n);
+    if (!valid_params(p, dt)) return fail(AGN_EINVAL, "invalid PSD parameters or dt");
+    if (!ctx->scratch_dev) return fail(AGN_EDEVICE, "the scratch array's device address is unknown");
+    const size_t need = align256(sizeof(SpecDesc)) + spectrum_ws(n);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(AGN_EUNSUPPORTED_N, "n=%lld needs %zu bytes of scratch; the array holds %zu", (long long)n, need,
+                    NOALLOC_SCRATCH_BYTES);
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    unsigned char* base = (unsigned char*)ctx->scratch_dev;
+    SpecDesc s;
+    memset(&s, 0, sizeof(s));
+    s.n = n; s.dt = dt; s.norm = p->norm; s.f_br = p->f_br; s.a_low = p->a_low; s.a_high = p->a_high;
+    s.seed = seed; s.curve_id = curve_id; s.is_f32 = prec == AGN_FP32;
+    s.chunk0 = 0; s.nchunk = spec_chunks(n);
+    s.amp = amp_out;
+    s.partial = (double*)(base + align256(sizeof(SpecDesc)));
+    s.A = (double*)(base + align256(sizeof(SpecDesc)) + align256((size_t)s.nchunk * 8));
+    SpecDesc* d_sp = (SpecDesc*)base;
+    hipLaunchKernelGGL(k_put_spec_desc, dim3(1), dim3(64), 0, st, s, d_sp);
+    launch_spectrum(nullptr, d_sp, 1, s.nchunk, st);  // no kernel timing: its events would be allocations
     HIPCHK(hipGetLastError());
     return AGN_OK;
 }
