@@ -27,7 +27,6 @@ METRIC = "light-curve samples/s through full iteration (FP32 batched vs FP64 pla
 
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
-LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
 FP32_PEAK_TFLOPS = 157.3        # FP32 vector, packed FMA
 
 # What the FP64 GPU path used as the reference here has been shown to equal.
@@ -148,6 +147,8 @@ def main():
     ap.add_argument("--workload", default="lsst_long",
                     choices=["ptf_batch", "single_curve", "lsst_long", "lsst_long_fp64", "uneven_batch", "serving",
                              "paper_scale", "observables", "convergence", "pdf_draw"])
+    ap.add_argument("--segment-iters", type=int, default=25,
+                    help="serving: iterations per launch of a request (0: whole requests)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the FP32-vs-FP64 accuracy report")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 run beside the FP32 form")
@@ -333,12 +334,17 @@ def run_standard(args, agn, synth, np, torch):
         achieved = fl * samples * iters / (dom_ms / 1000.0) / 1e12
         per = lds_bytes_per_sample_iter(n, pb)
         lds_gbs = per * samples * iters / (dom_ms / 1000.0) / 1e9
+        # LDS ceiling measured on this device (agn_test_lds_bandwidth: 16-byte
+        # conflict-free reads, 2048 workgroups x 4000 passes over 64 KB)
+        probe = torch.empty(2048 * 1024, dtype=torch.float32, device=dev)
+        lds_peak = agn.agn_test_lds_bandwidth(2048, 4000, probe) / 1e9
         roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                 "traffic": recorded_traffic(args.workload, dom),
                 "flops_per_sample_iter": fl, "avg_launch_ms": round(dom_ms, 4),
-                "lds_view": {"achieved_gbs": round(lds_gbs, 1), "peak_gbs": round(LDS_PEAK_GBS, 1),
-                             "frac": round(lds_gbs / LDS_PEAK_GBS, 4), "bytes_per_sample_iter": per}}
+                "lds_view": {"achieved_gbs": round(lds_gbs, 1), "peak_gbs_measured": round(lds_peak, 1),
+                             "frac": round(lds_gbs / lds_peak, 4), "bytes_per_sample_iter": per,
+                             "peak_source": "agn_test_lds_bandwidth on this device"}}
         vi = recorded_valu(args.workload, dom)
         if vi is not None:
             # issue view: a wave64 VALU instruction holds a 16-lane SIMD for 4
@@ -692,7 +698,10 @@ def run_serving(args, agn, np, torch):
     free, _ = torch.cuda.mem_get_info(0)
     budget = int(min(0.6 * free, 160 * 2**30))
     be = GpuBackend(ctx, n_slots=4, prec=agn.AGN_FP32)
-    srv = Server(be, budget_bytes=budget)
+    # iteration-level batching: a launch runs at most `seg` iterations of a
+    # request, so later arrivals join at the next segment boundary
+    seg = args.segment_iters if args.segment_iters > 0 else None
+    srv = Server(be, budget_bytes=budget, segment_iters=seg)
     # warm-up: one small request of each path
     srv.run([Request(rid=10**6 + i, n=n, iters=3, f_br=0.01, a_low=1.0, a_high=2.0, seed=i, arrival=0.0)
              for i, n in enumerate([4096, 2**20])])
@@ -721,7 +730,9 @@ def run_serving(args, agn, np, torch):
         # multi-pass requests: per iteration 4 passes of 32-bit keys (16 bytes per
         # key), once 8 passes of the 64-bit draw keys (24 bytes per key)
         big = [r for r in cap_reqs if not ((r.n % 3 == 0 and r.n <= 12288) or (r.n % 3 != 0 and r.n <= 16384))]
-        byts = float(sum(r.n * (r.iters * 4 * 16 + 8 * 24) for r in big))
+        # (the draw keys are sorted once per segment)
+        nseg = [1 if seg is None else -(-r.iters // seg) for r in big]
+        byts = float(sum(r.n * (r.iters * 4 * 16 + k * 8 * 24) for r, k in zip(big, nseg)))
         ach = byts / (kt[dom][0] / 1000.0) / 1e9
         roof.update({"achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4)})
@@ -784,7 +795,9 @@ def run_serving(args, agn, np, torch):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "serving: Poisson arrivals, N uniform over 2^12..2^22 (2^a and 3*2^a), 50-200 "
                                "iterations, PTF-like PSD parameters, device PDF draws, FP32 form, 4 streams, "
-                               "HBM-footprint admission", "budget_gib": round(budget / 2**30, 1)},
+                               "HBM-footprint admission, " + (f"segments of {seg} iterations" if seg else
+                                                               "whole requests per launch"),
+                   "budget_gib": round(budget / 2**30, 1), "segment_iters": seg},
         "capacity_req_per_s": cap_rps, "capacity_requests": n_cap,
         "load_sweep": sweep, "offered_2000_per_s": spec, "fp64_one_at_a_time": fp64,
         "roofline": roof, "cpu_baseline": serving_cpu_baseline(args, base),

@@ -219,7 +219,12 @@ int agn_lc_generate_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n,
  *              write x_out.  Neither choice changes any arithmetic: chains
  *              only reorder independent curves, and the sort is exact.
  *              AGN_PLAN_LARGE_SORT_TILE: use the 16384-key sort tile
- *              without tuning (not with AGN_PLAN_AUTOTUNE).  The FFT
+ *              without tuning (not with AGN_PLAN_AUTOTUNE).
+ *              AGN_PLAN_NARROW_FFT: 16 butterflies per multi-pass FFT
+ *              workgroup instead of up to 64, without tuning.  With
+ *              AGN_PLAN_AUTOTUNE this width (64, 32 or 16) is also tuned,
+ *              after the chains and the sort tile.  The width changes no
+ *              arithmetic: results are bit-identical for every width.  The FFT
  *              decomposition is fixed per length, because it sets the
  *              rounding of the transforms.
  *   branches   chain count when AGN_PLAN_AUTOTUNE is not set (0 or 1: one
@@ -232,7 +237,7 @@ int agn_lc_generate_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n,
  * launches of one plan must not overlap in time (they share ws).
  */
 typedef struct agn_batch_plan agn_batch_plan;
-enum { AGN_PLAN_GRAPH = 1, AGN_PLAN_AUTOTUNE = 2, AGN_PLAN_LARGE_SORT_TILE = 4 };
+enum { AGN_PLAN_GRAPH = 1, AGN_PLAN_AUTOTUNE = 2, AGN_PLAN_LARGE_SORT_TILE = 4, AGN_PLAN_NARROW_FFT = 8 };
 
 int agn_batch_plan_create(agn_ctx* ctx, int32_t n_curves, const int64_t* n, const int64_t* offset,
                           const agn_psd_params* p, const double* dt, const int32_t* iters,
@@ -241,11 +246,17 @@ int agn_batch_plan_create(agn_ctx* ctx, int32_t n_curves, const int64_t* n, cons
                           int flags, int branches, void* ws, size_t ws_bytes, void* stream,
                           agn_batch_plan** out);
 int agn_batch_plan_launch(agn_batch_plan* plan, void* stream);
-/* Chain count in use, number of launch groups (distinct lengths per path), 1 if graph mode. */
+/* Chain count in use, number of launch groups, 1 if graph mode.  A launch
+ * group is one length on one path, except that when two or more LDS-resident
+ * lengths run whole waves per curve they share one persistent pack launch,
+ * which counts once. */
 int agn_batch_plan_info(const agn_batch_plan* plan, int32_t* branches, int32_t* groups, int32_t* uses_graph);
-/* The tuned (or requested) choices: chain count and sort tile (8192 or 16384;
- * 16384 applies to FP32 multi-pass curves whose length it divides). */
-int agn_batch_plan_tuning(const agn_batch_plan* plan, int32_t* branches, int32_t* sort_tile);
+/* The tuned (or requested) choices: chain count, sort tile (8192 or 16384;
+ * 16384 applies to FP32 multi-pass curves whose length it divides) and the
+ * most butterflies per multi-pass FFT workgroup (64, 32 or 16).  Any output
+ * pointer may be NULL. */
+int agn_batch_plan_tuning(const agn_batch_plan* plan, int32_t* branches, int32_t* sort_tile,
+                          int32_t* fft_cols);
 int agn_batch_plan_destroy(agn_batch_plan* plan);
 
 /* Parameters of the PDF draw: a sharp broken power law in dN/dlog10(lambda)
@@ -418,6 +429,18 @@ int agn_test_philox(uint64_t key0, uint64_t key1, uint64_t ctr0, int64_t n_block
  *                 values closer than (max - min) 2^-30 can share a key and
  *                 are then ordered by index.
  */
+/*
+ * agn_test_lds_bandwidth -- measured LDS read bandwidth, the ceiling against
+ * which the LDS-resident kernels' LDS traffic is rated: `blocks` workgroups
+ * of 1024 threads each read a 64 KB LDS buffer `reps` times in 16-byte words
+ * (consecutive lanes, consecutive words: no bank conflicts).  Bytes read:
+ * blocks * reps * 65536.  *seconds = device time of the timed launch (after
+ * one untimed launch); out: device, blocks * 1024 floats (the sums read, so
+ * the loads cannot be elided).  Synchronises the stream.  Errors: AGN_EINVAL,
+ * AGN_EDEVICE.
+ */
+int agn_test_lds_bandwidth(int32_t blocks, int32_t reps, float* out, double* seconds, void* stream);
+
 enum { AGN_TEST_PATH_LDS = 0, AGN_TEST_PATH_HBM = 1 };
 int agn_test_workspace_size(int64_t n, agn_precision prec, int32_t path, size_t* bytes);
 int agn_test_rfft(agn_ctx* ctx, const double* x, int64_t n, agn_precision prec, int32_t path,

@@ -97,6 +97,7 @@ def _declare(lib):
                                           vp, vp, vp, vp, sz, vp]
     lib.agn_test_philox.argtypes = [u64, u64, u64, i64, vp, vp]
     lib.agn_test_workspace_size.argtypes = [i64, C.c_int, i32, C.POINTER(sz)]
+    lib.agn_test_lds_bandwidth.argtypes = [i32, i32, vp, C.POINTER(d), vp]
     for f in ("agn_test_rfft", "agn_test_irfft", "agn_test_argsort"):
         getattr(lib, f).argtypes = [vp, vp, i64, C.c_int, i32, vp, vp, sz, vp]
     lib.agn_erdf_draw.argtypes = [vp, C.POINTER(agn_erdf_params), i64, u64, u32, vp, vp]
@@ -110,7 +111,7 @@ def _declare(lib):
                                           C.c_int, C.c_int, vp, sz, vp, C.POINTER(vp)]
     lib.agn_batch_plan_launch.argtypes = [vp, vp]
     lib.agn_batch_plan_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
-    lib.agn_batch_plan_tuning.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+    lib.agn_batch_plan_tuning.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.agn_batch_plan_destroy.argtypes = [vp]
     lib.agn_log_bin_count.argtypes = [i64, d, C.POINTER(i32)]
     lib.agn_periodogram_workspace_size.argtypes = [i32, vp, d, C.POINTER(sz)]
@@ -126,7 +127,8 @@ def _declare(lib):
               "agn_batch_plan_launch", "agn_batch_plan_info", "agn_batch_plan_tuning", "agn_batch_plan_destroy", "agn_log_bin_count",
               "agn_periodogram_workspace_size", "agn_periodogram_batch", "agn_lag_stats_workspace_size",
               "agn_lag_stats_batch", "agn_psd_fit_workspace_size", "agn_psd_fit_batch",
-              "agn_test_workspace_size", "agn_test_rfft", "agn_test_irfft", "agn_test_argsort"):
+              "agn_test_workspace_size", "agn_test_rfft", "agn_test_irfft", "agn_test_argsort",
+              "agn_test_lds_bandwidth"):
         getattr(lib, f).restype = C.c_int
 
 
@@ -347,6 +349,7 @@ def _batch_bufs(ctx, n, offset, iters, erdf, x_out, delta_out, iters_done, tol, 
 AGN_PLAN_GRAPH = 1
 AGN_PLAN_AUTOTUNE = 2
 AGN_PLAN_LARGE_SORT_TILE = 4
+AGN_PLAN_NARROW_FFT = 8
 
 
 class BatchPlan:
@@ -360,9 +363,10 @@ class BatchPlan:
     def info(self):
         b, g, u = C.c_int32(), C.c_int32(), C.c_int32()
         _check(lib().agn_batch_plan_info(self.handle, C.byref(b), C.byref(g), C.byref(u)))
-        t = C.c_int32()
-        _check(lib().agn_batch_plan_tuning(self.handle, None, C.byref(t)))
-        return {"branches": b.value, "groups": g.value, "graph": bool(u.value), "sort_tile": t.value}
+        t, f = C.c_int32(), C.c_int32()
+        _check(lib().agn_batch_plan_tuning(self.handle, None, C.byref(t), C.byref(f)))
+        return {"branches": b.value, "groups": g.value, "graph": bool(u.value), "sort_tile": t.value,
+                "fft_cols": f.value}
 
     def close(self):
         if self.handle:
@@ -548,3 +552,11 @@ def agn_test_argsort(ctx: Context, y, n, prec, path, rank_out, ws, stream=None):
     _check(lib().agn_test_argsort(ctx.handle, _buf(y, "y", _F64, k, dv), int(n), int(prec), int(path),
                                   _buf(rank_out, "rank_out", _I32, k, dv), _buf(ws, "ws", None, 0, dv),
                                   0 if ws is None else ws.numel() * ws.element_size(), _stream(stream, dv)))
+
+
+def agn_test_lds_bandwidth(blocks: int, reps: int, out, stream=None, device=0) -> float:
+    """Measured LDS read bandwidth in bytes/s (blocks x reps x 64 KB read)."""
+    sec = C.c_double()
+    _check(lib().agn_test_lds_bandwidth(int(blocks), int(reps), _buf(out, "out", _F32, int(blocks) * 1024, device),
+                                        C.byref(sec), _stream(stream, device)))
+    return int(blocks) * int(reps) * 65536 / sec.value

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -161,7 +162,7 @@ static size_t big_curve_ws(int64_t n, agn_precision prec) {
 
 static size_t header_ws(int32_t nc) {
     return align256(sizeof(LcDesc) * (size_t)nc) + align256(sizeof(SpecDesc) * (size_t)nc) +
-           align256(sizeof(BigCurve) * (size_t)nc);
+           align256(sizeof(BigCurve) * (size_t)nc) + align256(sizeof(LdsPack) * (size_t)nc);
 }
 
 // ---------------------------------------------------------------------------
@@ -191,6 +192,7 @@ struct agn_ctx {
     int device = 0;
     void* scratch_dev = nullptr;  // this device's copy of `scratch` (null if the lookup failed)
     size_t lds_max = 65536;  // LDS bytes one workgroup may allocate
+    int ncu = 256;           // compute units
     bool prof = false;
     std::vector<ProfRec> prof_recs;
     std::mutex mu;
@@ -199,11 +201,11 @@ struct agn_ctx {
     std::vector<void*> tw64_mem;
     std::vector<StageSlot> ring;
     size_t ring_next = 0;
-    std::map<std::string, std::pair<int, int>> tuned;  // batch signature -> (chains, sort tile) chosen by the autotuner
+    std::map<std::string, std::array<int, 3>> tuned;  // batch signature -> (chains, sort tile, FFT cap) chosen by the autotuner
 };
 
 static const char* KERNEL_NAMES =
-    "spectrum_partial,spectrum_norm,spectrum_amp,lds_prep,lds_iterate,big_prep,fft_pass,fft_mid,"
+    "spectrum_partial,spectrum_norm,spectrum_amp,lds_prep,lds_iterate,lds_packs,big_prep,fft_pass,fft_mid,"
     "sort_hist,sort_scan,sort_scatter,delta,big_output,erdf_draw,batch_graph,periodogram,log_bins,lag_stats,psd_fit";
 
 // Kernel timing: events recorded on the launch stream around each launch.
@@ -335,6 +337,7 @@ extern "C" int agn_ctx_create(int device, agn_ctx** out) {
     agn_ctx* c = new agn_ctx();
     c->device = device;
     c->lds_max = prop.sharedMemPerBlock;
+    c->ncu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     c->scratch_dev = sp;
     *out = c;
     return AGN_OK;
@@ -590,20 +593,27 @@ static std::vector<int> big_radices(int64_t M, agn_precision prec) {
 static int fft_tile(agn_precision prec) { return prec == AGN_FP32 ? 8192 : 4096; }
 
 // Butterflies per workgroup of a pass over stride Ns: the largest power of
-// two <= 64 with R * cols within the tile, dividing M / R and, after the first
-// pass, dividing Ns (a workgroup's columns then share one j mod Ns offset
-// run); 0 if none >= 16.  The column count does not change the arithmetic.
-static int fft_cols(int64_t M, int R, int64_t Ns, agn_precision prec) {
-    for (int c = FFT_COLS_MAX; c >= FFT_COLS_MIN; c >>= 1)
+// two <= cap (64, or a plan's tuned cap) with R * cols within the tile,
+// dividing M / R and, after the first pass, dividing Ns (a workgroup's
+// columns then share one j mod Ns offset run); 0 if none >= 16.  The column
+// count does not change the arithmetic: each element's twiddle chain depends
+// on its row and the rows a thread steps by (R / E), not on the columns.
+static int fft_cols(int64_t M, int R, int64_t Ns, agn_precision prec, int cap = FFT_COLS_MAX) {
+    for (int c = cap; c >= FFT_COLS_MIN; c >>= 1)
         if ((int64_t)R * c <= fft_tile(prec) && (M / R) % c == 0 && (Ns == 1 || Ns % c == 0)) return c;
     return 0;
 }
+
+// Values per thread of the multi-pass FFT passes (R * cols / FFT_E threads,
+// at most 1024 since R * cols <= 8192): 8 rather than 16 puts twice the waves
+// on the same tiles (-2% per pass at 2^26).
+static constexpr int FFT_E = 8;
 
 template <typename T, bool INV, int C>
 static void launch_fft_pass_c(const BigCurve* d, int nc, const FftPass& P, const TwTable& tb, size_t lds,
                               hipStream_t st) {
     dim3 grid((unsigned)(P.M / P.R / C), (unsigned)nc);
-    hipLaunchKernelGGL((k_fft_pass<T, 16, INV, C>), grid, dim3(P.nthreads), lds, st, d, P, tb);
+    hipLaunchKernelGGL((k_fft_pass<T, FFT_E, INV, C>), grid, dim3(P.nthreads), lds, st, d, P, tb);
 }
 
 template <typename T>
@@ -611,7 +621,7 @@ static void launch_fft_pass(agn_ctx* ctx, const BigCurve* d, int nc, const FftPa
                             hipStream_t st) {
     const int C = P.cols;
     const size_t lds = (size_t)(P.R * C + 1 + ((P.R * C + 1) >> (sizeof(T) == 4 ? 5 : 4))) * sizeof(cplx<T>) +
-                       16 + (size_t)P.R * sizeof(cplx<T>) + 8 * 8 + 8 * 4;
+                       16 + (size_t)P.R * sizeof(cplx<T>) + 16 * 8 + 16 * 4;
     ProfScope ps(ctx, "fft_pass", st);
     if (P.inverse) {
         if (C == 64) launch_fft_pass_c<T, true, 64>(d, nc, P, tb, lds, st);
@@ -624,12 +634,17 @@ static void launch_fft_pass(agn_ctx* ctx, const BigCurve* d, int nc, const FftPa
     }
 }
 
-// Column pairs per workgroup of the middle pass: the largest of 32, 16, 8 with
-// the 2 * cols columns of R values within the tile and dividing M / R.
+// Column pairs per workgroup of the middle pass: 8 (16 columns of R values,
+// at most 32 KB in FP32 and 64 KB in FP64 for R <= 256), with 8 values per
+// thread; 0 if 16 columns do not divide M / R.  The middle pass does two
+// in-LDS transforms and the fold per trip through HBM, and more, smaller
+// workgroups per CU overlap those phases better: at 2^26 (R = 256, FP32) this
+// shape takes 1.22 ms per launch against 1.30-1.42 ms for 16 or 32 column
+// pairs or 16 values per thread.
+static constexpr int MID_E = 8;
 static int mid_cols(int64_t M, int R, agn_precision prec) {
-    for (int c = 32; c >= 8; c >>= 1)
-        if ((int64_t)R * 2 * c <= fft_tile(prec) && (M / R) % (2 * c) == 0) return c;
-    return 0;
+    const int c = 8;
+    return ((int64_t)R * 2 * c <= fft_tile(prec) && (M / R) % (2 * c) == 0) ? c : 0;
 }
 
 static MidPass make_mid(int64_t M, int R, int src_sel, int dst_sel, agn_precision prec) {
@@ -638,7 +653,7 @@ static MidPass make_mid(int64_t M, int R, int src_sel, int dst_sel, agn_precisio
     P.M = M;
     P.R = R;
     P.cols = mid_cols(M, R, prec);
-    P.nthreads = R * 2 * P.cols / 16;
+    P.nthreads = R * 2 * P.cols / MID_E;
     P.src_sel = src_sel;
     P.dst_sel = dst_sel;
     P.sub = make_plan(R);
@@ -653,9 +668,7 @@ static void launch_fft_mid(agn_ctx* ctx, const BigCurve* d, int nc, const MidPas
                        16 + (size_t)P.R * sizeof(cplx<T>);
     const dim3 grid((unsigned)(P.M / P.R / C2), (unsigned)nc);
     ProfScope ps(ctx, "fft_mid", st);
-    if (P.cols == 32) hipLaunchKernelGGL((k_fft_mid<T, 16, 32, MODE>), grid, dim3(P.nthreads), lds, st, d, P, tb);
-    else if (P.cols == 16) hipLaunchKernelGGL((k_fft_mid<T, 16, 16, MODE>), grid, dim3(P.nthreads), lds, st, d, P, tb);
-    else hipLaunchKernelGGL((k_fft_mid<T, 16, 8, MODE>), grid, dim3(P.nthreads), lds, st, d, P, tb);
+    hipLaunchKernelGGL((k_fft_mid<T, MID_E, 8, MODE>), grid, dim3(P.nthreads), lds, st, d, P, tb);
 }
 
 template <typename K, int TILE>
@@ -731,7 +744,8 @@ static int big_group_setup(agn_ctx* ctx, int64_t n, agn_precision prec, TwTable*
 // big_group_setup).  ctx may be NULL (no kernel timing, e.g. under capture).
 template <typename T>
 static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, int32_t max_iters,
-                          const TwTable& tb, const std::vector<int>& rad, int sort_tile, hipStream_t st) {
+                          const TwTable& tb, const std::vector<int>& rad, int sort_tile, int fft_cap,
+                          hipStream_t st) {
     typedef typename key_of<T>::type K;
     const int64_t M = n / 2, ntiles = n / BIG_TILE;
     const dim3 gt((unsigned)ntiles, (unsigned)nc);
@@ -754,6 +768,9 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
     const int np = (int)rad.size();
     const int prec_bits = sizeof(T) == 4 ? 1 : 0;
     const agn_precision prec = prec_bits ? AGN_FP32 : AGN_FP64;
+    // The first forward pass also sums the Eq. 4 terms per workgroup, so its
+    // width fixes the order of that sum: it keeps the default width, and only
+    // the other passes take the plan's (bit-neutral for them) width.
     const int64_t npart0 = M / rad[0] / fft_cols(M, rad[0], 1, prec);  // blocks of the first FFT pass
     for (int it = 0; it < max_iters; ++it) {
         const int cur = it & 1;  // x_it lives in X0 (even) or X1 (odd)
@@ -762,7 +779,8 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
         for (int p = 0; p < np - 1; ++p) {
             FftPass P;
             memset(&P, 0, sizeof(P));
-            P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, prec); P.nthreads = rad[p] * P.cols / 16;
+            P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, prec, p == 0 ? FFT_COLS_MAX : fft_cap);
+            P.nthreads = rad[p] * P.cols / FFT_E;
             P.Ns = Ns;
             P.in_mode = p == 0 ? 1 : 0; P.out_mode = 0; P.inverse = 0;
             P.x_sel = cur; P.with_delta = (p == 0 && it > 0) ? 1 : 0;
@@ -784,7 +802,7 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
         for (int p = np - 2; p >= 0; --p) {
             FftPass P;
             memset(&P, 0, sizeof(P));
-            P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, prec); P.nthreads = rad[p] * P.cols / 16;
+            P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, prec, fft_cap); P.nthreads = rad[p] * P.cols / FFT_E;
             P.Ns = Ns;
             P.in_mode = 0; P.out_mode = (p == 0) ? 1 : 0; P.inverse = 1;
             P.src_sel = 1 - sel; P.dst_sel = sel; P.sub = make_plan(rad[p]);
@@ -806,11 +824,22 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
         }
     }
     {
-        // delta of the last iteration for curves that ran all of them
+        // delta of the last iteration for curves that ran all of them: the
+        // first forward pass's loads and partials without its transform, so
+        // that a call that stops here and one that goes on sum the same terms
+        // in the same order
         ProfScope ps(ctx, "delta", st);
-        hipLaunchKernelGGL(k_big_delta_last, gt, dim3(BIG_THREADS), 0, st, d, max_iters & 1);
+        FftPass P;
+        memset(&P, 0, sizeof(P));
+        P.M = M; P.R = rad[0]; P.cols = fft_cols(M, rad[0], 1, prec, FFT_COLS_MAX);
+        P.nthreads = rad[0] * P.cols / FFT_E;
+        P.Ns = 1;
+        P.in_mode = 1; P.out_mode = 2; P.inverse = 0;
+        P.x_sel = max_iters & 1; P.with_delta = 1;
+        P.src_sel = 1; P.dst_sel = 0; P.sub = make_plan(rad[0]);
+        launch_fft_pass<T>(nullptr, d, nc, P, tb, st);
         hipLaunchKernelGGL(k_big_delta_final, dim3((unsigned)nc), dim3(BIG_THREADS), 0, st, d, max_iters - 1,
-                           ntiles);
+                           npart0);
     }
     {
         ProfScope ps(ctx, "big_output", st);
@@ -826,6 +855,13 @@ struct LdsGroup {
     int first, count, E, nt;
     int64_t n;
     size_t pl, il;
+    // pack launch (one persistent k_lds_packs launch for every LDS length):
+    // first/count unused; npacks work items at d_packs, LDS per workgroup, grid
+    int npacks = 0;
+    const LdsPack* d_packs = nullptr;
+    size_t pack_lds = 0;
+    int pack_grid = 0;
+    std::string lens;  // pack launch: the lengths and curve counts it covers (plan signature)
 };
 struct BigGroup {
     int first, count;
@@ -848,6 +884,7 @@ struct agn_batch_plan {
     std::vector<double> lds_cost, big_cost;  // relative run time of each group
     int branches = 1;                         // concurrent launch chains
     int sort_tile = BIG_TILE;                 // requested tile of 32-bit-key sorts (multi-pass curves)
+    int fft_cap = FFT_COLS_MAX;               // most butterflies per multi-pass FFT workgroup
     int flags = 0;
     std::vector<hipStream_t> aux;             // chains 1..branches-1 (default priority)
     std::vector<hipEvent_t> ev;               // fork + one join event per chain
@@ -1011,6 +1048,81 @@ static int build_plan(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_p
         pl.lds_cost.push_back((double)g.count * (double)g.n * (1.0 + max_it));
         i = j;
     }
+    // Several LDS-resident lengths, each with at least one whole wave per
+    // curve: one persistent launch of packs instead of a launch pair per
+    // length (same per-curve arithmetic; bit-identical results).
+    // A length packs if a 1024-thread workgroup's worth of its curves (1024 /
+    // nt of them) fits the LDS (in FP64 the 3 * 2^k lengths 768, 1536 and 3072
+    // do not: they keep their own launches).
+    auto pack_stride = [](const LdsGroup& g) { return (std::max(g.pl, g.il) + 15) & ~(size_t)15; };
+    auto packable = [&](const LdsGroup& g) {
+        return g.nt >= 64 && g.nt <= 1024 && (g.E == 4 || g.E == 6 || g.E == 8) &&
+               (size_t)(1024 / g.nt) * pack_stride(g) <= ctx->lds_max;
+    };
+    int n_packable = 0;
+    for (const LdsGroup& g : pl.lds) n_packable += packable(g) ? 1 : 0;
+    if (n_packable >= 2) {
+        std::vector<LdsPack> packs;
+        std::vector<LdsGroup> rest;
+        std::vector<double> rest_cost;
+        size_t need = 0;
+        double cost = 0.0;
+        std::string lens;
+        int packed_curves = 0;
+        for (size_t q = 0; q < pl.lds.size(); ++q) {
+            const LdsGroup& g = pl.lds[q];
+            if (!packable(g)) {
+                rest.push_back(g);
+                rest_cost.push_back(pl.lds_cost[q]);
+                continue;
+            }
+            lens += "|L" + std::to_string((long long)g.n) + ":" + std::to_string(g.count);
+            packed_curves += g.count;
+            const int S = 1024 / g.nt;
+            const size_t stride = pack_stride(g);
+            need = std::max(need, (size_t)S * stride);
+            for (int c0 = 0; c0 < g.count; c0 += S) {
+                LdsPack pk;
+                memset(&pk, 0, sizeof(pk));
+                pk.first = g.first + c0;
+                pk.count = std::min(S, g.count - c0);
+                pk.E = g.E;
+                pk.nt = g.nt;
+                pk.fuse2 = lds_fuse2(g.n) ? 1 : 0;
+                for (int c = 0; c < pk.count; ++c) pk.max_iters = std::max(pk.max_iters, lc[pk.first + c].iters);
+                pk.stride = (uint32_t)stride;
+                packs.push_back(pk);
+            }
+            cost += pl.lds_cost[q];
+        }
+        {
+            std::stable_sort(packs.begin(), packs.end(), [&](const LdsPack& a, const LdsPack& b) {
+                return (double)lc[a.first].n * (1.0 + a.max_iters) > (double)lc[b.first].n * (1.0 + b.max_iters);
+            });
+            LdsPack* d_packs = (LdsPack*)(base + align256(sizeof(LcDesc) * (size_t)nc) +
+                                          align256(sizeof(SpecDesc) * (size_t)nc) +
+                                          align256(sizeof(BigCurve) * (size_t)nc));
+            int rc = stage_upload(ctx, d_packs, packs.data(), sizeof(LdsPack) * packs.size(), st);
+            if (rc) return rc;
+            LdsGroup g;
+            g.first = 0;
+            g.count = packed_curves;
+            g.E = 0;
+            g.nt = 1024;
+            g.n = 0;
+            g.pl = g.il = need;
+            g.npacks = (int)packs.size();
+            g.d_packs = d_packs;
+            g.pack_lds = need;
+            const int per_cu = std::max(1, std::min(2, (int)(ctx->lds_max / need)));
+            g.pack_grid = std::min(g.npacks, ctx->ncu * per_cu);
+            g.lens = lens;
+            pl.lds = rest;
+            pl.lds_cost = rest_cost;
+            pl.lds.push_back(g);
+            pl.lds_cost.push_back(cost);
+        }
+    }
     // Multi-pass path: one launch sequence per distinct length.
     i = n_lds;
     while (i < nc) {
@@ -1034,15 +1146,27 @@ static int build_plan(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_p
 static void enqueue_group(const agn_batch_plan& pl, agn_ctx* pctx, bool is_big, int k, hipStream_t st) {
     if (!is_big) {
         const LdsGroup& g = pl.lds[k];
+        if (g.npacks > 0) {
+            ProfScope ps(pctx, "lds_packs", st);
+            if (pl.prec == AGN_FP32)
+                hipLaunchKernelGGL(k_lds_packs<float>, dim3((unsigned)g.pack_grid), dim3(1024), g.pack_lds, st,
+                                   pl.d_lc, g.d_packs, g.npacks);
+            else
+                hipLaunchKernelGGL(k_lds_packs<double>, dim3((unsigned)g.pack_grid), dim3(1024), g.pack_lds, st,
+                                   pl.d_lc, g.d_packs, g.npacks);
+            return;
+        }
         const bool f2 = lds_fuse2(g.n);
         if (pl.prec == AGN_FP32) launch_lds_E<float>(pctx, g.E, pl.d_lc + g.first, g.count, g.nt, f2, g.pl, g.il, st);
         else launch_lds_E<double>(pctx, g.E, pl.d_lc + g.first, g.count, g.nt, f2, g.pl, g.il, st);
     } else {
         const BigGroup& g = pl.big[k];
         if (pl.prec == AGN_FP32)
-            run_big_group<float>(pctx, pl.d_bg + g.first, g.count, g.n, g.max_it, g.tb, g.rad, pl.sort_tile, st);
+            run_big_group<float>(pctx, pl.d_bg + g.first, g.count, g.n, g.max_it, g.tb, g.rad, pl.sort_tile,
+                                 pl.fft_cap, st);
         else
-            run_big_group<double>(pctx, pl.d_bg + g.first, g.count, g.n, g.max_it, g.tb, g.rad, pl.sort_tile, st);
+            run_big_group<double>(pctx, pl.d_bg + g.first, g.count, g.n, g.max_it, g.tb, g.rad, pl.sort_tile,
+                                  pl.fft_cap, st);
     }
 }
 
@@ -1284,6 +1408,10 @@ static std::string plan_signature(const agn_batch_plan& pl) {
     std::string sig = pl.prec == AGN_FP32 ? "f32" : "f64";
     char buf[96];
     for (const auto& g : pl.lds) {
+        if (g.npacks > 0) {
+            sig += "|packs" + g.lens;
+            continue;
+        }
         snprintf(buf, sizeof(buf), "|L%lld:%d", (long long)g.n, g.count);
         sig += buf;
     }
@@ -1299,7 +1427,7 @@ static std::string plan_signature(const agn_batch_plan& pl) {
 // after it) and returns the fastest.  Both choices leave every result
 // bit-identical.  Synchronises st.
 static int autotune_plan(agn_ctx* ctx, std::vector<CurveReq> rq, double tol, agn_precision prec, void* ws,
-                         size_t ws_bytes, hipStream_t st, int* best_branches, int* best_tile) {
+                         size_t ws_bytes, hipStream_t st, int* best_branches, int* best_tile, int* best_cap) {
     for (auto& r : rq) {
         r.iters = std::min(r.iters, 2);
         r.delta_out = nullptr;  // the real plan's delta rows are laid out for its own iteration count
@@ -1320,30 +1448,49 @@ static int autotune_plan(agn_ctx* ctx, std::vector<CurveReq> rq, double tol, agn
     bool have = false;
     *best_branches = 1;
     *best_tile = BIG_TILE;
+    *best_cap = FFT_COLS_MAX;
     rc = AGN_OK;
+    // best of three launches after a warm-up one
+    auto time_plan = [&](int nb, float* out_ms) -> int {
+        float m = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+            if (hipEventRecord(a, st) != hipSuccess) return fail(AGN_EDEVICE, "event record failed");
+            int r2 = enqueue_plan(tp, nullptr, nb, st);
+            if (r2) return r2;
+            if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess)
+                return fail(AGN_EDEVICE, "event wait failed");
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, a, b);
+            if (rep == 1 || (rep == 2 && ms < m)) m = ms;
+        }
+        *out_ms = m;
+        return AGN_OK;
+    };
     for (int ti = 0; ti < 2 && rc == AGN_OK; ++ti) {
         if (ti == 1 && !big_tile_ok) break;
         tp.sort_tile = tiles[ti];
         for (int ci = 0; ci < 3 && rc == AGN_OK; ++ci) {
             if (cand[ci] > 1 && cand[ci] > ng) break;
             float m = 0.f;
-            for (int rep = 0; rep < 3 && rc == AGN_OK; ++rep) {  // first run warms up
-                if (hipEventRecord(a, st) != hipSuccess) { rc = fail(AGN_EDEVICE, "event record failed"); break; }
-                rc = enqueue_plan(tp, nullptr, cand[ci], st);
-                if (rc) break;
-                if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
-                    rc = fail(AGN_EDEVICE, "event wait failed");
-                    break;
-                }
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, a, b);
-                if (rep == 1 || (rep == 2 && ms < m)) m = ms;
-            }
+            rc = time_plan(cand[ci], &m);
             if (rc == AGN_OK && (!have || m < best_ms)) {
                 best_ms = m;
                 *best_branches = cand[ci];
                 *best_tile = tiles[ti];
                 have = true;
+            }
+        }
+    }
+    // then the FFT workgroup width at that choice (multi-pass groups only)
+    if (rc == AGN_OK && !tp.big.empty()) {
+        tp.sort_tile = *best_tile;
+        for (int cap = FFT_COLS_MAX / 2; cap >= FFT_COLS_MIN && rc == AGN_OK; cap >>= 1) {
+            tp.fft_cap = cap;
+            float m = 0.f;
+            rc = time_plan(*best_branches, &m);
+            if (rc == AGN_OK && m < best_ms) {
+                best_ms = m;
+                *best_cap = cap;
             }
         }
     }
@@ -1361,10 +1508,12 @@ extern "C" int agn_batch_plan_create(agn_ctx* ctx, int32_t n_curves, const int64
                                      void* stream, agn_batch_plan** out) {
     if (!ctx || !out) return fail(AGN_EINVAL, "NULL argument");
     *out = nullptr;
-    if (flags & ~(AGN_PLAN_GRAPH | AGN_PLAN_AUTOTUNE | AGN_PLAN_LARGE_SORT_TILE))
+    if (flags & ~(AGN_PLAN_GRAPH | AGN_PLAN_AUTOTUNE | AGN_PLAN_LARGE_SORT_TILE | AGN_PLAN_NARROW_FFT))
         return fail(AGN_EINVAL, "unknown plan flags 0x%x", flags);
     if ((flags & AGN_PLAN_AUTOTUNE) && (flags & AGN_PLAN_LARGE_SORT_TILE))
         return fail(AGN_EINVAL, "AGN_PLAN_LARGE_SORT_TILE fixes the tile that AGN_PLAN_AUTOTUNE would choose");
+    if ((flags & AGN_PLAN_AUTOTUNE) && (flags & AGN_PLAN_NARROW_FFT))
+        return fail(AGN_EINVAL, "AGN_PLAN_NARROW_FFT fixes the FFT width that AGN_PLAN_AUTOTUNE would choose");
     if (branches < 0 || branches > 8) return fail(AGN_EINVAL, "branches must be 0..8");
     std::vector<CurveReq> rq;
     int rc = batch_requests(n_curves, n, offset, p, dt, iters, seed, curve_id, erdf, tol, prec, x_out, delta_out,
@@ -1376,16 +1525,22 @@ extern "C" int agn_batch_plan_create(agn_ctx* ctx, int32_t n_curves, const int64
     if ((rc = build_plan(ctx, rq, tol, prec, ws, ws_bytes, st, *pl))) { destroy_plan_resources(*pl); return rc; }
     int nb = branches > 0 ? branches : 1;
     int tile = (flags & AGN_PLAN_LARGE_SORT_TILE) ? SORT_TILE_BIG : BIG_TILE;
+    int cap = (flags & AGN_PLAN_NARROW_FFT) ? FFT_COLS_MIN : FFT_COLS_MAX;
     if ((flags & AGN_PLAN_AUTOTUNE) && !rq.empty()) {
         const std::string sig = plan_signature(*pl);
         bool hit = false;
         {
             std::lock_guard<std::mutex> lk(ctx->mu);
             auto it = ctx->tuned.find(sig);
-            if (it != ctx->tuned.end()) { nb = it->second.first; tile = it->second.second; hit = true; }
+            if (it != ctx->tuned.end()) {
+                nb = it->second[0];
+                tile = it->second[1];
+                cap = it->second[2];
+                hit = true;
+            }
         }
         if (!hit) {
-            if ((rc = autotune_plan(ctx, rq, tol, prec, ws, ws_bytes, st, &nb, &tile))) {
+            if ((rc = autotune_plan(ctx, rq, tol, prec, ws, ws_bytes, st, &nb, &tile, &cap))) {
                 destroy_plan_resources(*pl);
                 return rc;
             }
@@ -1398,11 +1553,12 @@ extern "C" int agn_batch_plan_create(agn_ctx* ctx, int32_t n_curves, const int64
                 return rc;
             }
             std::lock_guard<std::mutex> lk(ctx->mu);
-            ctx->tuned[sig] = std::make_pair(nb, tile);
+            ctx->tuned[sig] = {nb, tile, cap};
         }
     }
     pl->branches = nb;
     pl->sort_tile = tile;
+    pl->fft_cap = cap;
     *out = pl.release();
     return AGN_OK;
 }
@@ -1443,10 +1599,12 @@ extern "C" int agn_batch_plan_info(const agn_batch_plan* pl, int32_t* branches, 
     return AGN_OK;
 }
 
-extern "C" int agn_batch_plan_tuning(const agn_batch_plan* pl, int32_t* branches, int32_t* sort_tile) {
+extern "C" int agn_batch_plan_tuning(const agn_batch_plan* pl, int32_t* branches, int32_t* sort_tile,
+                                     int32_t* fft_cols) {
     if (!pl) return fail(AGN_EINVAL, "plan is NULL");
     if (branches) *branches = pl->branches;
     if (sort_tile) *sort_tile = pl->sort_tile;
+    if (fft_cols) *fft_cols = pl->fft_cap;
     return AGN_OK;
 }
 
@@ -1670,7 +1828,7 @@ extern "C" int agn_periodogram_batch(agn_ctx* ctx, int32_t n_curves, const int64
             for (size_t p = 0; p < rad.size(); ++p) {
                 FftPass P;
                 memset(&P, 0, sizeof(P));
-                P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, AGN_FP64); P.nthreads = rad[p] * P.cols / 16;
+                P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, AGN_FP64); P.nthreads = rad[p] * P.cols / FFT_E;
                 P.Ns = Ns;
                 P.in_mode = p == 0 ? 1 : 0; P.out_mode = 0; P.inverse = 0;
                 P.x_sel = 0; P.with_delta = 0;
@@ -2188,7 +2346,7 @@ static int test_run_big(agn_ctx* ctx, int mode, int64_t n, agn_precision prec, c
         for (int p = 0; p < np - 1; ++p) {
             FftPass P;
             memset(&P, 0, sizeof(P));
-            P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, prec); P.nthreads = rad[p] * P.cols / 16;
+            P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, prec); P.nthreads = rad[p] * P.cols / FFT_E;
             P.Ns = Ns;
             P.in_mode = p == 0 ? 1 : 0; P.out_mode = 0; P.inverse = 0;
             P.x_sel = 0; P.with_delta = 0;
@@ -2210,7 +2368,7 @@ static int test_run_big(agn_ctx* ctx, int mode, int64_t n, agn_precision prec, c
     for (int p = np - 2; p >= 0; --p) {
         FftPass P;
         memset(&P, 0, sizeof(P));
-        P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, prec); P.nthreads = rad[p] * P.cols / 16;
+        P.M = M; P.R = rad[p]; P.cols = fft_cols(M, rad[p], Ns, prec); P.nthreads = rad[p] * P.cols / FFT_E;
         P.Ns = Ns;
         P.in_mode = 0; P.out_mode = 0; P.inverse = 1;
         P.src_sel = 1 - sel; P.dst_sel = sel; P.sub = make_plan(rad[p]);
@@ -2259,4 +2417,31 @@ extern "C" int agn_test_irfft(agn_ctx* ctx, const double* Y, int64_t n, agn_prec
 extern "C" int agn_test_argsort(agn_ctx* ctx, const double* y, int64_t n, agn_precision prec, int32_t path,
                                 uint32_t* rank_out, void* ws, size_t ws_bytes, void* stream) {
     return test_dispatch(ctx, TEST_RANK, y, n, prec, path, nullptr, rank_out, ws, ws_bytes, stream);
+}
+
+extern "C" int agn_test_lds_bandwidth(int32_t blocks, int32_t reps, float* out, double* seconds, void* stream) {
+    if (!out || !seconds || blocks < 1 || reps < 1) return fail(AGN_EINVAL, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    HIPCHK(hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return fail(AGN_EDEVICE, "hipEventCreate failed");
+    }
+    // one untimed launch, then the timed one
+    hipLaunchKernelGGL(k_lds_read_bw, dim3((unsigned)blocks), dim3(1024), 0, st, reps, out);
+    hipError_t e = hipEventRecord(a, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_lds_read_bw, dim3((unsigned)blocks), dim3(1024), 0, st, reps, out);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return fail(AGN_EDEVICE, "LDS bandwidth probe: %s", hipGetErrorString(e));
+    *seconds = (double)ms * 1e-3;
+    return AGN_OK;
 }

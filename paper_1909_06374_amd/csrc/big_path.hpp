@@ -100,7 +100,7 @@ struct FftPass {
     int32_t cols;        // butterflies per workgroup (power of two, 16..64)
     int64_t Ns;          // product of the previous radices
     int32_t in_mode;     // 0: complex buffer, 1: series x_i (FP64, time order)
-    int32_t out_mode;    // 0: complex buffer, 1: keys of y (real view)
+    int32_t out_mode;    // 0: complex buffer, 1: keys of y (real view), 2: none (Eq. 4 partials only)
     int32_t inverse;
     int32_t x_sel;       // in_mode 1: x_i in X0 (0) or X1 (1)
     int32_t with_delta;  // in_mode 1: add Eq. 4 terms of x_i against x_{i-1}
@@ -178,9 +178,10 @@ template <typename T>
 AGN_DEV cplx<T> to_T(cplx<double> a) { return cmk((T)a.re, (T)a.im); }
 
 // grid: (M / R / C, curves), block: P.nthreads (E = R * C / nthreads, nthreads a
-// multiple of C, so each thread stays in one column c = tid mod C).
+// multiple of C and at most 1024, so each thread stays in one column
+// c = tid mod C).
 template <typename T, int E, bool INV, int C>
-__global__ __launch_bounds__(512) void k_fft_pass(const BigCurve* __restrict__ cv, FftPass P, TwTable tb) {
+__global__ __launch_bounds__(1024) void k_fft_pass(const BigCurve* __restrict__ cv, FftPass P, TwTable tb) {
     typedef typename key_of<T>::type K;
     extern __shared__ __align__(16) unsigned char smem[];
     const BigCurve& d = cv[blockIdx.y];
@@ -193,8 +194,8 @@ __global__ __launch_bounds__(512) void k_fft_pass(const BigCurve* __restrict__ c
     const int64_t j0m = (Ns > 1) ? (j0 % Ns) : 0;
     cplx<T>* buf = (cplx<T>*)smem;
     cplx<T>* wr = (cplx<T>*)(smem + (size_t)tpad<T>(R * C + 1) * sizeof(cplx<T>) + 16);
-    double* red = (double*)(wr + R);         // 8 doubles
-    uint32_t* redc = (uint32_t*)(red + 8);   // 8 words
+    double* red = (double*)(wr + R);          // one double per wave (<= 16 waves)
+    uint32_t* redc = (uint32_t*)(red + 16);   // one word per wave
 
 
     // R-th roots for the in-LDS passes: W_R^u = W_N^{u N / R}.
@@ -271,6 +272,9 @@ __global__ __launch_bounds__(512) void k_fft_pass(const BigCurve* __restrict__ c
             d.cpart[blockIdx.x] = cc;
         }
     }
+    // Eq. 4 of the last iteration of a call: the same loads and partition as
+    // the first pass of an iteration, so every delta has one summation order
+    if (P.out_mode == 2) return;
     __syncthreads();
     col_fft<T, E, INV, C>(buf, wr, R, P.sub, tid, nt);
 
@@ -334,7 +338,7 @@ struct MidPass {
 
 // grid: (M / R / (2 C), curves), block P.nthreads (E = 2 R C / nthreads).
 template <typename T, int E, int C, int MODE>
-__global__ __launch_bounds__(512) void k_fft_mid(const BigCurve* __restrict__ cv, MidPass P, TwTable tb) {
+__global__ __launch_bounds__(1024) void k_fft_mid(const BigCurve* __restrict__ cv, MidPass P, TwTable tb) {
     constexpr int C2 = 2 * C;
     extern __shared__ __align__(16) unsigned char smem[];
     const BigCurve& d = cv[blockIdx.y];
@@ -748,41 +752,6 @@ __global__ void k_big_after_prep(const BigCurve* __restrict__ cv) {
     const BigCurve& d = cv[blockIdx.x];
     if (threadIdx.x == 0) {
         if (d.state[0] == 0 || d.iters <= 0) d.state[1] = 0;
-    }
-}
-
-// Eq. 4 partials of the last iteration (x_sel holds x_last, the other buffer
-// x_{last-1}); only for curves still active.  grid: (ntiles, curves), block 256.
-__global__ __launch_bounds__(BIG_THREADS) void k_big_delta_last(const BigCurve* __restrict__ cv, int x_sel) {
-    __shared__ double shd[4];
-    __shared__ uint32_t shc[4];
-    const BigCurve& d = cv[blockIdx.y];
-    if (d.state[1] == 0) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const double* xc = x_sel ? d.X1 : d.X0;
-    const double* xp = x_sel ? d.X0 : d.X1;
-    const int64_t base = (int64_t)blockIdx.x * BIG_TILE;
-    double acc = 0.0;
-    uint32_t chg = 0;
-    for (int i = 0; i < BIG_IPT; ++i) {
-        const int64_t p = base + i * BIG_THREADS + tid;
-        const double a = xc[p], b = xp[p];
-        if (a != b) {
-            const double l = log10(a / b);
-            acc += l * l;
-            ++chg;
-        }
-    }
-#pragma unroll
-    for (int s2 = 32; s2 >= 1; s2 >>= 1) {
-        acc += __shfl_xor(acc, s2, 64);
-        chg += __shfl_xor(chg, s2, 64);
-    }
-    if (lane == 0) { shd[wave] = acc; shc[wave] = chg; }
-    __syncthreads();
-    if (tid == 0) {
-        d.dpart[blockIdx.x] = (shd[0] + shd[1]) + (shd[2] + shd[3]);
-        d.cpart[blockIdx.x] = shc[0] + shc[1] + shc[2] + shc[3];
     }
 }
 

@@ -81,10 +81,11 @@ AGN_DEV double read_lane(double x, int l) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// Deterministic block sum (fixed butterfly + fixed wave order).
+// Deterministic sum over a group of threads (fixed butterfly + fixed wave
+// order); (tid, nt) as for block_radix_sort.  Every thread of the workgroup
+// calls it (it holds workgroup barriers).
 template <typename V>
-AGN_DEV V block_sum(V v, V* scratch /* >= 64 */) {
-    const int tid = threadIdx.x, nt = blockDim.x;
+AGN_DEV V block_sum(V v, V* scratch /* >= 64 */, int tid, int nt) {
     const int lane = tid & 63, wave = tid >> 6, nw = (nt + 63) >> 6;
     __syncthreads();
     if (nt < 64) {
@@ -142,17 +143,18 @@ AGN_DEV TwLds lds_load_twiddles(unsigned char* at, const cplx<double>* __restric
 // Stable ascending ranking of the N = IPT * blockDim.x real values y held in
 // LDS at Zf[rpad(p)] (the inverse transform's output): on return
 // ibuf[hpad(k)] is the sample index at sorted position k, ties by index.
+// (tid, nt): the curve's threads (see block_radix_sort).
 // FP64: keys are the order-preserving integer images of y.  FP32 form: keys
 // are y mapped in FP64 onto 2^30 levels over [min y, max y] (rounded toward
 // zero).  The map is non-decreasing, not strictly increasing: two values
 // closer than its step, range * 2^-30, can share a key and are then ordered
 // by index.  That step lies far below the FP32 round-off of the transforms,
 // and 30-bit keys take 6 radix passes instead of 7.  Every thread of the
-// block calls this; it overwrites the LDS work region from `smem` on.
+// workgroup calls this; it overwrites the LDS work region from `smem` on.
 template <typename T, int IPT>
-AGN_DEV void lds_rank_series(const T* Zf, unsigned char* smem, uint16_t* ibuf, uint32_t* scratch) {
+AGN_DEV void lds_rank_series(const T* Zf, unsigned char* smem, uint16_t* ibuf, uint32_t* scratch, int tid,
+                             int nt) {
     typedef typename key_of<T>::type K;
-    const int tid = threadIdx.x, nt = blockDim.x;
     K key[IPT];
     uint32_t idx2[IPT / 2];
     const int tk = opaque(tid);
@@ -213,18 +215,18 @@ AGN_DEV void lds_rank_series(const T* Zf, unsigned char* smem, uint16_t* ibuf, u
     __syncthreads();
     // FP32 form: indices < N <= 2^14 ride in the key word for the last passes
     block_radix_sort<K, IPT, true, sizeof(T) == 4 ? 30 : 8 * (int)sizeof(K), sizeof(T) == 4 ? 14 : 0>(
-        key, idx2, smem, ibuf, scratch);
+        key, idx2, smem, ibuf, scratch, tid, nt);
 }
 
-// One-time preparation: stable argsort of the draw (64-bit keys), sorted
-// tables and starting ranks.  Same block shape as the iteration kernel.
+// One-time preparation of one curve: stable argsort of the draw (64-bit
+// keys), sorted tables and starting ranks.  (tid, nt): the curve's threads
+// (the workgroup, or an aligned run of whole waves of it) with the LDS region
+// at smem; every thread of the workgroup calls this.  writes = false: compute
+// only (a workgroup slot without a curve of its own).
 template <typename T, int E>
-__global__ __launch_bounds__(1024) void k_lds_prep(const LcDesc* __restrict__ descs) {
+AGN_DEV void lds_prep_curve(const LcDesc& d, unsigned char* smem, int tid, int nt, bool writes) {
     constexpr int IPT = 2 * E;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const LcDesc& d = descs[blockIdx.x];
     const int N = d.n;
-    const int tid = threadIdx.x, nt = blockDim.x;
     size_t sc_off;
     lds_prep_layout(N, nt, &sc_off);
     uint32_t* scratch = (uint32_t*)(smem + sc_off);
@@ -243,8 +245,15 @@ __global__ __launch_bounds__(1024) void k_lds_prep(const LcDesc* __restrict__ de
 #pragma unroll
     for (int j = 0; j < IPT / 2; ++j)
         idx2[j] = (uint32_t)(tid * IPT + 2 * j) | ((uint32_t)(tid * IPT + 2 * j + 1) << 16);
-    bad = __syncthreads_or(bad);
-    block_radix_sort<uint64_t, IPT, false>(key, idx2, smem, ibuf, scratch);
+    // any invalid value among this curve's threads (the sort's first use of
+    // scratch comes after a barrier, so the flag word is read before it)
+    if (tid == 0) scratch[0] = 0u;
+    __syncthreads();
+    if (bad) atomicOr(&scratch[0], 1u);
+    __syncthreads();
+    bad = (int)scratch[0];
+    block_radix_sort<uint64_t, IPT, false>(key, idx2, smem, ibuf, scratch, tid, nt);
+    if (!writes) return;
     T* sT = (T*)d.sT;
 #pragma unroll 4
     for (int u = 0; u < IPT; ++u) {
@@ -259,18 +268,29 @@ __global__ __launch_bounds__(1024) void k_lds_prep(const LcDesc* __restrict__ de
     if (tid == 0) *d.valid = bad ? 0 : 1;
 }
 
-// FUSE2: the plan ends with radix 2 (the host checks), and the forward
-// transform's last pass is fused with the replacement (lds_fold_replace_r2).
-template <typename T, int E, bool FUSE2>
-__global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__ descs) {
-    constexpr int IPT = 2 * E;
+// Same block shape as the iteration kernel; one workgroup per curve.
+template <typename T, int E>
+__global__ __launch_bounds__(1024) void k_lds_prep(const LcDesc* __restrict__ descs) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const LcDesc& d = descs[blockIdx.x];
-    const int N = d.n, M = N / 2;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    lds_prep_curve<T, E>(descs[blockIdx.x], smem, threadIdx.x, blockDim.x, true);
+}
 
-    if (*d.valid == 0) {
-        if (tid == 0 && d.iters_done) *d.iters_done = -1;
+// The iteration of one curve (Sec. 2.1, Sec. 3.2.2) in LDS.  FUSE2: the plan
+// ends with radix 2 (the host checks), and the forward transform's last pass
+// is fused with the replacement (lds_fold_replace_r2).  (tid, nt, smem,
+// writes) as for lds_prep_curve.  The loop runs max_iters >= d.iters trips so
+// that curves sharing a workgroup meet the same barriers; a curve that has
+// done its iterations, stopped, or holds an invalid draw keeps computing but
+// changes and writes nothing.  solo: the curve has the workgroup to itself
+// (an invalid draw then returns at once).
+template <typename T, int E, bool FUSE2>
+AGN_DEV void lds_iterate_curve(const LcDesc& d, unsigned char* smem, int tid, int nt, bool writes, int max_iters,
+                               bool solo) {
+    constexpr int IPT = 2 * E;
+    const int N = d.n, M = N / 2;
+    const bool valid = *d.valid != 0;
+    if (solo && !valid) {
+        if (tid == 0 && d.iters_done && writes) *d.iters_done = -1;
         return;
     }
 
@@ -299,9 +319,13 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
     }
     __syncthreads();
 
+    // the stopping rule is the batch's (one tol for every curve)
+    const bool stop_rule = d.tol >= 0.0;
+    bool active = valid && d.iters > 0;
     int done = 0;
 #pragma unroll 1
-    for (int it = 0; it < d.iters; ++it) {
+    for (int it = 0; it < max_iters; ++it) {
+        if (stop_rule && !solo && !__syncthreads_or(active ? 1 : 0)) break;
         if constexpr (FUSE2) {
             // the last forward pass (radix 2) runs inside the replacement
             lds_fft_passes<T, E, false>(Zc, M, plan, 0, plan.npass - 1, 1, tid, nt, tw);
@@ -313,7 +337,7 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
             lds_fft<T, E, true>(Zc, M, plan, tid, nt, tw);
         }
 
-        lds_rank_series<T, IPT>(Zf, smem, ibuf, scratch);
+        lds_rank_series<T, IPT>(Zf, smem, ibuf, scratch, tid, nt);
 
         // x_i[t] = s[k]; Eq. 4 terms from the log10 table.  The exact
         // fixed-point test (values equal, not only ranks) matters only to the
@@ -324,7 +348,6 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
         double acc = 0.0;
         uint32_t chg = 0;
         const int tpost = opaque(tid);
-        const bool stop_rule = d.tol >= 0.0;
         constexpr int HALF = (IPT % 4 == 0) ? 4 : 2;  // positions per group
 #pragma unroll
         for (int h = 0; h < IPT / HALF; ++h) {
@@ -348,23 +371,36 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
             for (int u = 0; u < HALF; ++u) {
                 const uint32_t k = (uint32_t)((h * HALF + u) * nt + tpost);
                 const uint32_t t = tr[u] & 0xFFFFu, ro = tr[u] >> 16;
-                rank16[t] = (uint16_t)k;
+                if (active) {
+                    rank16[t] = (uint16_t)k;
+                    Zf[rpad<T>(t)] = sv[u];
+                }
                 const double dl = lk[u] - lr[u];
                 acc += dl * dl;
                 if (stop_rule && ro != k) chg += (s64[k] != s64[ro]) ? 1u : 0u;
-                Zf[rpad<T>(t)] = sv[u];
             }
         }
-        acc = block_sum<double>(acc, dscratch);
+        acc = block_sum<double>(acc, dscratch, tid, nt);
         const double delta = sqrt(acc / (double)N);
-        if (tid == 0 && d.delta_out) d.delta_out[it] = delta;
-        done = it + 1;
-        if (stop_rule) {
-            chg = block_sum<uint32_t>(chg, scratch + 64);
-            if (chg == 0u || (d.tol > 0.0 && delta <= d.tol)) break;
+        if (active) {
+            if (tid == 0 && d.delta_out && writes) d.delta_out[it] = delta;
+            done = it + 1;
         }
+        if (stop_rule) {
+            chg = block_sum<uint32_t>(chg, scratch + 64, tid, nt);
+            if (chg == 0u || (d.tol > 0.0 && delta <= d.tol)) {
+                active = false;
+                if (solo) break;
+            }
+        }
+        if (it + 1 >= d.iters) active = false;
     }
     __syncthreads();
+    if (!writes) return;
+    if (!valid) {
+        if (tid == 0 && d.iters_done) *d.iters_done = -1;
+        return;
+    }
 #pragma unroll 4
     for (int u = 0; u < IPT; ++u) {
         const int p = u * nt + tid;
@@ -376,6 +412,69 @@ __global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__
         if (d.iters_done) *d.iters_done = done;
         if (d.delta_out)
             for (int j = done; j < d.iters; ++j) d.delta_out[j] = 0.0;
+    }
+}
+
+// One workgroup per curve.
+template <typename T, int E, bool FUSE2>
+__global__ __launch_bounds__(1024) void k_lds_iterate(const LcDesc* __restrict__ descs) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const LcDesc& d = descs[blockIdx.x];
+    lds_iterate_curve<T, E, FUSE2>(d, smem, threadIdx.x, blockDim.x, true, d.iters, true);
+}
+
+// ----------------------------------------------------------------------------
+// Every LDS-resident curve of a batch, whatever its length, in one persistent
+// launch.  Work items are packs: the curves of one length that fill a
+// 1024-thread workgroup (1024 / nt of them, nt = N / IPT threads each, every
+// curve's threads an aligned run of whole waves, each curve its own LDS
+// region of `stride` bytes); the last pack of a length may hold fewer, and
+// its empty slots compute on a copy of the pack's first curve without
+// writing.  The packs are ordered longest first and the persistent
+// workgroups take them in grid-stride order.  Each pack runs the one-time
+// preparation and then the iteration, with the same per-curve code and
+// arithmetic as k_lds_prep / k_lds_iterate, so results are bit-identical.
+// ----------------------------------------------------------------------------
+struct LdsPack {
+    int32_t first;      // first curve (index into the descriptor array)
+    int32_t count;      // curves in the pack (<= 1024 / nt)
+    int32_t E;          // size class: IPT / 2 (4, 6 or 8)
+    int32_t nt;         // threads per curve (a multiple of 64)
+    int32_t fuse2;      // the length's plan ends with radix 2
+    int32_t max_iters;  // largest iteration count in the pack
+    uint32_t stride;    // LDS bytes per curve
+    int32_t pad;
+};
+
+template <typename T, int E>
+AGN_DEV void lds_pack_curve(const LcDesc& d, unsigned char* smem, int tid, int nt, bool real, int max_iters,
+                            bool fuse2) {
+    lds_prep_curve<T, E>(d, smem, tid, nt, real);
+    // the tables written above are read back below by other threads of the
+    // workgroup: make them visible first
+    __threadfence();
+    __syncthreads();
+    if (fuse2) lds_iterate_curve<T, E, true>(d, smem, tid, nt, real, max_iters, false);
+    else lds_iterate_curve<T, E, false>(d, smem, tid, nt, real, max_iters, false);
+}
+
+// grid: persistent workgroups (at most npacks), block 1024, dynamic LDS: the
+// largest 1024 / nt * stride of the packs.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_lds_packs(const LcDesc* __restrict__ descs,
+                                                    const LdsPack* __restrict__ packs, int npacks) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    for (int p = blockIdx.x; p < npacks; p += gridDim.x) {
+        const LdsPack& pk = packs[p];
+        const int nt = pk.nt;
+        const int sub = (int)threadIdx.x / nt, tid = (int)threadIdx.x - sub * nt;
+        const bool real = sub < pk.count;
+        const LcDesc& d = descs[pk.first + (real ? sub : 0)];
+        unsigned char* base = smem + (size_t)sub * pk.stride;
+        if (pk.E == 8) lds_pack_curve<T, 8>(d, base, tid, nt, real, pk.max_iters, pk.fuse2 != 0);
+        else if (pk.E == 6) lds_pack_curve<T, 6>(d, base, tid, nt, real, pk.max_iters, pk.fuse2 != 0);
+        else lds_pack_curve<T, 4>(d, base, tid, nt, real, pk.max_iters, pk.fuse2 != 0);
+        __syncthreads();  // the next pack reuses the LDS
     }
 }
 

@@ -46,9 +46,11 @@ AGN_DEV uint32_t wave_inclusive_scan(uint32_t x) {
 // word in turn: right after the barrier every wave is here, so such waits
 // would leave the SIMDs idle.  The caller must not overwrite scratch[0 .. nw)
 // until every thread has returned (a later barrier).
+// (tid, nt): the thread's index within the group of threads that scans, and
+// the group's size; a group is a whole workgroup or an aligned run of whole
+// waves of it.
 AGN_DEV uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= nw words */,
-                                      uint32_t* total) {
-    const int tid = threadIdx.x, nt = blockDim.x;
+                                      uint32_t* total, int tid, int nt) {
     const int lane = tid & 63, wave = tid >> 6, nw = (nt + 63) >> 6;
     const uint32_t inc = wave_inclusive_scan(v);
     const int last = (nt - (wave << 6) < 64) ? (nt - (wave << 6) - 1) : 63;
@@ -115,10 +117,9 @@ constexpr int sort_pack_at() {
 
 template <typename K, int IPT, bool SEP, bool ALIGNED, int KBITS, int IB>
 AGN_DEV void block_radix_sort_impl(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned char* work,
-                                   uint16_t* ibuf, uint32_t* scratch) {
+                                   uint16_t* ibuf, uint32_t* scratch, int tid, int T) {
     static_assert(IPT % 2 == 0, "IPT must be even");
     static_assert(KBITS >= 1 && KBITS <= 8 * (int)sizeof(K), "key bits out of range");
-    const int T = blockDim.x;
     constexpr int NPASS = (KBITS + SORT_RB - 1) / SORT_RB;
     constexpr int PACK_AT = sort_pack_at<K, KBITS, IB>();
     static_assert(PACK_AT == NPASS || SEP, "the packed tail is built for separate key and index regions");
@@ -137,7 +138,7 @@ AGN_DEV void block_radix_sort_impl(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], uns
 
 #pragma unroll 1
     for (int pass = 0; pass < NPASS; ++pass) {
-        const int t = opaque((int)threadIdx.x);
+        const int t = opaque(tid);
         const int tb = t + (t >> 5);
         // packed words hold the key bits from SORT_RB * PACK_AT up, above the index
         const int shift = pass < PACK_AT ? pass * SORT_RB : PIB + (pass - PACK_AT) * SORT_RB;
@@ -168,7 +169,7 @@ AGN_DEV void block_radix_sort_impl(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], uns
                 s += w[q];
             }
             uint32_t total;
-            uint32_t run = block_exclusive_scan(s, scratch, &total);
+            uint32_t run = block_exclusive_scan(s, scratch, &total, t, T);
             run += (total & 0xFFFFu) << 16;
 #pragma unroll
             for (int q = 0; q < SORT_LANES; ++q) {
@@ -249,24 +250,27 @@ AGN_DEV void block_radix_sort_impl(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], uns
     }
 }
 
-// IPT 16 is used only with 1024-thread blocks (the host checks that the
-// block size is a multiple of 32 for it), so only the aligned form is built.
+// IPT 16 is used only with 1024-thread groups (the host checks that the
+// group size is a multiple of 32 for it), so only the aligned form is built.
 // Keys use their low KBITS bits (all others must be zero).  IB > 0: every
 // index is below 2^IB, and the tail passes move packed words (32-bit keys).
+// (tid, nt): index within and size of the sorting group of threads (the
+// workgroup, or an aligned run of whole waves of it); every thread of the
+// workgroup must call this, as it contains workgroup barriers.
 template <typename K, int IPT, bool SEP, int KBITS = 8 * (int)sizeof(K), int IB = 0>
 AGN_DEV void block_radix_sort(K (&key)[IPT], uint32_t (&idx2)[IPT / 2], unsigned char* work,
-                              uint16_t* ibuf, uint32_t* scratch) {
+                              uint16_t* ibuf, uint32_t* scratch, int tid, int nt) {
     if constexpr (IPT >= 16) {
-        block_radix_sort_impl<K, IPT, SEP, true, KBITS, IB>(key, idx2, work, ibuf, scratch);
+        block_radix_sort_impl<K, IPT, SEP, true, KBITS, IB>(key, idx2, work, ibuf, scratch, tid, nt);
     } else if constexpr (sizeof(K) == 8) {
         // 64-bit keys (one-time draw sort, FP64 path): one general form keeps
         // register pressure low
-        block_radix_sort_impl<K, IPT, SEP, false, KBITS, IB>(key, idx2, work, ibuf, scratch);
+        block_radix_sort_impl<K, IPT, SEP, false, KBITS, IB>(key, idx2, work, ibuf, scratch, tid, nt);
     } else {
-        if ((blockDim.x & 31) == 0)
-            block_radix_sort_impl<K, IPT, SEP, true, KBITS, IB>(key, idx2, work, ibuf, scratch);
+        if ((nt & 31) == 0)
+            block_radix_sort_impl<K, IPT, SEP, true, KBITS, IB>(key, idx2, work, ibuf, scratch, tid, nt);
         else
-            block_radix_sort_impl<K, IPT, SEP, false, KBITS, IB>(key, idx2, work, ibuf, scratch);
+            block_radix_sort_impl<K, IPT, SEP, false, KBITS, IB>(key, idx2, work, ibuf, scratch, tid, nt);
     }
 }
 

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(1024) void k_test_lds(const TestLds* __restrict__ d
         }
         return;
     }
-    lds_rank_series<T, IPT>(Zf, smem, ibuf, scratch);
+    lds_rank_series<T, IPT>(Zf, smem, ibuf, scratch, tid, nt);
     for (int k = tid; k < N; k += nt) d.rank_out[ibuf[hpad(k)]] = (uint32_t)k;
 }
 
@@ -110,6 +110,32 @@ __global__ __launch_bounds__(256) void k_test_big_keys(const BigCurve* __restric
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     ((K*)d.sortA)[p] = ord_key((T)y[p]);
+}
+
+// LDS read bandwidth probe (the ceiling of the LDS-resident kernels'
+// LDS traffic): every thread of a 1024-thread workgroup reads 16-byte words
+// of a 64 KB LDS buffer, consecutive lanes consecutive words (no bank
+// conflicts), `reps` times over; the sum of what it read goes to out, so
+// the loads cannot be removed.  Bytes read per workgroup: reps * 64 KB.
+// grid: any, block 1024.
+__global__ __launch_bounds__(1024) void k_lds_read_bw(int reps, float* __restrict__ out) {
+    __shared__ float4 buf[4096];
+    const int t = threadIdx.x;
+    for (int i = t; i < 4096; i += 1024) buf[i] = make_float4((float)i, 1.0f, 2.0f, 3.0f);
+    __syncthreads();
+    float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int r = 0; r < reps; ++r) {
+        const int base = opaque(r & 1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float4 v = buf[(t + k * 1024 + base) & 4095];
+            acc.x += v.x;
+            acc.y += v.y;
+            acc.z += v.z;
+            acc.w += v.w;
+        }
+    }
+    out[(size_t)blockIdx.x * 1024 + t] = acc.x + acc.y + acc.z + acc.w;
 }
 
 }  // namespace agn

@@ -13,12 +13,22 @@ The server
   cap) as one batch on that stream, so several batches of mixed lengths are in
   flight at once and a request never waits for a whole earlier batch to end
   before it is launched;
+* optionally works at the granularity of iterations (``segment_iters``): a
+  launch runs at most that many iterations of each request in it, and a
+  request with iterations left goes back to the end of the queue, so that
+  requests that arrive later join the device at the next segment boundary
+  instead of waiting for a long request's whole run;
 * records, per request, arrival time and completion time on the device clock
   (events), giving latency = completion - arrival.
 
 Batching never changes results: a curve's output depends only on its own
 inputs (per-curve Philox keys, per-curve launch groups), so a request served
-in a mixed batch is bit-identical to the same request served alone.
+in a mixed batch is bit-identical to the same request served alone.  A
+segment restarts the generator from the request's current series with the
+same seed: the Timmer-Koenig moduli are drawn again identically, the series
+is a permutation of the draw (the same sorted values), and the iteration's
+only state is the series itself (Sec. 2.1), so segmented and uninterrupted
+runs are bit-identical too.
 
 The scheduling logic is independent of the GPU (``Backend``), so it is tested
 on the CPU with a simulated backend; ``GpuBackend`` drives the C ABI.
@@ -48,6 +58,8 @@ class Request:
     launched: float = -1.0
     done: float = -1.0      # completion time (seconds after start)
     batch: int = -1
+    progress: int = 0       # iterations run so far
+    segments: int = 0       # launches the request took part in
 
 
 @dataclass
@@ -57,6 +69,9 @@ class Batch:
     slot: int
     handle: object = None
     footprint: int = 0
+    # per request: first iteration and iteration count of this launch
+    start: List[int] = field(default_factory=list)
+    count: List[int] = field(default_factory=list)
 
 
 class Backend:
@@ -71,7 +86,9 @@ class Backend:
         """Marks time zero on the device clock."""
 
     def launch(self, batch: Batch) -> object:
-        """Enqueues the batch on its slot; returns a handle."""
+        """Enqueues the batch on its slot: iterations batch.start[i] ..
+        batch.start[i] + batch.count[i] - 1 of request batch.reqs[i]; returns
+        a handle."""
         raise NotImplementedError
 
     def finished(self, handle) -> Optional[float]:
@@ -80,6 +97,9 @@ class Backend:
 
     def release(self, handle) -> None:
         """Frees what the batch held (after it finished)."""
+
+    def retire(self, req: Request) -> None:
+        """The request has run all its iterations: frees what it held."""
 
     def now(self) -> float:
         raise NotImplementedError
@@ -111,16 +131,20 @@ class Server:
     """Continuous-batching scheduler with HBM-footprint admission."""
 
     def __init__(self, backend: Backend, budget_bytes: int, max_batch_samples: int = 2**26,
-                 max_batch_curves: int = 4096):
+                 max_batch_curves: int = 4096, segment_iters: Optional[int] = None):
         self.be = backend
         self.budget = int(budget_bytes)
         self.max_batch_samples = int(max_batch_samples)
         self.max_batch_curves = int(max_batch_curves)
+        if segment_iters is not None and int(segment_iters) < 1:
+            raise ValueError("segment_iters must be at least 1")
+        self.segment_iters = None if segment_iters is None else int(segment_iters)
 
     def run(self, reqs: List[Request]) -> ServeStats:
         be = self.be
         reqs = sorted(reqs, key=lambda r: (r.arrival, r.rid))
         for r in reqs:
+            r.progress, r.segments = 0, 0
             r.footprint = int(be.footprint(r))
             if r.footprint > self.budget:
                 raise ValueError(f"request {r.rid} needs {r.footprint} bytes, over the {self.budget}-byte budget")
@@ -142,11 +166,16 @@ class Server:
                 t = be.finished(b.handle)
                 if t is None:
                     continue
-                for r in b.reqs:
-                    r.done = t
-                done_count += len(b.reqs)
-                used -= b.footprint
                 be.release(b.handle)
+                for r, k in zip(b.reqs, b.count):
+                    r.progress += k
+                    if r.progress >= r.iters:
+                        r.done = t
+                        done_count += 1
+                        used -= r.footprint
+                        be.retire(r)
+                    else:
+                        admitted.append(r)  # next segment, behind what is queued
                 del inflight[slot]
                 progressed = True
             now = be.now()
@@ -173,9 +202,15 @@ class Server:
                     r = admitted.pop(0)
                     take.append(r)
                     samples += r.n
-                b = Batch(nb, take, slot, footprint=sum(r.footprint for r in take))
+                seg = self.segment_iters
+                b = Batch(nb, take, slot, footprint=sum(r.footprint for r in take),
+                          start=[r.progress for r in take],
+                          count=[r.iters - r.progress if seg is None else min(seg, r.iters - r.progress)
+                                 for r in take])
                 for r in take:
-                    r.launched = now
+                    if r.segments == 0:
+                        r.launched = now
+                    r.segments += 1
                     r.batch = nb
                 b.handle = be.launch(b)
                 inflight[slot] = b
@@ -211,7 +246,11 @@ def make_requests(rate_hz: float, duration_s: float, seed: int, k_lo: int = 12, 
 
 class GpuBackend(Backend):
     """Runs batches through agn_erdf_draw + agn_lc_generate_batch on
-    default-priority streams of one device; completion times from events."""
+    default-priority streams of one device; completion times from events.
+    A request that runs in segments keeps its current series (and its Eq. 4
+    history) in buffers of its own between launches; a segment's launch
+    starts from that series (as the PDF draw of a generate call with the
+    request's seed) and writes the next one back."""
 
     def __init__(self, ctx, n_slots: int = 4, prec: int = 1, erdf_params=None, keep_outputs: bool = False):
         import torch
@@ -226,13 +265,16 @@ class GpuBackend(Backend):
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(self.n_slots)]
         self.keep = keep_outputs
         self.outputs: Dict[int, np.ndarray] = {}
+        self.histories: Dict[int, np.ndarray] = {}
+        self.state: Dict[int, Dict] = {}
         self._ws_size = agn_batch_workspace_size
         self._t0 = None
         self._wall0 = 0.0
 
     def footprint(self, req: Request) -> int:
-        # workspace (incl. descriptors) + PDF draw + output + history + iteration count
-        return int(self._ws_size([req.n], self.prec)) + 16 * req.n + 8 * req.iters + 4
+        # workspace (incl. descriptors) + PDF draw + output + history + iteration count,
+        # plus the series and history a segmented request keeps between launches
+        return int(self._ws_size([req.n], self.prec)) + 24 * req.n + 16 * req.iters + 4
 
     def start_clock(self) -> None:
         torch = self.torch
@@ -249,34 +291,61 @@ class GpuBackend(Backend):
         from . import agn_erdf_draw, agn_lc_generate_batch, psd_params
         torch = self.torch
         st = self.streams[batch.slot]
-        ns = [r.n for r in batch.reqs]
+        reqs = batch.reqs
+        counts = list(batch.count) if batch.count else [r.iters for r in reqs]
+        starts = list(batch.start) if batch.start else [0] * len(reqs)
+        ns = [r.n for r in reqs]
         offs = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)
         tot = int(sum(ns))
-        mx = max(r.iters for r in batch.reqs)
+        mx = max(max(counts), 1)
         with torch.cuda.stream(st):
             erdf = torch.empty(tot, dtype=torch.float64, device=self.dev)
             x = torch.empty(tot, dtype=torch.float64, device=self.dev)
-            d = torch.empty(len(ns) * max(mx, 1), dtype=torch.float64, device=self.dev)
+            d = torch.empty(len(ns) * mx, dtype=torch.float64, device=self.dev)
             done = torch.empty(len(ns), dtype=torch.int32, device=self.dev)
             ws = torch.empty(self._ws_size(ns, self.prec), dtype=torch.uint8, device=self.dev)
-        for r, o in zip(batch.reqs, offs):
-            agn_erdf_draw(self.ctx, self.ep, r.n, r.seed, r.rid, erdf[int(o):int(o) + r.n], stream=st)
-        agn_lc_generate_batch(self.ctx, ns, offs, [psd_params(0.0, r.f_br, r.a_low, r.a_high) for r in batch.reqs],
-                              [r.dt for r in batch.reqs], [r.iters for r in batch.reqs],
-                              [r.seed for r in batch.reqs], [r.rid for r in batch.reqs], erdf, -1.0, self.prec,
-                              x, d, done, ws, stream=st)
+            for r, o, s0, k in zip(reqs, offs, starts, counts):
+                seg = erdf[int(o):int(o) + r.n]
+                if s0 == 0:
+                    agn_erdf_draw(self.ctx, self.ep, r.n, r.seed, r.rid, seg, stream=st)
+                    if k < r.iters:  # segmented: the request keeps its series between launches
+                        self.state[r.rid] = dict(
+                            x=torch.empty(r.n, dtype=torch.float64, device=self.dev),
+                            hist=torch.zeros(max(r.iters, 1), dtype=torch.float64, device=self.dev))
+                else:
+                    seg.copy_(self.state[r.rid]["x"])
+        agn_lc_generate_batch(self.ctx, ns, offs, [psd_params(0.0, r.f_br, r.a_low, r.a_high) for r in reqs],
+                              [r.dt for r in reqs], counts, [r.seed for r in reqs], [r.rid for r in reqs], erdf, -1.0,
+                              self.prec, x, d, done, ws, stream=st)
+        with torch.cuda.stream(st):
+            for i, (r, o, s0, k) in enumerate(zip(reqs, offs, starts, counts)):
+                if r.rid in self.state:
+                    stt = self.state[r.rid]
+                    stt["x"].copy_(x[int(o):int(o) + r.n])
+                    if k > 0:
+                        stt["hist"][s0:s0 + k].copy_(d[i * mx:i * mx + k])
         ev = torch.cuda.Event(enable_timing=True)
         ev.record(st)
-        return dict(ev=ev, bufs=(erdf, x, d, done, ws), batch=batch, offs=offs)
+        return dict(ev=ev, bufs=(erdf, x, d, done, ws), batch=batch, offs=offs, starts=starts, counts=counts, mx=mx)
 
     def finished(self, h) -> Optional[float]:
         if not h["ev"].query():
             return None
         if self.keep:
             x = h["bufs"][1].cpu().numpy()
-            for r, o in zip(h["batch"].reqs, h["offs"]):
+            d = h["bufs"][2].cpu().numpy()
+            for i, (r, o, s0, k) in enumerate(zip(h["batch"].reqs, h["offs"], h["starts"], h["counts"])):
+                if s0 + k < r.iters:
+                    continue  # more segments to come
                 self.outputs[r.rid] = x[int(o):int(o) + r.n].copy()
+                if r.rid in self.state:
+                    self.histories[r.rid] = self.state[r.rid]["hist"].cpu().numpy()[:r.iters].copy()
+                else:
+                    self.histories[r.rid] = d[i * h["mx"]:i * h["mx"] + r.iters].copy()
         return self._t0.elapsed_time(h["ev"]) / 1000.0
 
     def release(self, h) -> None:
         h["bufs"] = None
+
+    def retire(self, req: Request) -> None:
+        self.state.pop(req.rid, None)

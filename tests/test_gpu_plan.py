@@ -55,10 +55,11 @@ def _plan(ctx, b, erdf_t, o, flags, branches):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("flags,branches", [(0, 1), (0, 3), (1, 1), (1, 4), (4, 1), (5, 2)])
+@pytest.mark.parametrize("flags,branches", [(0, 1), (0, 3), (1, 1), (1, 4), (4, 1), (5, 2), (8, 1), (9, 2)])
 def test_plan_launch_equals_batch(gpu_ctx, prec, flags, branches):
     """Also with the 16384-key sort tile (flag 4): in FP32 it applies to the
-    2^15 and 2^16 curves of the batch, whose sorts must stay exact."""
+    2^15 and 2^16 curves of the batch, whose sorts must stay exact; and with
+    16 butterflies per FFT workgroup (flag 8), which must not change a bit."""
     m = agn()
     b = _batch(prec)
     erdf_t = dev(b["erdf"])
@@ -66,9 +67,15 @@ def test_plan_launch_equals_batch(gpu_ctx, prec, flags, branches):
     o = _buffers(b)
     plan = _plan(gpu_ctx, b, erdf_t, o, flags, branches)
     info = plan.info()
-    assert info["groups"] == len(set(NS)) and info["graph"] == bool(flags & m.AGN_PLAN_GRAPH)
+    # launch groups: one per length, except that in FP32 the LDS-resident
+    # lengths 1024, 1536 and 2^14 (whole waves per curve) share one pack
+    # launch; in FP64 only 1024 qualifies (1536 does not fit a workgroup's
+    # worth of curves), and one length alone is not packed
+    groups = len(set(NS)) - (2 if prec == 1 else 0)
+    assert info["groups"] == groups and info["graph"] == bool(flags & m.AGN_PLAN_GRAPH)
     assert info["branches"] == max(branches, 1)
     assert info["sort_tile"] == (16384 if flags & m.AGN_PLAN_LARGE_SORT_TILE else 8192)
+    assert info["fft_cols"] == (16 if flags & m.AGN_PLAN_NARROW_FFT else 64)
     for rep in range(3):
         o["x"].fill_(float("nan"))
         o["done"].fill_(-7)
@@ -135,10 +142,12 @@ def test_plan_argument_errors(gpu_ctx):
     b = _batch(0)
     erdf_t = dev(b["erdf"])
     o = _buffers(b)
-    with pytest.raises(m.AgnError):
-        _plan(gpu_ctx, b, erdf_t, o, 8, 1)
+    with pytest.raises(m.AgnError):  # unknown flag
+        _plan(gpu_ctx, b, erdf_t, o, 16, 1)
     with pytest.raises(m.AgnError):  # a fixed tile and tuning exclude each other
         _plan(gpu_ctx, b, erdf_t, o, m.AGN_PLAN_AUTOTUNE | m.AGN_PLAN_LARGE_SORT_TILE, 1)
+    with pytest.raises(m.AgnError):  # so do a fixed FFT width and tuning
+        _plan(gpu_ctx, b, erdf_t, o, m.AGN_PLAN_AUTOTUNE | m.AGN_PLAN_NARROW_FFT, 1)
     with pytest.raises(m.AgnError):
         _plan(gpu_ctx, b, erdf_t, o, 0, 9)
     small = dict(o, ws=o["ws"][:1024])

@@ -30,7 +30,8 @@ class SimBackend(Backend):
         self.t += max(seconds, 1e-5)
 
     def launch(self, batch):
-        work = sum(r.n * r.iters for r in batch.reqs)
+        counts = batch.count if batch.count else [r.iters for r in batch.reqs]
+        work = sum(r.n * k for r, k in zip(batch.reqs, counts))
         end = self.t + self.overhead + work / self.rate
         self.log.append((batch.bid, batch.slot, self.t, end, [r.rid for r in batch.reqs]))
         return end
@@ -115,3 +116,38 @@ def test_request_generator_matches_recipe():
     assert its.min() >= 50 and its.max() <= 200
     gaps = np.diff([r.arrival for r in reqs])
     assert abs(gaps.mean() - 1 / 2000.0) < 0.1 / 2000.0
+
+
+def test_segments_let_a_short_request_overtake_a_long_one():
+    """With iteration segments a request that arrives while a long one runs
+    joins at the next segment boundary and finishes first; without them it
+    waits for the long run to end."""
+    def run(seg):
+        be = SimBackend(n_slots=1, rate=1e9, overhead=1e-5)
+        long_r = Request(rid=0, n=2**20, iters=200, f_br=0.01, a_low=1.0, a_high=2.0, seed=0, arrival=0.0)
+        short = Request(rid=1, n=2**12, iters=50, f_br=0.01, a_low=1.0, a_high=2.0, seed=1, arrival=1e-3)
+        st = Server(be, budget_bytes=2**36, segment_iters=seg).run([long_r, short])
+        assert st.completed == 2
+        assert long_r.progress == 200 and short.progress == 50
+        return long_r, short, be
+    long_r, short, _ = run(None)
+    assert short.done > long_r.done
+    long_s, short_s, be = run(25)
+    assert short_s.done < long_s.done
+    assert long_s.segments == 8 and short_s.segments == 2
+    # the long run's total work is unchanged; its completion moves only by the
+    # short request's share of the shared launches
+    assert long_s.done >= long_r.done
+
+
+def test_segments_keep_budget_and_order():
+    be = SimBackend(n_slots=2, rate=2e9)
+    reqs = make_requests(rate_hz=300.0, duration_s=1.0, seed=8, k_lo=12, k_hi=18, iters_lo=50, iters_hi=200)
+    srv = Server(be, budget_bytes=2**34, segment_iters=30)
+    st = srv.run(reqs)
+    _check_common(reqs, st, srv)
+    assert all(r.progress == r.iters for r in reqs)
+    assert all(r.segments == -(-r.iters // 30) for r in reqs)
+    # every launch runs at most 30 iterations of each request
+    work = sum(r.n * r.iters for r in reqs)
+    assert st.sample_iterations == work
