@@ -609,8 +609,8 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
     constexpr int SCAT_THREADS = TILE / SCAT_IPT;
     static_assert(SCAT_THREADS <= 1024, "tile too large for one workgroup");
     constexpr int SCAT_WAVES = SCAT_THREADS / 64;
-    __shared__ uint16_t wcnt[SCAT_WAVES][256];  // per-wave running digit counters (<= 64 * SCAT_IPT)
-    __shared__ uint16_t wpre[SCAT_WAVES][256];  // exclusive prefix over waves
+    __shared__ uint16_t wcnt[SCAT_WAVES][256];  // per-wave running digit counters (<= 64 * SCAT_IPT),
+                                                // then their exclusive prefix over waves
     __shared__ uint32_t tstart[256];            // digit start inside the tile
     __shared__ uint32_t gbase[256];             // global start of the tile's digit run
     __shared__ uint32_t wtot[4];                // digit-scan totals of the first four waves
@@ -667,7 +667,7 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
 #pragma unroll
         for (int w = 0; w < SCAT_WAVES; ++w) {
             const uint32_t c = wcnt[w][q];
-            wpre[w][q] = (uint16_t)run;
+            wcnt[w][q] = (uint16_t)run;
             run += c;
         }
         tot = run;
@@ -691,7 +691,7 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
 #pragma unroll
     for (int i = 0; i < SCAT_IPT; ++i) {
         const uint32_t dg = (uint32_t)(key[i] >> P.shift) & 255u;
-        const uint32_t pl = tstart[dg] + wpre[wave][dg] + loc[i];
+        const uint32_t pl = tstart[dg] + wcnt[wave][dg] + loc[i];
         skey[pl] = key[i];
         sval[pl] = val[i];
     }
