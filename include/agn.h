@@ -156,7 +156,9 @@ int agn_psd_spectrum_noalloc(agn_ctx* ctx, const agn_psd_params* p, int64_t n, d
  *              sqrt(mean_n (log10 x_i[n] - log10 x_{i-1}[n])^2); entries past
  *              iters_done are 0.
  *   iters_done device, one int32 or NULL: iterations performed, -1 if x0 holds
- *              a value that is not finite and > 0.
+ *              a value that is not finite and > 0, -2 if a multi-pass sort
+ *              step gave up waiting for another workgroup (a device fault
+ *              that should not occur; x_out is then not valid).
  *   rank_out   device, n uint32 or NULL: rank_out[t] = index into s of x_out[t].
  * Each iteration: X = rFFT(x_{i-1}); Y_j = amp_j X_j / |X_j| (Y_0 = 0,
  * Y_{n/2} = amp_{n/2} sign(Re X_{n/2}) with sign(0) = +1, phase 0 where

@@ -150,8 +150,9 @@ static size_t big_curve_ws(int64_t n, agn_precision prec) {
     b += 2 * align256((size_t)n * 8);       // X0, X1
     b += 2 * align256((size_t)n * 4);       // rankA, rankB
     b += 2 * align256(region);              // sortA, sortB
-    b += align256((size_t)ntiles * 256 * 4);  // hist
-    b += align256(256 * 4);                 // dstart
+    b += align256((size_t)ntiles * 256 * 4);  // look
+    b += 2 * align256(SORT_MAX_PASSES * 256 * 4);  // dcount, dstart
+    b += align256(SORT_MAX_PASSES * 4);     // tickets
     b += align256((size_t)big_npart(n) * 8);  // dpart
     b += align256((size_t)big_npart(n) * 4);  // cpart
     b += align256(16);                      // state
@@ -671,27 +672,42 @@ static void launch_fft_mid(agn_ctx* ctx, const BigCurve* d, int nc, const MidPas
     hipLaunchKernelGGL((k_fft_mid<T, MID_E, 8, MODE>), grid, dim3(P.nthreads), lds, st, d, P, tb);
 }
 
+// One LSD sort of the keys in region src0, sizeof(K) passes of 8-bit digits:
+// digit totals of every pass, their starts, then the scatter passes (the last
+// in `last_mode`).  *seq counts the scatter passes of the call, which gives
+// each pass its look-back epoch (consecutive passes differ).
+constexpr int SORT_COUNT_WORKGROUPS = 512;  // k_sort_count workgroups over all curves of a launch
+
 template <typename K, int TILE>
-static void launch_sort_pass_t(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, const SortPass& P,
-                               hipStream_t st) {
+static void run_sort_t(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, int src0, int last_mode, int rank_sel,
+                       int* seq, hipStream_t st) {
     const int64_t ntiles = n / TILE;
-    dim3 gt((unsigned)ntiles, (unsigned)nc);
+    const int npass = (int)sizeof(K);
     {
         ProfScope ps(ctx, "sort_hist", st);
-        hipLaunchKernelGGL((k_sort_hist<K, TILE>), gt, dim3(BIG_THREADS), 0, st, d, P, ntiles);
+        const int64_t g = std::min<int64_t>(ntiles, std::max(1, SORT_COUNT_WORKGROUPS / nc));
+        hipLaunchKernelGGL((k_sort_count<K, TILE>), dim3((unsigned)g, (unsigned)nc), dim3(BIG_THREADS), 0, st, d,
+                           src0, ntiles);
     }
     {
         ProfScope ps(ctx, "sort_scan", st);
-        if (ntiles <= SCAN_SMALL_TILES) {
-            hipLaunchKernelGGL(k_sort_scan_small, dim3((unsigned)nc), dim3(BIG_THREADS), 0, st, d, ntiles);
-        } else {
-            hipLaunchKernelGGL(k_sort_scan_rows, dim3(256, (unsigned)nc), dim3(BIG_THREADS), 0, st, d, ntiles);
-            hipLaunchKernelGGL(k_sort_scan_digits, dim3((unsigned)nc), dim3(BIG_THREADS), 0, st, d);
-        }
+        hipLaunchKernelGGL(k_sort_starts, dim3((unsigned)nc), dim3(BIG_THREADS), 0, st, d, npass);
     }
-    {
+    int src = src0;
+    for (int p = 0; p < npass; ++p) {
+        SortPass P;
+        memset(&P, 0, sizeof(P));
+        P.shift = 8 * p;
+        P.first = p == 0;
+        P.src_sel = src;
+        P.mode = p == npass - 1 ? last_mode : SORT_MODE_MOVE;
+        P.rank_sel = rank_sel;
+        P.pass = p;
+        P.epoch = (*seq)++ % 3 + 1;
         ProfScope ps(ctx, "sort_scatter", st);
-        hipLaunchKernelGGL((k_sort_scatter<K, TILE>), gt, dim3(TILE / scat_ipt<K>::value), 0, st, d, P, ntiles);
+        hipLaunchKernelGGL((k_sort_scatter<K, TILE>), dim3((unsigned)ntiles, (unsigned)nc),
+                           dim3(TILE / scat_ipt<K>::value), 0, st, d, P, ntiles);
+        src = 1 - src;
     }
 }
 
@@ -701,16 +717,16 @@ static int sort_tile_for(int64_t n, int want) {
     return (sizeof(K) == 4 && want == SORT_TILE_BIG && n % SORT_TILE_BIG == 0) ? SORT_TILE_BIG : BIG_TILE;
 }
 
-template <typename K, typename T>
-static void launch_sort_pass(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, const SortPass& P, int tile,
-                             hipStream_t st) {
+template <typename K>
+static void run_sort(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, int src0, int last_mode, int rank_sel,
+                     int tile, int* seq, hipStream_t st) {
     if constexpr (sizeof(K) == 4) {
         if (sort_tile_for<K>(n, tile) == SORT_TILE_BIG) {
-            launch_sort_pass_t<K, SORT_TILE_BIG>(ctx, d, nc, n, P, st);
+            run_sort_t<K, SORT_TILE_BIG>(ctx, d, nc, n, src0, last_mode, rank_sel, seq, st);
             return;
         }
     }
-    launch_sort_pass_t<K, BIG_TILE>(ctx, d, nc, n, P, st);
+    run_sort_t<K, BIG_TILE>(ctx, d, nc, n, src0, last_mode, rank_sel, seq, st);
 }
 
 // Checks the multi-pass FFT plan of length n and resolves its twiddle table.
@@ -750,21 +766,14 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
     const int64_t M = n / 2, ntiles = n / BIG_TILE;
     const dim3 gt((unsigned)ntiles, (unsigned)nc);
     hipLaunchKernelGGL(k_big_init, dim3((unsigned)nc), dim3(64), 0, st, d);
+    hipLaunchKernelGGL(k_sort_clear, gt, dim3(BIG_THREADS), 0, st, d);
+    int seq = 0;  // scatter passes so far (look-back epochs)
     {
         ProfScope ps(ctx, "big_prep", st);
         hipLaunchKernelGGL(k_big_prep_keys, gt, dim3(BIG_THREADS), 0, st, d);
-        for (int p = 0; p < 8; ++p) {
-            SortPass P;
-            P.shift = 8 * p;
-            P.first = p == 0;
-            P.src_sel = p & 1;
-            P.mode = p == 7 ? SORT_MODE_PREP : SORT_MODE_MOVE;
-            P.rank_sel = 0;
-            launch_sort_pass<uint64_t, T>(nullptr, d, nc, n, P, BIG_TILE, st);
-        }
+        run_sort<uint64_t>(nullptr, d, nc, n, 0, SORT_MODE_PREP, 0, BIG_TILE, &seq, st);
     }
     hipLaunchKernelGGL(k_big_after_prep, dim3((unsigned)nc), dim3(64), 0, st, d);
-    const int npass_sort = (int)sizeof(K);
     const int np = (int)rad.size();
     const int prec_bits = sizeof(T) == 4 ? 1 : 0;
     const agn_precision prec = prec_bits ? AGN_FP32 : AGN_FP64;
@@ -811,17 +820,7 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
             sel = 1 - sel;
         }
         // keys are in region (1 - sel)
-        int src = 1 - sel;
-        for (int p = 0; p < npass_sort; ++p) {
-            SortPass P;
-            P.shift = 8 * p;
-            P.first = p == 0;
-            P.src_sel = src;
-            P.mode = p == npass_sort - 1 ? SORT_MODE_RANK : SORT_MODE_MOVE;
-            P.rank_sel = 1 - cur;
-            launch_sort_pass<K, T>(ctx, d, nc, n, P, sort_tile, st);
-            src = 1 - src;
-        }
+        run_sort<K>(ctx, d, nc, n, 1 - sel, SORT_MODE_RANK, 1 - cur, sort_tile, &seq, st);
     }
     {
         // delta of the last iteration for curves that ran all of them: the
@@ -975,8 +974,10 @@ static int build_plan(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_p
             d.rankB = (uint32_t*)(base + off); off += align256((size_t)n * 4);
             d.sortA = base + off; off += align256((size_t)n * 12);
             d.sortB = base + off; off += align256((size_t)n * 12);
-            d.hist = (uint32_t*)(base + off); off += align256((size_t)ntiles * 256 * 4);
-            d.dstart = (uint32_t*)(base + off); off += align256(256 * 4);
+            d.look = (uint32_t*)(base + off); off += align256((size_t)ntiles * 256 * 4);
+            d.dcount = (uint32_t*)(base + off); off += align256(SORT_MAX_PASSES * 256 * 4);
+            d.dstart = (uint32_t*)(base + off); off += align256(SORT_MAX_PASSES * 256 * 4);
+            d.tickets = (uint32_t*)(base + off); off += align256(SORT_MAX_PASSES * 4);
             d.dpart = (double*)(base + off); off += align256((size_t)big_npart(n) * 8);
             d.cpart = (uint32_t*)(base + off); off += align256((size_t)big_npart(n) * 4);
             d.state = (int32_t*)(base + off); off += align256(16);
@@ -2304,8 +2305,10 @@ static int test_run_big(agn_ctx* ctx, int mode, int64_t n, agn_precision prec, c
     d.rankB = (uint32_t*)(base + off); off += align256((size_t)n * 4);
     d.sortA = base + off; off += align256((size_t)n * 12);
     d.sortB = base + off; off += align256((size_t)n * 12);
-    d.hist = (uint32_t*)(base + off); off += align256((size_t)ntiles * 256 * 4);
-    d.dstart = (uint32_t*)(base + off); off += align256(256 * 4);
+    d.look = (uint32_t*)(base + off); off += align256((size_t)ntiles * 256 * 4);
+    d.dcount = (uint32_t*)(base + off); off += align256(SORT_MAX_PASSES * 256 * 4);
+    d.dstart = (uint32_t*)(base + off); off += align256(SORT_MAX_PASSES * 256 * 4);
+    d.tickets = (uint32_t*)(base + off); off += align256(SORT_MAX_PASSES * 4);
     d.dpart = (double*)(base + off); off += align256((size_t)big_npart(n) * 8);
     d.cpart = (uint32_t*)(base + off); off += align256((size_t)big_npart(n) * 4);
     d.state = (int32_t*)(base + off); off += align256(16);
@@ -2322,18 +2325,9 @@ static int test_run_big(agn_ctx* ctx, int mode, int64_t n, agn_precision prec, c
     const unsigned nb = (unsigned)((n + 255) / 256);
     if (mode == TEST_RANK) {
         hipLaunchKernelGGL((k_test_big_keys<T>), dim3(nb), dim3(256), 0, st, dv, n, in);
-        int src = 0;
-        const int npass = (int)sizeof(K);
-        for (int p = 0; p < npass; ++p) {
-            SortPass P;
-            P.shift = 8 * p;
-            P.first = p == 0;
-            P.src_sel = src;
-            P.mode = p == npass - 1 ? SORT_MODE_RANK : SORT_MODE_MOVE;
-            P.rank_sel = 1;
-            launch_sort_pass<K, T>(ctx, dv, 1, n, P, BIG_TILE, st);
-            src = 1 - src;
-        }
+        int seq = 0;
+        hipLaunchKernelGGL(k_sort_clear, dim3((unsigned)ntiles), dim3(BIG_THREADS), 0, st, dv);
+        run_sort<K>(ctx, dv, 1, n, 0, SORT_MODE_RANK, 1, BIG_TILE, &seq, st);
         return AGN_OK;
     }
     // The iteration's transforms: forward passes 0 .. np-2, then the middle

@@ -11,9 +11,11 @@
 //                transform's first pass (k_fft_mid)
 //   IFFT passes  the remaining radices in reverse order ... -> y, written as
 //                order-preserving integer keys
-//   sort passes  LSD radix sort of (key, sample index), 8-bit digits: per tile
-//                histogram -> per-curve scan -> stable scatter staged through
-//                LDS in digit order, so global writes are contiguous runs; the
+//   sort passes  LSD radix sort of (key, sample index), 8-bit digits: one
+//                histogram of every pass's digits, their starts, then per pass
+//                one stable scatter staged through LDS in digit order (global
+//                writes are contiguous runs), each tile finding where its runs
+//                start by a decoupled look-back over the tiles before it; the
 //                last pass writes x_{i+1}[sample] = s[sorted position] into the
 //                other series buffer (the sorted values are read contiguously)
 //
@@ -65,11 +67,13 @@ struct BigCurve {
     uint32_t* rankB;       // [N] ranks of x_i, odd i
     unsigned char* sortA;  // N * 12 bytes: keys, then 32-bit values
     unsigned char* sortB;
-    uint32_t* hist;        // 256 * ntiles digit counts, scanned in place
-    uint32_t* dstart;      // 256 digit starts
+    uint32_t* look;        // ntiles * 256 look-back words of the sort scatter
+    uint32_t* dcount;      // [SORT_MAX_PASSES][256] digit totals of one sort (accumulated)
+    uint32_t* dstart;      // [SORT_MAX_PASSES][256] digit starts of one sort
+    uint32_t* tickets;     // [SORT_MAX_PASSES] tile tickets of the scatter passes
     double* dpart;         // [npart] delta partial sums
     uint32_t* cpart;       // [npart] changed-sample counts
-    int32_t* state;        // [0] valid, [1] active, [2] iterations done
+    int32_t* state;        // [0] valid, [1] active, [2] iterations done, [3] a look-back wait gave up
     double* x_out;
     double* delta_out;     // [iters] or null
     int32_t* iters_done;   // or null
@@ -470,6 +474,7 @@ __global__ __launch_bounds__(1024) void k_fft_mid(const BigCurve* __restrict__ c
 // / 64, lane p mod 64 (striped inside a wave, so loads are coalesced and the
 // wave ranks its items in position order).
 enum { SORT_MODE_MOVE = 0, SORT_MODE_RANK = 1, SORT_MODE_PREP = 2 };
+constexpr int SORT_MAX_PASSES = 8;
 
 struct SortPass {
     int32_t shift;     // digit = (key >> shift) & 255
@@ -477,131 +482,122 @@ struct SortPass {
     int32_t src_sel;   // 0: sortA, 1: sortB
     int32_t mode;      // SORT_MODE_*
     int32_t rank_sel;  // MODE_RANK: x_{i+1} and its ranks go to X1/rankB (1) or X0/rankA (0)
+    int32_t pass;      // index of the pass within its sort (digit starts, tickets)
+    int32_t epoch;     // 1..3, different for consecutive passes (look-back words)
 };
 
-// grid: (ntiles, curves), block 256.  hist[d * ntiles + tile] = count of digit d.
-// All loads of a thread are issued before its counting.  Each wave counts
-// into HIST_COPIES LDS histograms, lane l into copy l mod HIST_COPIES, rows
-// padded to 257 words so that equal digits of different copies fall in
-// different banks: when a few digits dominate (the exponent byte of the
-// keys), fewer lanes of one atomic instruction collide.
-constexpr int HIST_COPIES = 4;
+// Look-back word of (tile, digit): bits 31-30 the pass's epoch, bits 29-28
+// the state (AGG: the tile's own count; PREFIX: the count of the digit in all
+// tiles up to and including this one), bits 27-0 the count (n <= 2^27).  A
+// word of another epoch (the previous pass, or zero from k_sort_clear) is not
+// ready.
+constexpr uint32_t LOOK_AGG = 1u << 28;
+constexpr uint32_t LOOK_PREFIX = 2u << 28;
+constexpr uint32_t LOOK_COUNT = (1u << 28) - 1;
+// A look-back wait that exceeds this many polls gives up (state[3] = 1) rather
+// than spin on; the waited-for tile has a ticket, so it is running and
+// publishes within microseconds.
+constexpr int LOOK_SPIN_MAX = 1 << 18;
 
+AGN_DEV uint32_t look_load(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+AGN_DEV void look_store(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Zero the look-back words, digit totals and tickets of every curve (once
+// per call, before its first sort).  grid: (ntiles, curves), block 256.
+__global__ __launch_bounds__(BIG_THREADS) void k_sort_clear(const BigCurve* __restrict__ cv) {
+    const BigCurve& d = cv[blockIdx.y];
+    const int tid = threadIdx.x;
+    d.look[(int64_t)blockIdx.x * 256 + tid] = 0u;
+    if (blockIdx.x == 0) {
+        for (int i = tid; i < SORT_MAX_PASSES * 256; i += BIG_THREADS) d.dcount[i] = 0u;
+        if (tid < SORT_MAX_PASSES) d.tickets[tid] = 0u;
+    }
+}
+
+// Digit totals of every pass of one sort, from its input keys (a pass only
+// permutes the keys, so each pass's digit counts are those of the input).
+// grid: (workgroups per curve, curves), block 256; workgroup x takes tiles
+// x, x + gridDim.x, ...  Each wave counts into COPIES LDS histograms per pass,
+// lane l into copy l mod COPIES, rows padded to 257 words so that equal
+// digits of different copies fall in different banks (the exponent byte is
+// dominated by a few values); totals go to dcount by one global atomic add
+// per (pass, digit) and workgroup.
 template <typename K, int TILE>
-__global__ __launch_bounds__(BIG_THREADS) void k_sort_hist(const BigCurve* __restrict__ cv, SortPass P,
-                                                           int64_t ntiles) {
+__global__ __launch_bounds__(BIG_THREADS) void k_sort_count(const BigCurve* __restrict__ cv, int src_sel,
+                                                            int64_t ntiles) {
+    constexpr int NP = (int)sizeof(K);
+    constexpr int COPIES = 16 / NP;
+    constexpr int WAVES = BIG_THREADS / 64;
+    constexpr int ROWS = WAVES * COPIES;
     constexpr int IPT = TILE / BIG_THREADS;
-    constexpr int ROWS = BIG_THREADS / 64 * HIST_COPIES;
-    __shared__ uint32_t h[ROWS * 257];
+    __shared__ uint32_t h[NP * ROWS * 257];
     const BigCurve& d = cv[blockIdx.y];
     if (d.state[1] == 0) return;
     const int tid = threadIdx.x, wave = tid >> 6;
-    const K* keys = (const K*)(P.src_sel ? d.sortB : d.sortA);
-    const int64_t base = (int64_t)blockIdx.x * TILE;
-    K k[IPT];
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) k[i] = keys[base + i * BIG_THREADS + tid];
-#pragma unroll
-    for (int w = 0; w < ROWS; ++w) h[w * 257 + tid] = 0;
+    for (int i = tid; i < NP * ROWS * 257; i += BIG_THREADS) h[i] = 0u;
     __syncthreads();
-    uint32_t* mine = h + (wave * HIST_COPIES + (tid & (HIST_COPIES - 1))) * 257;
+    const K* keys = (const K*)(src_sel ? d.sortB : d.sortA);
+    uint32_t* mine = h + (wave * COPIES + (tid % COPIES)) * 257;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t base = t * TILE + tid;
+        K k[IPT];
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) atomicAdd(&mine[(uint32_t)(k[i] >> P.shift) & 255u], 1u);
+        for (int i = 0; i < IPT; ++i) k[i] = keys[base + i * BIG_THREADS];
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p) atomicAdd(&mine[p * ROWS * 257 + ((uint32_t)(k[i] >> (8 * p)) & 255u)], 1u);
+        }
+    }
     __syncthreads();
-    uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < ROWS; ++w) c += h[w * 257 + tid];
-    d.hist[(int64_t)tid * ntiles + blockIdx.x] = c;
+    for (int p = 0; p < NP; ++p) {
+        uint32_t c = 0;
+        for (int r = 0; r < ROWS; ++r) c += h[(p * ROWS + r) * 257 + tid];
+        if (c) atomicAdd(&d.dcount[p * 256 + tid], c);
+    }
 }
 
-// grid: (256, curves), block 256: exclusive scan of one digit's tile counts,
-// in place; the digit total goes to dstart[d] (turned into starts below).
-__global__ __launch_bounds__(BIG_THREADS) void k_sort_scan_rows(const BigCurve* __restrict__ cv,
-                                                                int64_t ntiles) {
-    __shared__ uint32_t sh[8];
-    const BigCurve& d = cv[blockIdx.y];
+// Digit starts of every pass (exclusive scans of the totals); clears the
+// totals and the tickets for the next sort.  grid: (curves), block 256.
+__global__ __launch_bounds__(BIG_THREADS) void k_sort_starts(const BigCurve* __restrict__ cv, int npass) {
+    __shared__ uint32_t sh[4];
+    const BigCurve& d = cv[blockIdx.x];
     if (d.state[1] == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    uint32_t* row = d.hist + (int64_t)blockIdx.x * ntiles;
-    uint32_t carry = 0;
-    for (int64_t b0 = 0; b0 < ntiles; b0 += BIG_THREADS) {
-        const int64_t i = b0 + tid;
-        const uint32_t v = (i < ntiles) ? row[i] : 0u;
+    for (int p = 0; p < npass; ++p) {
+        const uint32_t v = d.dcount[p * 256 + tid];
         uint32_t inc = v;
 #pragma unroll
-        for (int s = 1; s < 64; s <<= 1) {
-            const uint32_t o = __shfl_up(inc, s, 64);
-            if (lane >= s) inc += o;
+        for (int s2 = 1; s2 < 64; s2 <<= 1) {
+            const uint32_t o = __shfl_up(inc, s2, 64);
+            if (lane >= s2) inc += o;
         }
         if (lane == 63) sh[wave] = inc;
         __syncthreads();
         uint32_t wpre = 0;
         for (int w = 0; w < wave; ++w) wpre += sh[w];
-        const uint32_t tot = sh[0] + sh[1] + sh[2] + sh[3];
-        if (i < ntiles) row[i] = carry + wpre + inc - v;
-        carry += tot;
+        d.dstart[p * 256 + tid] = wpre + inc - v;
+        d.dcount[p * 256 + tid] = 0u;
         __syncthreads();
     }
-    if (tid == 0) d.dstart[blockIdx.x] = carry;
-}
-
-// Curves of at most SCAN_SMALL_TILES tiles: both scans in one launch.  grid:
-// (curves), block 256; thread d scans digit d's row of tile counts in place,
-// then the digit totals are scanned across the block into dstart.
-constexpr int64_t SCAN_SMALL_TILES = 128;
-
-__global__ __launch_bounds__(BIG_THREADS) void k_sort_scan_small(const BigCurve* __restrict__ cv, int64_t ntiles) {
-    __shared__ uint32_t sh[8];
-    const BigCurve& d = cv[blockIdx.x];
-    if (d.state[1] == 0) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    uint32_t* row = d.hist + (int64_t)tid * ntiles;
-    uint32_t v = 0;
-    for (int64_t i = 0; i < ntiles; ++i) {
-        const uint32_t c = row[i];
-        row[i] = v;
-        v += c;
-    }
-    uint32_t inc = v;
-#pragma unroll
-    for (int s = 1; s < 64; s <<= 1) {
-        const uint32_t o = __shfl_up(inc, s, 64);
-        if (lane >= s) inc += o;
-    }
-    if (lane == 63) sh[wave] = inc;
-    __syncthreads();
-    uint32_t wpre = 0;
-    for (int w = 0; w < wave; ++w) wpre += sh[w];
-    d.dstart[tid] = wpre + inc - v;
-}
-
-// grid: (curves), block 256: digit totals -> exclusive digit starts.
-__global__ __launch_bounds__(BIG_THREADS) void k_sort_scan_digits(const BigCurve* __restrict__ cv) {
-    __shared__ uint32_t sh[8];
-    const BigCurve& d = cv[blockIdx.x];
-    if (d.state[1] == 0) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t v = d.dstart[tid];
-    uint32_t inc = v;
-#pragma unroll
-    for (int s = 1; s < 64; s <<= 1) {
-        const uint32_t o = __shfl_up(inc, s, 64);
-        if (lane >= s) inc += o;
-    }
-    if (lane == 63) sh[wave] = inc;
-    __syncthreads();
-    uint32_t wpre = 0;
-    for (int w = 0; w < wave; ++w) wpre += sh[w];
-    __syncthreads();
-    d.dstart[tid] = wpre + inc - v;
+    if (tid < SORT_MAX_PASSES) d.tickets[tid] = 0u;
 }
 
 // grid: (ntiles, curves), block TILE / scat_ipt<K>.  Stable scatter of one
-// 8-bit digit.  Each wave ranks its 64 x SCAT_IPT keys with ballots and per-wave
-// running digit counters; the tile is then rearranged in LDS into digit order,
-// and thread q takes tile positions q, q + SCAT_THREADS, ... so that
-// consecutive threads write consecutive global positions inside each digit's
-// run (runs of TILE / 256 keys on average).
+// 8-bit digit.  A workgroup takes the next tile of its curve in ticket order
+// (so every tile it may wait for is already running).  Each wave ranks its
+// 64 x SCAT_IPT keys with ballots and per-wave running digit counters; the
+// tile publishes its digit counts (AGG), then thread d walks back over the
+// look-back words of digit d of the tiles before it, adding AGG counts until
+// it meets a PREFIX, and publishes its own PREFIX.  The tile is then
+// rearranged in LDS into digit order, and thread q takes tile positions q,
+// q + SCAT_THREADS, ... so that consecutive threads write consecutive global
+// positions inside each digit's run (runs of TILE / 256 keys on average).
 template <typename K, int TILE>
 __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(const BigCurve* __restrict__ cv,
                                                                             SortPass P, int64_t ntiles) {
@@ -614,6 +610,7 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
     __shared__ uint32_t tstart[256];            // digit start inside the tile
     __shared__ uint32_t gbase[256];             // global start of the tile's digit run
     __shared__ uint32_t wtot[4];                // digit-scan totals of the first four waves
+    __shared__ uint32_t s_tile;                 // ticket
     __shared__ K skey[TILE];
     __shared__ uint32_t sval[TILE];
     static_assert(64 * SCAT_IPT * (SCAT_WAVES - 1) < 65536, "wave prefix must fit 16 bits");
@@ -622,14 +619,15 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
     if (d.state[1] == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n = d.n;
-    const int64_t tile = blockIdx.x;
+    if (tid == 0) s_tile = atomicAdd(&d.tickets[P.pass], 1u);
+    for (int q = lane; q < 256; q += 64) wcnt[wave][q] = 0;
+    __syncthreads();
+    const int64_t tile = s_tile;
+    if (tile >= ntiles) return;  // (never: one ticket per workgroup)
     const int64_t base = tile * TILE + (int64_t)wave * 64 * SCAT_IPT;
     const unsigned char* srcb = P.src_sel ? d.sortB : d.sortA;
     const K* skeys = (const K*)srcb;
     const uint32_t* svals = (const uint32_t*)(srcb + (size_t)n * sizeof(K));
-
-    for (int q = lane; q < 256; q += 64) wcnt[wave][q] = 0;
-    __syncthreads();
 
     K key[SCAT_IPT];
     uint32_t val[SCAT_IPT];
@@ -641,7 +639,10 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
         val[i] = P.first ? (uint32_t)p : svals[p];
     }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    volatile uint16_t* vc = wcnt[wave];
+    // LDS-typed, so that the counter traffic compiles to ds_ instructions
+    // (a volatile generic pointer becomes coherent flat loads and stores)
+    volatile __attribute__((address_space(3))) uint16_t* vc =
+        (volatile __attribute__((address_space(3))) uint16_t*)wcnt[wave];
 #pragma unroll
     for (int i = 0; i < SCAT_IPT; ++i) {
         const uint32_t dg = (uint32_t)(key[i] >> P.shift) & 255u;
@@ -671,6 +672,8 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
             run += c;
         }
         tot = run;
+        // publish this tile's count of digit q (tile 0: its prefix)
+        look_store(&d.look[tile * 256 + q], ((uint32_t)P.epoch << 30) | (tile == 0 ? LOOK_PREFIX : LOOK_AGG) | tot);
         inc = tot;
 #pragma unroll
         for (int s2 = 1; s2 < 64; s2 <<= 1) {
@@ -685,7 +688,28 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
         uint32_t pre = 0;
         for (int w = 0; w < wave; ++w) pre += wtot[w];
         tstart[q] = pre + inc - tot;
-        gbase[q] = d.dstart[q] + d.hist[(int64_t)q * ntiles + tile];
+        // decoupled look-back: count of digit q in the tiles before this one
+        const uint32_t ep = (uint32_t)P.epoch << 30;
+        uint32_t excl = 0;
+        if (tile > 0) {
+            int64_t j = tile - 1;
+            int polls = 0;
+            while (j >= 0) {
+                const uint32_t w = look_load(&d.look[j * 256 + q]);
+                if ((w & 0xC0000000u) == ep && (w & (LOOK_AGG | LOOK_PREFIX))) {
+                    excl += w & LOOK_COUNT;
+                    if (w & LOOK_PREFIX) break;
+                    --j;
+                } else if (++polls > LOOK_SPIN_MAX) {
+                    d.state[3] = 1;
+                    break;
+                } else {
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            look_store(&d.look[tile * 256 + q], ep | LOOK_PREFIX | (excl + tot));
+        }
+        gbase[q] = d.dstart[P.pass * 256 + q] + excl;
     }
     __syncthreads();
 #pragma unroll
@@ -707,6 +731,7 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
         const uint32_t v = sval[q];
         const uint32_t dg = (uint32_t)(k >> P.shift) & 255u;
         const uint32_t dest = gbase[dg] + (uint32_t)q - tstart[dg];
+        if (dest >= (uint32_t)n) continue;  // (never, unless a look-back wait gave up)
         if (P.mode == SORT_MODE_MOVE) {
             dkeys[dest] = k;
             dvals[dest] = v;
@@ -737,13 +762,14 @@ __global__ __launch_bounds__(BIG_THREADS) void k_big_prep_keys(const BigCurve* _
     if (__syncthreads_or(bad) && threadIdx.x == 0) atomicAnd(&d.state[0], 0);
 }
 
-// State init: valid = 1, active = 1, done = 0.  grid: (curves), block 64.
+// State init: valid = 1, active = 1, done = 0, no look-back wait given up.  grid: (curves), block 64.
 __global__ void k_big_init(const BigCurve* __restrict__ cv) {
     const BigCurve& d = cv[blockIdx.x];
     if (threadIdx.x == 0) {
         d.state[0] = 1;
         d.state[1] = 1;
         d.state[2] = 0;
+        d.state[3] = 0;
     }
 }
 
@@ -802,7 +828,7 @@ __global__ __launch_bounds__(BIG_THREADS) void k_big_output(const BigCurve* __re
         if (d.rank_out) d.rank_out[p] = r[p];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (d.iters_done) *d.iters_done = d.state[0] ? done : -1;
+        if (d.iters_done) *d.iters_done = d.state[3] ? -2 : (d.state[0] ? done : -1);
         if (d.delta_out)
             for (int j = done; j < d.iters; ++j) d.delta_out[j] = 0.0;
     }
