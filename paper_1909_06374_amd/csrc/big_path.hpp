@@ -210,9 +210,9 @@ __global__ __launch_bounds__(1024) void k_fft_pass(const BigCurve* __restrict__ 
     // r_k = tid / C + k (nt / C); its twiddle W_N^{b r_k}, b = (j0m + c) N / (Ns R),
     // is W_N^{b r_0} (W_N^{b nt / C})^k, formed by FP64 products (at most
     // E - 1 of them, a few ulp of FP64) and rounded once to T.
-    const cplx<T>* src = (const cplx<T>*)(P.src_sel ? d.sortB : d.sortA);
-    const double* xc = P.x_sel ? d.X1 : d.X0;
-    const double* xp = P.x_sel ? d.X0 : d.X1;
+    const gmem<cplx<T>>* src = as_global((const cplx<T>*)(P.src_sel ? d.sortB : d.sortA));
+    const gmem<cplx<double>>* xc = as_global((const cplx<double>*)(P.x_sel ? d.X1 : d.X0));
+    const gmem<cplx<double>>* xp = as_global((const cplx<double>*)(P.x_sel ? d.X0 : d.X1));
     double acc = 0.0;
     uint32_t chg = 0;
     const int c_t = tid % C, r_t = tid / C, dr = nt / C;
@@ -234,15 +234,15 @@ __global__ __launch_bounds__(1024) void k_fft_pass(const BigCurve* __restrict__ 
             const int r = r_t + (h * (E / 2) + u) * dr;
             const int64_t m = j0 + c_t + (int64_t)r * MR;
             if (P.in_mode == 1) {
-                const double2 a = *(const double2*)(xc + 2 * m);
+                const cplx<double> a = gload(xc + m);  // x[2m], x[2m + 1]
                 if (P.with_delta) {
-                    const double2 b = *(const double2*)(xp + 2 * m);
-                    if (a.x != b.x) { const double l = log10(a.x / b.x); acc += l * l; ++chg; }
-                    if (a.y != b.y) { const double l = log10(a.y / b.y); acc += l * l; ++chg; }
+                    const cplx<double> b = gload(xp + m);
+                    if (a.re != b.re) { const double l = log10(a.re / b.re); acc += l * l; ++chg; }
+                    if (a.im != b.im) { const double l = log10(a.im / b.im); acc += l * l; ++chg; }
                 }
-                v[u] = cmk((T)a.x, (T)a.y);
+                v[u] = cmk((T)a.re, (T)a.im);
             } else {
-                v[u] = src[m];
+                v[u] = gload(src + m);
             }
         }
 #pragma unroll
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(1024) void k_fft_pass(const BigCurve* __restrict__ 
 
     // Write outputs: butterfly j = j0 + c, output q goes to (j - jm) R + jm + q Ns.
     if (P.out_mode == 1) {
-        K* keys = (K*)(P.dst_sel ? d.sortB : d.sortA);
+        gmem<K>* keys = as_global((K*)(P.dst_sel ? d.sortB : d.sortA));
         for (int e = tid; e < R * C; e += nt) {
             int q, c;
             if (Ns == 1) { c = e / R; q = e % R; } else { q = e / C; c = e % C; }
@@ -295,13 +295,13 @@ __global__ __launch_bounds__(1024) void k_fft_pass(const BigCurve* __restrict__ 
             keys[2 * m + 1] = ord_key(v.im);
         }
     } else {
-        cplx<T>* dst = (cplx<T>*)(P.dst_sel ? d.sortB : d.sortA);
+        gmem<cplx<T>>* dst = as_global((cplx<T>*)(P.dst_sel ? d.sortB : d.sortA));
         for (int e = tid; e < R * C; e += nt) {
             int q, c;
             if (Ns == 1) { c = e / R; q = e % R; } else { q = e / C; c = e % C; }
             const int64_t jm = (Ns > 1) ? j0m + c : 0;
             const int64_t m = (j0 + c - jm) * R + jm + (int64_t)q * Ns;
-            dst[m] = buf[tpad<T>(q * C + c)];
+            gstore(dst + m, buf[tpad<T>(q * C + c)]);
         }
     }
 }
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(1024) void k_fft_mid(const BigCurve* __restrict__ c
     if constexpr (MODE != MID_UNFOLD) {
         // Load the columns; element (r, slot) takes the last forward pass's
         // twiddle W_M^{j r} = W_N^{2 j r}, formed in FP64 as in k_fft_pass.
-        const cplx<T>* src = (const cplx<T>*)(P.src_sel ? d.sortB : d.sortA);
+        const gmem<cplx<T>>* src = as_global((const cplx<T>*)(P.src_sel ? d.sortB : d.sortA));
         const int c_t = tid % C2, r_t = tid / C2, dr = nt / C2;
         const int64_t jc = col_of(c_t);
         cplx<double> wk = tw64(tb, 2 * jc * r_t);
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(1024) void k_fft_mid(const BigCurve* __restrict__ c
 #pragma unroll
             for (int u = 0; u < E / 2; ++u) {
                 const int r = r_t + (h * (E / 2) + u) * dr;
-                v[u] = src[jc + (int64_t)r * MR];
+                v[u] = gload(src + jc + (int64_t)r * MR);
             }
 #pragma unroll
             for (int u = 0; u < E / 2; ++u) {
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(1024) void k_fft_mid(const BigCurve* __restrict__ c
     // Hermitian pairs.  Item e < R C: primary element (q, s); block 0 adds
     // R/2 items for the self-paired column M/R/2 in slot C.  Each pair is
     // taken once, with ka = its index <= M/2 (the fold's convention).
-    const T* amp = (const T*)d.amp;
+    const gmem<T>* amp = as_global((const T*)d.amp);
     const int items = R * C + (j0 == 0 ? R / 2 : 0);
     for (int e = tid; e < items; e += nt) {
         int qa, sa, qb, sb;
@@ -460,10 +460,10 @@ __global__ __launch_bounds__(1024) void k_fft_mid(const BigCurve* __restrict__ c
     // The inverse transform's first pass: length-R DFTs of the columns (no
     // twiddles), column j's outputs to z[j R + q].
     col_fft<T, E, true, C2>(buf, wr, R, P.sub, tid, nt);
-    cplx<T>* dst = (cplx<T>*)(P.dst_sel ? d.sortB : d.sortA);
+    gmem<cplx<T>>* dst = as_global((cplx<T>*)(P.dst_sel ? d.sortB : d.sortA));
     for (int e = tid; e < R * C2; e += nt) {
         const int sl = e / R, q = e % R;
-        dst[col_of(sl) * R + q] = buf[tpad<T>(q * C2 + sl)];
+        gstore(dst + col_of(sl) * R + q, buf[tpad<T>(q * C2 + sl)]);
     }
 }
 
@@ -626,8 +626,8 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
     if (tile >= ntiles) return;  // (never: one ticket per workgroup)
     const int64_t base = tile * TILE + (int64_t)wave * 64 * SCAT_IPT;
     const unsigned char* srcb = P.src_sel ? d.sortB : d.sortA;
-    const K* skeys = (const K*)srcb;
-    const uint32_t* svals = (const uint32_t*)(srcb + (size_t)n * sizeof(K));
+    const gmem<K>* skeys = as_global((const K*)srcb);
+    const gmem<uint32_t>* svals = as_global((const uint32_t*)(srcb + (size_t)n * sizeof(K)));
 
     K key[SCAT_IPT];
     uint32_t val[SCAT_IPT];
@@ -721,10 +721,12 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
     }
     __syncthreads();
     unsigned char* dstb = P.src_sel ? d.sortA : d.sortB;
-    K* dkeys = (K*)dstb;
-    uint32_t* dvals = (uint32_t*)(dstb + (size_t)n * sizeof(K));
-    uint32_t* rnk = P.rank_sel ? d.rankB : d.rankA;
-    double* xn = P.rank_sel ? d.X1 : d.X0;
+    gmem<K>* dkeys = as_global((K*)dstb);
+    gmem<uint32_t>* dvals = as_global((uint32_t*)(dstb + (size_t)n * sizeof(K)));
+    gmem<uint32_t>* rnk = as_global(P.rank_sel ? d.rankB : d.rankA);
+    gmem<double>* xn = as_global(P.rank_sel ? d.X1 : d.X0);
+    gmem<double>* s64 = as_global(d.s64);
+    const gmem<double>* x0 = as_global(d.x0);
 #pragma unroll 4
     for (int q = tid; q < TILE; q += SCAT_THREADS) {
         const K k = skey[q];
@@ -736,10 +738,10 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
             dkeys[dest] = k;
             dvals[dest] = v;
         } else if (P.mode == SORT_MODE_RANK) {
-            xn[v] = d.s64[dest];
+            xn[v] = s64[dest];
             if (d.rank_out) rnk[v] = dest;
         } else {
-            d.s64[dest] = d.x0[v];
+            s64[dest] = x0[v];
             rnk[v] = dest;
         }
     }

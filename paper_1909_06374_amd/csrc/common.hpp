@@ -43,6 +43,31 @@ AGN_DEV int opaque(int x) {
     return x;
 }
 
+// Global-memory pointers typed as such.  Through a generic pointer the
+// compiler emits flat loads, which count against both the vector-memory and
+// the LDS counters, so every wait for LDS traffic also waits for them; typed
+// global loads are counted by the vector-memory counter alone.
+template <typename T> using gmem = __attribute__((address_space(1))) T;
+template <typename T> AGN_DEV const gmem<T>* as_global(const T* p) { return (const gmem<T>*)p; }
+template <typename T> AGN_DEV gmem<T>* as_global(T* p) { return (gmem<T>*)p; }
+
+// Complex values through typed global pointers, as one 2-element vector load
+// or store (a struct cannot be copied out of another address space).
+template <typename T> struct vec2_of { typedef T type __attribute__((ext_vector_type(2))); };
+template <typename T> AGN_DEV cplx<T> gload(const gmem<cplx<T>>* p) {
+    const typename vec2_of<T>::type v = *(const gmem<typename vec2_of<T>::type>*)p;
+    cplx<T> r;
+    r.re = v.x;
+    r.im = v.y;
+    return r;
+}
+template <typename T> AGN_DEV void gstore(gmem<cplx<T>>* p, cplx<T> a) {
+    typename vec2_of<T>::type v;
+    v.x = a.re;
+    v.y = a.im;
+    *(gmem<typename vec2_of<T>::type>*)p = v;
+}
+
 template <typename T> struct key_of;
 template <> struct key_of<float> { typedef uint32_t type; };
 template <> struct key_of<double> { typedef uint64_t type; };

@@ -284,8 +284,8 @@ AGN_DEV cplx<T> fold_dc(cplx<T> z0, cplx<T> w0, T amp_n) {
     return cmk(yn, -yn);
 }
 
-template <typename T>
-AGN_DEV void lds_fold_replace(cplx<T>* Z, int M, const T* __restrict__ amp, const TwLds& tw, int tid,
+template <typename T, typename AmpPtr>
+AGN_DEV void lds_fold_replace(cplx<T>* Z, int M, AmpPtr __restrict__ amp, const TwLds& tw, int tid,
                               int nthreads) {
     const int half = M / 2;
     for (int k = tid; k <= half; k += nthreads) {
@@ -314,8 +314,8 @@ AGN_DEV void lds_fold_replace(cplx<T>* Z, int M, const T* __restrict__ amp, cons
 // no barrier is needed between the reads and the writes.  The operations are
 // those of the separate pass and fold (the compiler may fuse multiply-adds
 // differently, so results can differ in the last bit).  Needs M >= 16.
-template <typename T>
-AGN_DEV void lds_fold_replace_r2(cplx<T>* Z, int M, const T* __restrict__ amp, const TwLds& tw, int tid,
+template <typename T, typename AmpPtr>
+AGN_DEV void lds_fold_replace_r2(cplx<T>* Z, int M, AmpPtr __restrict__ amp, const TwLds& tw, int tid,
                                  int nt) {
     const int h = M / 2, q = M / 4;
     for (int k = tid; k <= q; k += nt) {

@@ -303,17 +303,18 @@ AGN_DEV void lds_iterate_curve(const LcDesc& d, unsigned char* smem, int tid, in
     uint32_t* scratch = (uint32_t*)(smem + sc_off);
     double* dscratch = (double*)(smem + sc_off + 128 * 4);
 
-    const T* __restrict__ amp = (const T*)d.amp;
-    const T* __restrict__ sT = (const T*)d.sT;
-    const double* __restrict__ s64 = d.s64;
-    const double* __restrict__ L = d.L;
+    const gmem<T>* __restrict__ amp = as_global((const T*)d.amp);
+    const gmem<T>* __restrict__ sT = as_global((const T*)d.sT);
+    const gmem<double>* __restrict__ s64 = as_global(d.s64);
+    const gmem<double>* __restrict__ L = as_global(d.L);
+    const gmem<uint32_t>* __restrict__ rank0 = as_global(d.rank0);
     const TwLds tw = lds_load_twiddles(smem + tw_off, (const cplx<double>*)d.tw, N, tid, nt);
     const FftPlan& plan = d.plan;  // read in place (uniform loads), not copied to private memory
 
 #pragma unroll 4
     for (int u = 0; u < IPT; ++u) {
         const int p = u * nt + tid;
-        const uint32_t r = d.rank0[p];
+        const uint32_t r = rank0[p];
         rank16[p] = (uint16_t)r;
         Zf[rpad<T>(p)] = sT[r];
     }
