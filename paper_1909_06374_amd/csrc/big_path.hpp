@@ -340,7 +340,18 @@ struct MidPass {
     const double* Y_in;  // MID_UNFOLD: n/2 + 1 complex doubles
 };
 
+// Workgroups are dealt to the 8 XCDs in turn (workgroup x of a launch whose
+// row count is a multiple of 8 runs on XCD x mod 8).  xcd_order numbers the
+// rows so that consecutive numbers run on one XCD, one after another.
+AGN_DEV int64_t xcd_order(int64_t x, int64_t rows) {
+    return (rows & 7) ? x : (x & 7) * (rows >> 3) + (x >> 3);
+}
+
 // grid: (M / R / (2 C), curves), block P.nthreads (E = 2 R C / nthreads).
+// Column block b = xcd_order(x): a row of 8 columns is 64 bytes (FP32) and
+// its 8 target moduli 32 bytes, so two and four neighbouring blocks share
+// each cache line; numbered this way, they run on one XCD at about the same
+// time and find the line in its L2 instead of each fetching it.
 template <typename T, int E, int C, int MODE>
 __global__ __launch_bounds__(1024) void k_fft_mid(const BigCurve* __restrict__ cv, MidPass P, TwTable tb) {
     constexpr int C2 = 2 * C;
@@ -350,7 +361,7 @@ __global__ __launch_bounds__(1024) void k_fft_mid(const BigCurve* __restrict__ c
     const int tid = threadIdx.x, nt = blockDim.x;
     const int R = P.R;
     const int64_t M = P.M, N = 2 * M, MR = M / R;
-    const int64_t j0 = (int64_t)blockIdx.x * C;
+    const int64_t j0 = xcd_order(blockIdx.x, gridDim.x) * C;
     cplx<T>* buf = (cplx<T>*)smem;
     cplx<T>* wr = (cplx<T>*)(smem + (size_t)tpad<T>(R * C2 + 1) * sizeof(cplx<T>) + 16);
     for (int u = tid; u < R; u += nt) wr[u] = to_T<T>(tw64(tb, (int64_t)u * (N / R)));
