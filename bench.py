@@ -90,10 +90,12 @@ def recorded_valu(workload, kernel):
 
 def lds_flops_per_sample_iter(n):
     """FP32 flops per sample-iteration of the LDS-resident kernel counted
-    algorithmically: two complex FFTs of length N/2 at 5 (N/2) log2(N/2) flops
-    each, plus about 40 flops per Hermitian pair for the fold, the modulus
-    replacement and the unfold (20 per real sample)."""
-    return 5.0 * math.log2(n // 2) + 20.0
+    algorithmically: the forward and the inverse real transform at
+    2.5 N log2 N flops each, i.e. 5 log2 N per sample (70 at N = 2^14).  The
+    modulus replacement (about 20 flops per sample) and the sort (integer
+    work) are not counted, so the fraction understates how busy the kernel
+    is; the LDS and VALU-issue views beside it say more."""
+    return 5.0 * math.log2(n)
 
 
 def lds_bytes_per_sample_iter(n, prec_bytes):

@@ -65,7 +65,7 @@ struct BigCurve {
     double* X1;            // [N] x_i for odd i
     uint32_t* rankA;       // [N] ranks of x_i, even i (kept only if rank_out)
     uint32_t* rankB;       // [N] ranks of x_i, odd i
-    unsigned char* sortA;  // N * 12 bytes: keys, then 32-bit values
+    unsigned char* sortA;  // N * 12 bytes: 64-bit keys then 32-bit values, or 8-byte key/index records
     unsigned char* sortB;
     uint32_t* look;        // ntiles * 256 look-back words of the sort scatter
     uint32_t* dcount;      // [SORT_MAX_PASSES][256] digit totals of one sort (accumulated)
@@ -486,6 +486,12 @@ __global__ __launch_bounds__(1024) void k_fft_mid(const BigCurve* __restrict__ c
 // wave ranks its items in position order).
 enum { SORT_MODE_MOVE = 0, SORT_MODE_RANK = 1, SORT_MODE_PREP = 2 };
 constexpr int SORT_MAX_PASSES = 8;
+// Between passes, 32-bit keys travel with their sample index as one 8-byte
+// record (key << 32 | index): one load and one store per key, and a digit
+// run is one contiguous run of records rather than one run in each of two
+// arrays.  64-bit keys keep separate key and index arrays (a 12-byte record
+// would straddle lines).  The first pass reads bare keys (index implicit).
+template <typename K> constexpr bool SORT_AOS = sizeof(K) == 4;
 
 struct SortPass {
     int32_t shift;     // digit = (key >> shift) & 255
@@ -643,11 +649,21 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
     K key[SCAT_IPT];
     uint32_t val[SCAT_IPT];
     uint32_t loc[SCAT_IPT];
+    if (SORT_AOS<K> && !P.first) {
+        const gmem<uint64_t>* srec = as_global((const uint64_t*)srcb);
 #pragma unroll
-    for (int i = 0; i < SCAT_IPT; ++i) {
-        const int64_t p = base + i * 64 + lane;
-        key[i] = skeys[p];
-        val[i] = P.first ? (uint32_t)p : svals[p];
+        for (int i = 0; i < SCAT_IPT; ++i) {
+            const uint64_t r = srec[base + i * 64 + lane];
+            key[i] = (K)(r >> 32);
+            val[i] = (uint32_t)r;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < SCAT_IPT; ++i) {
+            const int64_t p = base + i * 64 + lane;
+            key[i] = skeys[p];
+            val[i] = P.first ? (uint32_t)p : svals[p];
+        }
     }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     // LDS-typed, so that the counter traffic compiles to ds_ instructions
@@ -734,6 +750,7 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
     unsigned char* dstb = P.src_sel ? d.sortA : d.sortB;
     gmem<K>* dkeys = as_global((K*)dstb);
     gmem<uint32_t>* dvals = as_global((uint32_t*)(dstb + (size_t)n * sizeof(K)));
+    gmem<uint64_t>* drec = as_global((uint64_t*)dstb);
     gmem<uint32_t>* rnk = as_global(P.rank_sel ? d.rankB : d.rankA);
     gmem<double>* xn = as_global(P.rank_sel ? d.X1 : d.X0);
     gmem<double>* s64 = as_global(d.s64);
@@ -746,8 +763,12 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
         const uint32_t dest = gbase[dg] + (uint32_t)q - tstart[dg];
         if (dest >= (uint32_t)n) continue;  // (never, unless a look-back wait gave up)
         if (P.mode == SORT_MODE_MOVE) {
-            dkeys[dest] = k;
-            dvals[dest] = v;
+            if constexpr (SORT_AOS<K>) {
+                drec[dest] = ((uint64_t)k << 32) | v;
+            } else {
+                dkeys[dest] = k;
+                dvals[dest] = v;
+            }
         } else if (P.mode == SORT_MODE_RANK) {
             xn[v] = s64[dest];
             if (d.rank_out) rnk[v] = dest;
