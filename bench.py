@@ -127,18 +127,20 @@ def hbm_bytes_per_sample(kernel, prec_bytes):
     kernel.  FFT pass: read and write the N/2-point complex buffer (prec bytes
     per real sample each way; the first forward pass reads more, so this is a
     lower bound for the average launch).  Sort scatter (8-bit LSD, key of prec
-    bytes + 32-bit index): read key and index, write both; the last pass of a
-    sort instead reads the sorted value s[position] and writes x_{i+1}[sample]
-    (prec + 4 + 8 + 8 bytes), so the average over a sort's launches is
-    (16 x 3 + 24) / 4 = 18 bytes in the FP32 form and (24 x 7 + 28) / 8 =
-    24.5 in FP64.  Digit count (one launch per sort): read the key."""
+    bytes + 32-bit index): read key and index, write both; the first pass
+    reads the key alone (the index is the position); the last pass instead
+    reads the sorted value s[position] and writes x_{i+1}[sample].  Averaged
+    over a sort's launches: (12 + 16 + 16 + 24) / 4 = 17 bytes in the FP32
+    form, (20 + 6 x 24 + 28) / 8 = 24 in FP64.  Digit count (one launch per
+    sort): read the key."""
     if kernel == "fft_pass":
         return 2 * prec_bytes
     if kernel == "sort_scatter":
         npass = prec_bytes
         move = 2 * (prec_bytes + 4)
+        first = prec_bytes + prec_bytes + 4
         last = prec_bytes + 4 + 8 + 8
-        return (move * (npass - 1) + last) / npass
+        return (first + move * (npass - 2) + last) / npass
     if kernel == "sort_hist":
         return prec_bytes
     if kernel in ("fold", "fft_mid"):
@@ -662,15 +664,16 @@ def run_uneven(args, agn, synth, np, torch):
     }
     if dom == "sort_scatter":
         # algorithmic bytes of every scatter launch of the eager run: multi-pass
-        # curves only; per iteration 4 passes of 32-bit keys (18 bytes per key on
+        # curves only; per iteration 4 passes of 32-bit keys (17 bytes per key on
         # average), once 8 passes of the 64-bit draw keys (2 (8 + 4) bytes per key)
         big = [nn for nn in ns if not ((nn % 3 == 0 and nn <= 12288) or (nn % 3 != 0 and nn <= 16384))]
         byts = float(sum(big)) * (iters * 4 * hbm_bytes_per_sample("sort_scatter", 4) + 8 * 24)
         achieved = byts / (kt[dom][0] / 1000.0) / 1e9
         out["roofline"].update({"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                                "bytes": "18 per key per pass on average (FP32 keys; the last pass reads "
-                                         "s[position] and writes x), 24 for the one-time draw sort"})
+                                "bytes": "17 per key per pass on average (FP32 keys; the first pass reads the "
+                                         "key alone, the last reads s[position] and writes x), 24 for the one-time "
+                                         "draw sort"})
     if not args.no_cpu_baseline:
         import oracle
         # bounded sample: the first curves of the batch up to 2^21 samples, 3 iterations
@@ -736,7 +739,7 @@ def run_serving(args, agn, np, torch):
             "kernel_time_share": {k: round(v[0] / sum(u[0] for u in kt.values()), 4) for k, v in kt.items()},
             "note": "kernel times of a profiled repeat of the capacity run (all requests queued at once)"}
     if dom == "sort_scatter":
-        # multi-pass requests: per iteration 4 passes of 32-bit keys (18 bytes per
+        # multi-pass requests: per iteration 4 passes of 32-bit keys (17 bytes per
         # key on average), once 8 passes of the 64-bit draw keys (24 bytes per key)
         big = [r for r in cap_reqs if not ((r.n % 3 == 0 and r.n <= 12288) or (r.n % 3 != 0 and r.n <= 16384))]
         # (the draw keys are sorted once per segment)
