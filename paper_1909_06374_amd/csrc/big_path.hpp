@@ -769,12 +769,14 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
                 dkeys[dest] = k;
                 dvals[dest] = v;
             }
-        } else if (P.mode == SORT_MODE_RANK) {
-            xn[v] = s64[dest];
-            if (d.rank_out) rnk[v] = dest;
-        } else {
-            s64[dest] = x0[v];
-            rnk[v] = dest;
+        } else if (v < (uint32_t)n) {  // (always, unless a look-back wait gave up in an earlier pass)
+            if (P.mode == SORT_MODE_RANK) {
+                xn[v] = s64[dest];
+                if (d.rank_out) rnk[v] = dest;
+            } else {
+                s64[dest] = x0[v];
+                rnk[v] = dest;
+            }
         }
     }
 }
