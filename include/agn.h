@@ -375,6 +375,16 @@ int agn_periodogram_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n, cons
  * the launch stream. */
 int agn_ctx_set_profiling(agn_ctx* ctx, int on);
 
+/* For failure-handling tests of the multi-pass sort.  Each scatter workgroup
+ * of that sort waits, by polling, for the digit counts of the tiles before it
+ * (a decoupled look-back; those tiles are always running, so the wait ends
+ * within microseconds).  A wait that exceeds `polls` polls gives up: the
+ * curve's iters_done reads -2 and its x_out is not valid, but every store
+ * stays in bounds.  polls > 0 sets the limit, 0 restores the default
+ * (2^18), polls < 0 makes every wait give up at once.  Applies to calls and
+ * plans made with this context afterwards. */
+int agn_ctx_set_lookback_polls(agn_ctx* ctx, int32_t polls);
+
 /* Synchronises the recorded events and returns, for kernel `name` (one of the
  * names listed by agn_ctx_kernel_names), the summed duration in milliseconds
  * and the number of launches since the last reset; reset = 1 clears all

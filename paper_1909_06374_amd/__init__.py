@@ -117,13 +117,14 @@ def _declare(lib):
     lib.agn_periodogram_workspace_size.argtypes = [i32, vp, d, C.POINTER(sz)]
     lib.agn_periodogram_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, d, vp, vp, vp, sz, vp]
     lib.agn_ctx_set_profiling.argtypes = [vp, C.c_int]
+    lib.agn_ctx_set_lookback_polls.argtypes = [vp, i32]
     lib.agn_ctx_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(d), C.POINTER(i64), C.c_int]
     lib.agn_ctx_kernel_names.argtypes = []
     lib.agn_ctx_kernel_names.restype = C.c_char_p
     for f in ("agn_ctx_create", "agn_ctx_destroy", "agn_supported_n", "agn_spectrum_workspace_size",
               "agn_workspace_size", "agn_batch_workspace_size", "agn_psd_spectrum", "agn_psd_spectrum_noalloc",
               "agn_lc_iterate", "agn_lc_generate", "agn_lc_generate_batch", "agn_test_philox",
-              "agn_ctx_set_profiling", "agn_ctx_kernel_time", "agn_erdf_draw", "agn_pdf_draw", "agn_pdf_slice", "agn_batch_plan_create",
+              "agn_ctx_set_profiling", "agn_ctx_set_lookback_polls", "agn_ctx_kernel_time", "agn_erdf_draw", "agn_pdf_draw", "agn_pdf_slice", "agn_batch_plan_create",
               "agn_batch_plan_launch", "agn_batch_plan_info", "agn_batch_plan_tuning", "agn_batch_plan_destroy", "agn_log_bin_count",
               "agn_periodogram_workspace_size", "agn_periodogram_batch", "agn_lag_stats_workspace_size",
               "agn_lag_stats_batch", "agn_psd_fit_workspace_size", "agn_psd_fit_batch",
@@ -222,6 +223,11 @@ class Context:
 
     def set_profiling(self, on: bool):
         _check(lib().agn_ctx_set_profiling(self.handle, 1 if on else 0))
+
+    def set_lookback_polls(self, polls: int):
+        """Look-back wait limit of the multi-pass sort (0: default; < 0: every
+        wait gives up at once, for failure-handling tests)."""
+        _check(lib().agn_ctx_set_lookback_polls(self.handle, int(polls)))
 
     def kernel_times(self, reset: bool = True):
         """{kernel name: (total ms, launches)} of the launches timed so far."""

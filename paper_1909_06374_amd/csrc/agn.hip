@@ -203,6 +203,7 @@ struct agn_ctx {
     std::vector<StageSlot> ring;
     size_t ring_next = 0;
     std::map<std::string, std::array<int, 3>> tuned;  // batch signature -> (chains, sort tile, FFT cap) chosen by the autotuner
+    int look_polls = LOOK_SPIN_MAX;  // look-back wait limit of the multi-pass sort (< 0: give up at once)
 };
 
 static const char* KERNEL_NAMES =
@@ -347,6 +348,12 @@ extern "C" int agn_ctx_create(int device, agn_ctx** out) {
 extern "C" int agn_ctx_set_profiling(agn_ctx* ctx, int on) {
     if (!ctx) return fail(AGN_EINVAL, "ctx is NULL");
     ctx->prof = on != 0;
+    return AGN_OK;
+}
+
+extern "C" int agn_ctx_set_lookback_polls(agn_ctx* ctx, int32_t polls) {
+    if (!ctx) return fail(AGN_EINVAL, "ctx is NULL");
+    ctx->look_polls = polls == 0 ? LOOK_SPIN_MAX : polls;
     return AGN_OK;
 }
 
@@ -680,7 +687,7 @@ constexpr int SORT_COUNT_WORKGROUPS = 512;  // k_sort_count workgroups over all 
 
 template <typename K, int TILE>
 static void run_sort_t(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, int src0, int last_mode, int rank_sel,
-                       int* seq, hipStream_t st) {
+                       int* seq, int polls, hipStream_t st) {
     const int64_t ntiles = n / TILE;
     const int npass = (int)sizeof(K);
     {
@@ -704,6 +711,7 @@ static void run_sort_t(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, int s
         P.rank_sel = rank_sel;
         P.pass = p;
         P.epoch = (*seq)++ % 3 + 1;
+        P.spin_max = polls;
         ProfScope ps(ctx, "sort_scatter", st);
         hipLaunchKernelGGL((k_sort_scatter<K, TILE>), dim3((unsigned)ntiles, (unsigned)nc),
                            dim3(TILE / scat_ipt<K>::value), 0, st, d, P, ntiles);
@@ -719,14 +727,14 @@ static int sort_tile_for(int64_t n, int want) {
 
 template <typename K>
 static void run_sort(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, int src0, int last_mode, int rank_sel,
-                     int tile, int* seq, hipStream_t st) {
+                     int tile, int* seq, int polls, hipStream_t st) {
     if constexpr (sizeof(K) == 4) {
         if (sort_tile_for<K>(n, tile) == SORT_TILE_BIG) {
-            run_sort_t<K, SORT_TILE_BIG>(ctx, d, nc, n, src0, last_mode, rank_sel, seq, st);
+            run_sort_t<K, SORT_TILE_BIG>(ctx, d, nc, n, src0, last_mode, rank_sel, seq, polls, st);
             return;
         }
     }
-    run_sort_t<K, BIG_TILE>(ctx, d, nc, n, src0, last_mode, rank_sel, seq, st);
+    run_sort_t<K, BIG_TILE>(ctx, d, nc, n, src0, last_mode, rank_sel, seq, polls, st);
 }
 
 // Checks the multi-pass FFT plan of length n and resolves its twiddle table.
@@ -760,7 +768,7 @@ static int big_group_setup(agn_ctx* ctx, int64_t n, agn_precision prec, TwTable*
 // big_group_setup).  ctx may be NULL (no kernel timing, e.g. under capture).
 template <typename T>
 static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, int32_t max_iters,
-                          const TwTable& tb, const std::vector<int>& rad, int sort_tile, int fft_cap,
+                          const TwTable& tb, const std::vector<int>& rad, int sort_tile, int fft_cap, int polls,
                           hipStream_t st) {
     typedef typename key_of<T>::type K;
     const int64_t M = n / 2, ntiles = n / BIG_TILE;
@@ -771,7 +779,7 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
     {
         ProfScope ps(ctx, "big_prep", st);
         hipLaunchKernelGGL(k_big_prep_keys, gt, dim3(BIG_THREADS), 0, st, d);
-        run_sort<uint64_t>(nullptr, d, nc, n, 0, SORT_MODE_PREP, 0, BIG_TILE, &seq, st);
+        run_sort<uint64_t>(nullptr, d, nc, n, 0, SORT_MODE_PREP, 0, BIG_TILE, &seq, polls, st);
     }
     hipLaunchKernelGGL(k_big_after_prep, dim3((unsigned)nc), dim3(64), 0, st, d);
     const int np = (int)rad.size();
@@ -820,7 +828,7 @@ static void run_big_group(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, in
             sel = 1 - sel;
         }
         // keys are in region (1 - sel)
-        run_sort<K>(ctx, d, nc, n, 1 - sel, SORT_MODE_RANK, 1 - cur, sort_tile, &seq, st);
+        run_sort<K>(ctx, d, nc, n, 1 - sel, SORT_MODE_RANK, 1 - cur, sort_tile, &seq, polls, st);
     }
     {
         // delta of the last iteration for curves that ran all of them: the
@@ -884,6 +892,7 @@ struct agn_batch_plan {
     int branches = 1;                         // concurrent launch chains
     int sort_tile = BIG_TILE;                 // requested tile of 32-bit-key sorts (multi-pass curves)
     int fft_cap = FFT_COLS_MAX;               // most butterflies per multi-pass FFT workgroup
+    int look_polls = LOOK_SPIN_MAX;           // look-back wait limit (the context's, at plan build)
     int flags = 0;
     std::vector<hipStream_t> aux;             // chains 1..branches-1 (default priority)
     std::vector<hipEvent_t> ev;               // fork + one join event per chain
@@ -897,6 +906,7 @@ static int build_plan(agn_ctx* ctx, std::vector<CurveReq>& rq, double tol, agn_p
                       void* ws, size_t ws_bytes, hipStream_t st, agn_batch_plan& pl) {
     const int32_t nc = (int32_t)rq.size();
     pl.ctx = ctx;
+    pl.look_polls = ctx->look_polls;
     pl.prec = prec;
     if (nc == 0) return AGN_OK;
     size_t need = header_ws(nc);
@@ -1164,10 +1174,10 @@ static void enqueue_group(const agn_batch_plan& pl, agn_ctx* pctx, bool is_big, 
         const BigGroup& g = pl.big[k];
         if (pl.prec == AGN_FP32)
             run_big_group<float>(pctx, pl.d_bg + g.first, g.count, g.n, g.max_it, g.tb, g.rad, pl.sort_tile,
-                                 pl.fft_cap, st);
+                                 pl.fft_cap, pl.look_polls, st);
         else
             run_big_group<double>(pctx, pl.d_bg + g.first, g.count, g.n, g.max_it, g.tb, g.rad, pl.sort_tile,
-                                  pl.fft_cap, st);
+                                  pl.fft_cap, pl.look_polls, st);
     }
 }
 
@@ -2327,7 +2337,7 @@ static int test_run_big(agn_ctx* ctx, int mode, int64_t n, agn_precision prec, c
         hipLaunchKernelGGL((k_test_big_keys<T>), dim3(nb), dim3(256), 0, st, dv, n, in);
         int seq = 0;
         hipLaunchKernelGGL(k_sort_clear, dim3((unsigned)ntiles), dim3(BIG_THREADS), 0, st, dv);
-        run_sort<K>(ctx, dv, 1, n, 0, SORT_MODE_RANK, 1, BIG_TILE, &seq, st);
+        run_sort<K>(ctx, dv, 1, n, 0, SORT_MODE_RANK, 1, BIG_TILE, &seq, ctx->look_polls, st);
         return AGN_OK;
     }
     // The iteration's transforms: forward passes 0 .. np-2, then the middle

@@ -501,6 +501,7 @@ struct SortPass {
     int32_t rank_sel;  // MODE_RANK: x_{i+1} and its ranks go to X1/rankB (1) or X0/rankA (0)
     int32_t pass;      // index of the pass within its sort (digit starts, tickets)
     int32_t epoch;     // 1..3, different for consecutive passes (look-back words)
+    int32_t spin_max;  // polls before a look-back wait gives up; < 0: give up at once (tests)
 };
 
 // Look-back word of (tile, digit): bits 31-30 the pass's epoch, bits 29-28
@@ -513,7 +514,8 @@ constexpr uint32_t LOOK_PREFIX = 2u << 28;
 constexpr uint32_t LOOK_COUNT = (1u << 28) - 1;
 // A look-back wait that exceeds this many polls gives up (state[3] = 1) rather
 // than spin on; the waited-for tile has a ticket, so it is running and
-// publishes within microseconds.
+// publishes within microseconds.  (The context can lower the limit, or make
+// every wait give up at once, to exercise that path.)
 constexpr int LOOK_SPIN_MAX = 1 << 18;
 
 AGN_DEV uint32_t look_load(const uint32_t* p) {
@@ -718,7 +720,10 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
         // decoupled look-back: count of digit q in the tiles before this one
         const uint32_t ep = (uint32_t)P.epoch << 30;
         uint32_t excl = 0;
-        if (tile > 0) {
+        if (tile > 0 && P.spin_max < 0) {
+            d.state[3] = 1;  // forced give-up (failure-handling tests): excl stays 0
+            look_store(&d.look[tile * 256 + q], ep | LOOK_PREFIX | tot);
+        } else if (tile > 0) {
             int64_t j = tile - 1;
             int polls = 0;
             while (j >= 0) {
@@ -727,7 +732,7 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
                     excl += w & LOOK_COUNT;
                     if (w & LOOK_PREFIX) break;
                     --j;
-                } else if (++polls > LOOK_SPIN_MAX) {
+                } else if (++polls > P.spin_max) {
                     d.state[3] = 1;
                     break;
                 } else {
