@@ -131,7 +131,8 @@ class Server:
     """Continuous-batching scheduler with HBM-footprint admission."""
 
     def __init__(self, backend: Backend, budget_bytes: int, max_batch_samples: int = 2**26,
-                 max_batch_curves: int = 4096, segment_iters: Optional[int] = None):
+                 max_batch_curves: int = 4096, segment_iters: Optional[int] = None,
+                 segment_always: bool = False):
         self.be = backend
         self.budget = int(budget_bytes)
         self.max_batch_samples = int(max_batch_samples)
@@ -139,6 +140,11 @@ class Server:
         if segment_iters is not None and int(segment_iters) < 1:
             raise ValueError("segment_iters must be at least 1")
         self.segment_iters = None if segment_iters is None else int(segment_iters)
+        # Segments pay off only while the device is contended: a launch is cut
+        # into segments when it takes the last idle stream or requests are
+        # still queued behind it; otherwise (light load) it runs the requests'
+        # remaining iterations at once.  segment_always cuts every launch.
+        self.segment_always = bool(segment_always)
 
     def run(self, reqs: List[Request]) -> ServeStats:
         be = self.be
@@ -203,6 +209,10 @@ class Server:
                     take.append(r)
                     samples += r.n
                 seg = self.segment_iters
+                if seg is not None and not self.segment_always:
+                    contended = bool(admitted) or len(inflight) + 1 >= be.n_slots
+                    if not contended:
+                        seg = None
                 b = Batch(nb, take, slot, footprint=sum(r.footprint for r in take),
                           start=[r.progress for r in take],
                           count=[r.iters - r.progress if seg is None else min(seg, r.iters - r.progress)

@@ -143,7 +143,7 @@ def test_segments_let_a_short_request_overtake_a_long_one():
 def test_segments_keep_budget_and_order():
     be = SimBackend(n_slots=2, rate=2e9)
     reqs = make_requests(rate_hz=300.0, duration_s=1.0, seed=8, k_lo=12, k_hi=18, iters_lo=50, iters_hi=200)
-    srv = Server(be, budget_bytes=2**34, segment_iters=30)
+    srv = Server(be, budget_bytes=2**34, segment_iters=30, segment_always=True)
     st = srv.run(reqs)
     _check_common(reqs, st, srv)
     assert all(r.progress == r.iters for r in reqs)
@@ -151,3 +151,19 @@ def test_segments_keep_budget_and_order():
     # every launch runs at most 30 iterations of each request
     work = sum(r.n * r.iters for r in reqs)
     assert st.sample_iterations == work
+
+
+def test_segments_only_under_contention():
+    """By default a launch is cut into segments only while the device is
+    contended (it takes the last idle stream, or requests wait behind it).
+    Requests arriving far apart on a 4-stream device each run whole; the same
+    requests all queued at once on one stream run in segments."""
+    def reqs(spacing):
+        return [Request(rid=i, n=2**16, iters=100, f_br=0.01, a_low=1.0, a_high=2.0, seed=i, arrival=i * spacing)
+                for i in range(6)]
+    sparse = reqs(1.0)
+    st = Server(SimBackend(n_slots=4, rate=1e9), budget_bytes=2**36, segment_iters=25).run(sparse)
+    assert st.completed == 6 and all(r.segments == 1 for r in sparse)
+    dense = reqs(0.0)
+    st = Server(SimBackend(n_slots=1, rate=1e9), budget_bytes=2**36, segment_iters=25).run(dense)
+    assert st.completed == 6 and all(r.segments == 4 for r in dense)
