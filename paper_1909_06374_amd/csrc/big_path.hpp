@@ -181,6 +181,21 @@ AGN_DEV void col_fft(cplx<T>* buf, const cplx<T>* wr, int R, const FftPlan& plan
 template <typename T>
 AGN_DEV cplx<T> to_T(cplx<double> a) { return cmk((T)a.re, (T)a.im); }
 
+// One term of Eq. 4, log10(a / b), for a sample whose value changed from b to
+// a.  FP64: the exact ratio and log10.  FP32 form: the ratio of the values
+// rounded to float and the hardware log2 (a few 2^-24 relative in the ratio,
+// so about 1e-7 absolute in the term), scaled to log10; the sum over the
+// terms stays in FP64.
+template <typename T>
+AGN_DEV double eq4_term(double a, double b) {
+    if constexpr (sizeof(T) == 4) {
+        const float r = (float)a / (float)b;
+        return (double)__log2f(r) * 0.30102999566398119521;  // log10(2)
+    } else {
+        return log10(a / b);
+    }
+}
+
 // grid: (M / R / C, curves), block: P.nthreads (E = R * C / nthreads, nthreads a
 // multiple of C and at most 1024, so each thread stays in one column
 // c = tid mod C).
@@ -237,8 +252,8 @@ __global__ __launch_bounds__(1024) void k_fft_pass(const BigCurve* __restrict__ 
                 const cplx<double> a = gload(xc + m);  // x[2m], x[2m + 1]
                 if (P.with_delta) {
                     const cplx<double> b = gload(xp + m);
-                    if (a.re != b.re) { const double l = log10(a.re / b.re); acc += l * l; ++chg; }
-                    if (a.im != b.im) { const double l = log10(a.im / b.im); acc += l * l; ++chg; }
+                    if (a.re != b.re) { const double l = eq4_term<T>(a.re, b.re); acc += l * l; ++chg; }
+                    if (a.im != b.im) { const double l = eq4_term<T>(a.im, b.im); acc += l * l; ++chg; }
                 }
                 v[u] = cmk((T)a.re, (T)a.im);
             } else {

@@ -17,7 +17,7 @@ import pytest
 import oracle
 from paper_1909_06374_amd import synth
 
-from test_gpu_parity import PSD, delta_close, run_iterate
+from test_gpu_parity import DELTA_RTOL_FP32_HBM, PSD, delta_close, run_iterate
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -87,7 +87,8 @@ def test_zero_target_moduli_identity(gpu_ctx, n, prec):
     assert doneg == 3
     assert np.array_equal(rr, ident) and np.array_equal(rg, ident)
     assert np.array_equal(xg, np.sort(x0)) and np.array_equal(xr, xg)
-    assert delta_close(dg, dr) and dg[1] == 0 and dg[2] == 0
+    rtol = DELTA_RTOL_FP32_HBM if (prec == 1 and n > 16384) else 1e-12
+    assert delta_close(dg, dr, rtol) and dg[1] == 0 and dg[2] == 0
 
 
 @pytest.mark.parametrize("prec", [0, 1])
