@@ -392,7 +392,11 @@ int agn_ctx_set_lookback_polls(agn_ctx* ctx, int32_t polls);
 int agn_ctx_kernel_time(agn_ctx* ctx, const char* name, double* total_ms, int64_t* launches,
                         int reset);
 
-/* Comma-separated kernel names the library times. */
+/* Comma-separated kernel names the library times.  On the multi-pass path:
+ * fft_pass and fft_mid (the transform passes), sort_hist (the digit count of
+ * a sort, one launch per sort), sort_scan (the digit starts), sort_scatter
+ * (one launch per 8-bit pass), delta (Eq. 4 reductions), big_prep (spectrum
+ * moduli and the one-time sort of the draw), big_output. */
 const char* agn_ctx_kernel_names(void);
 
 /* ---- test-only exports (same conventions) ------------------------------- */
