@@ -395,8 +395,8 @@ int agn_ctx_kernel_time(agn_ctx* ctx, const char* name, double* total_ms, int64_
 /* Comma-separated kernel names the library times.  On the multi-pass path:
  * fft_pass and fft_mid (the transform passes), sort_hist (the digit count of
  * a sort, one launch per sort), sort_scan (the digit starts), sort_scatter
- * (one launch per 8-bit pass), delta (Eq. 4 reductions), big_prep (spectrum
- * moduli and the one-time sort of the draw), big_output. */
+ * (one launch per 8-bit pass), delta (Eq. 4 reductions), big_prep (the
+ * draw's keys and their one-time sort), big_output. */
 const char* agn_ctx_kernel_names(void);
 
 /* ---- test-only exports (same conventions) ------------------------------- */
