@@ -555,27 +555,38 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sort_clear(const BigCurve* __re
 // Digit totals of every pass of one sort, from its input keys (a pass only
 // permutes the keys, so each pass's digit counts are those of the input).
 // grid: (workgroups per curve, curves), block 256; workgroup x takes tiles
-// x, x + gridDim.x, ...  Each wave counts into COPIES LDS histograms per pass,
-// lane l into copy l mod COPIES, rows padded to 257 words so that equal
-// digits of different copies fall in different banks (the exponent byte is
-// dominated by a few values); totals go to dcount by one global atomic add
-// per (pass, digit) and workgroup.
+// x, x + gridDim.x, ...  Each wave counts into its own LDS histogram per
+// pass; for the exponent bytes (the top byte of 32-bit keys, the top two of
+// 64-bit keys), where a few digits dominate, into CT copies, lane l into copy
+// l mod CT, rows padded to 257 words, so that fewer lanes of one atomic hit
+// the same counter.  Totals go to dcount by one global atomic add per
+// (pass, digit) and workgroup.
+template <typename K>
+struct count_layout {
+    static constexpr int NP = (int)sizeof(K);
+    static constexpr int NTOP = NP == 4 ? 1 : 2;  // exponent bytes
+    static constexpr int CT = NP == 4 ? 16 : 8;   // their copies per wave
+    static constexpr int WAVES = BIG_THREADS / 64;
+    static constexpr int NLO = NP - NTOP;
+    static constexpr int WORDS = (NLO * WAVES + NTOP * WAVES * CT) * 257;
+    static constexpr int off(int p) {
+        return p < NLO ? p * WAVES * 257 : (NLO * WAVES + (p - NLO) * WAVES * CT) * 257;
+    }
+};
+
 template <typename K, int TILE>
 __global__ __launch_bounds__(BIG_THREADS) void k_sort_count(const BigCurve* __restrict__ cv, int src_sel,
                                                             int64_t ntiles) {
-    constexpr int NP = (int)sizeof(K);
-    constexpr int COPIES = 16 / NP;
-    constexpr int WAVES = BIG_THREADS / 64;
-    constexpr int ROWS = WAVES * COPIES;
+    typedef count_layout<K> CL;
     constexpr int IPT = TILE / BIG_THREADS;
-    __shared__ uint32_t h[NP * ROWS * 257];
+    __shared__ uint32_t h[CL::WORDS];
     const BigCurve& d = cv[blockIdx.y];
     if (d.state[1] == 0) return;
     const int tid = threadIdx.x, wave = tid >> 6;
-    for (int i = tid; i < NP * ROWS * 257; i += BIG_THREADS) h[i] = 0u;
+    for (int i = tid; i < CL::WORDS; i += BIG_THREADS) h[i] = 0u;
     __syncthreads();
-    const K* keys = (const K*)(src_sel ? d.sortB : d.sortA);
-    uint32_t* mine = h + (wave * COPIES + (tid % COPIES)) * 257;
+    const gmem<K>* keys = as_global((const K*)(src_sel ? d.sortB : d.sortA));
+    const int row_lo = wave * 257, row_hi = (wave * CL::CT + (tid % CL::CT)) * 257;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t base = t * TILE + tid;
         K k[IPT];
@@ -584,14 +595,18 @@ __global__ __launch_bounds__(BIG_THREADS) void k_sort_count(const BigCurve* __re
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
 #pragma unroll
-            for (int p = 0; p < NP; ++p) atomicAdd(&mine[p * ROWS * 257 + ((uint32_t)(k[i] >> (8 * p)) & 255u)], 1u);
+            for (int p = 0; p < CL::NP; ++p) {
+                const int row = p < CL::NLO ? row_lo : row_hi;
+                atomicAdd(&h[CL::off(p) + row + ((uint32_t)(k[i] >> (8 * p)) & 255u)], 1u);
+            }
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
+    for (int p = 0; p < CL::NP; ++p) {
+        const int rows = p < CL::NLO ? CL::WAVES : CL::WAVES * CL::CT;
         uint32_t c = 0;
-        for (int r = 0; r < ROWS; ++r) c += h[(p * ROWS + r) * 257 + tid];
+        for (int r = 0; r < rows; ++r) c += h[CL::off(p) + r * 257 + tid];
         if (c) atomicAdd(&d.dcount[p * 256 + tid], c);
     }
 }
