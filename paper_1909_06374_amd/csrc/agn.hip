@@ -617,11 +617,37 @@ static int fft_cols(int64_t M, int R, int64_t Ns, agn_precision prec, int cap = 
 // on the same tiles (-2% per pass at 2^26).
 static constexpr int FFT_E = 8;
 
+// log2 R for the power-of-two radices that have a compile-time transform
+// (k_fft_pass / k_fft_mid with LR > 0: the same arithmetic with constant
+// indexing), 0 for the others (the factor 3 of 3 * 2^k lengths).
+static int fft_lr(int R) {
+    for (int lr = 4; lr <= 9; ++lr)
+        if (R == (1 << lr)) return lr;
+    return 0;
+}
+
+template <typename T, bool INV, int C, int LR>
+static void launch_fft_pass_lr(const BigCurve* d, int nc, const FftPass& P, const TwTable& tb, size_t lds,
+                               hipStream_t st) {
+    dim3 grid((unsigned)(P.M / P.R / C), (unsigned)nc);
+    hipLaunchKernelGGL((k_fft_pass<T, FFT_E, INV, C, LR>), grid, dim3(P.nthreads), lds, st, d, P, tb);
+}
+
 template <typename T, bool INV, int C>
 static void launch_fft_pass_c(const BigCurve* d, int nc, const FftPass& P, const TwTable& tb, size_t lds,
                               hipStream_t st) {
-    dim3 grid((unsigned)(P.M / P.R / C), (unsigned)nc);
-    hipLaunchKernelGGL((k_fft_pass<T, FFT_E, INV, C>), grid, dim3(P.nthreads), lds, st, d, P, tb);
+    // fft_cols keeps R * C within the tile, so only those shapes are instantiated
+    constexpr int TILE = sizeof(T) == 4 ? 8192 : 4096;
+    switch (fft_lr(P.R)) {
+        case 4: if constexpr (16 * C <= TILE) { launch_fft_pass_lr<T, INV, C, 4>(d, nc, P, tb, lds, st); return; } break;
+        case 5: if constexpr (32 * C <= TILE) { launch_fft_pass_lr<T, INV, C, 5>(d, nc, P, tb, lds, st); return; } break;
+        case 6: if constexpr (64 * C <= TILE) { launch_fft_pass_lr<T, INV, C, 6>(d, nc, P, tb, lds, st); return; } break;
+        case 7: if constexpr (128 * C <= TILE) { launch_fft_pass_lr<T, INV, C, 7>(d, nc, P, tb, lds, st); return; } break;
+        case 8: if constexpr (256 * C <= TILE) { launch_fft_pass_lr<T, INV, C, 8>(d, nc, P, tb, lds, st); return; } break;
+        case 9: if constexpr (512 * C <= TILE) { launch_fft_pass_lr<T, INV, C, 9>(d, nc, P, tb, lds, st); return; } break;
+        default: break;
+    }
+    launch_fft_pass_lr<T, INV, C, 0>(d, nc, P, tb, lds, st);
 }
 
 template <typename T>
@@ -676,7 +702,25 @@ static void launch_fft_mid(agn_ctx* ctx, const BigCurve* d, int nc, const MidPas
                        16 + (size_t)P.R * sizeof(cplx<T>);
     const dim3 grid((unsigned)(P.M / P.R / C2), (unsigned)nc);
     ProfScope ps(ctx, "fft_mid", st);
-    hipLaunchKernelGGL((k_fft_mid<T, MID_E, 8, MODE>), grid, dim3(P.nthreads), lds, st, d, P, tb);
+    // the iteration's mode takes the compile-time transform for R = 2^6 .. 2^9
+    // (R * 16 columns within the tile); the test exports keep the general one
+    constexpr int TILE = sizeof(T) == 4 ? 8192 : 4096;
+    if constexpr (MODE == MID_REPLACE) {
+        switch (fft_lr(P.R)) {
+            case 6: { hipLaunchKernelGGL((k_fft_mid<T, MID_E, 8, MODE, 6>), grid, dim3(P.nthreads), lds, st, d, P, tb); return; }
+            case 7: { hipLaunchKernelGGL((k_fft_mid<T, MID_E, 8, MODE, 7>), grid, dim3(P.nthreads), lds, st, d, P, tb); return; }
+            case 8:
+                if constexpr (256 * 16 <= TILE)
+                    { hipLaunchKernelGGL((k_fft_mid<T, MID_E, 8, MODE, 8>), grid, dim3(P.nthreads), lds, st, d, P, tb); return; }
+                break;
+            case 9:
+                if constexpr (512 * 16 <= TILE)
+                    { hipLaunchKernelGGL((k_fft_mid<T, MID_E, 8, MODE, 9>), grid, dim3(P.nthreads), lds, st, d, P, tb); return; }
+                break;
+            default: break;
+        }
+    }
+    hipLaunchKernelGGL((k_fft_mid<T, MID_E, 8, MODE, 0>), grid, dim3(P.nthreads), lds, st, d, P, tb);
 }
 
 // One LSD sort of the keys in region src0, sizeof(K) passes of 8-bit digits:

@@ -178,6 +178,89 @@ AGN_DEV void col_fft(cplx<T>* buf, const cplx<T>* wr, int R, const FftPlan& plan
     }
 }
 
+// ---- The same in-LDS transform for R = 2^LR known at compile time ----
+// Power-of-two radices are the common case; with R, the thread count (R C / 8,
+// eight values per thread) and the sub-radices fixed, every butterfly index is
+// a shift or a mask and the eight LDS offsets of a butterfly are immediates.
+// Each butterfly does the arithmetic of col_pass (same elements, same
+// sub-twiddles, same dftR); the two can differ in the last bit only where the
+// compiler fuses a different product of a butterfly into a multiply-add.
+//
+// Padded LDS index of (row, column): tpad(row C + c) = row_off(row) + col_off(c).
+// With C a multiple of the padding period (32 FP32 values, 16 FP64) both parts
+// are linear; for FP32 and C = 16 a pad word follows every two rows, so
+// row_off(row) = 16 row + row / 2, which is additive over a step of k rows
+// from an even row, or of an even k from any row.
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
+
+template <typename T, int C>
+struct lds_lay {
+    static constexpr int SH = sizeof(T) == 4 ? 5 : 4;
+    static constexpr bool WIDE = C >= (1 << SH);
+    static_assert(WIDE || 2 * C == (1 << SH), "column count without a linear padded layout");
+    AGN_DEV static uint32_t row_off(uint32_t r) { return WIDE ? r * (C + (C >> SH)) : r * C + (r >> 1); }
+    AGN_DEV static uint32_t col_off(uint32_t c) { return WIDE ? c + (c >> SH) : c; }
+    static constexpr uint32_t step(uint32_t k) { return WIDE ? k * (C + (C >> SH)) : k * C + (k >> 1); }
+};
+
+template <typename T, int RR, bool INV, int C, int R, int NS>
+AGN_DEV void col_pass_fx(cplx<T>* buf, const cplx<T>* wr, uint32_t tid) {
+    typedef lds_lay<T, C> L;
+    constexpr int RB = R / RR;         // butterflies per column
+    constexpr int NT = R * C / 8;      // threads
+    constexpr int BPT = 8 / RR;        // butterflies per thread
+    constexpr int LC = ilog2c(C);
+    static_assert(RB % 2 == 0 && (NS == 1 || NS % 2 == 0), "row steps must be even");
+    cplx<T> v[BPT][RR];
+    cplx<T> w[BPT][RR];
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+        const uint32_t q = tid + b * NT;
+        const uint32_t j = q >> LC, c = q & (C - 1);
+        const uint32_t base = L::row_off(j) + L::col_off(c);
+#pragma unroll
+        for (int r = 0; r < RR; ++r) v[b][r] = buf[base + L::step(r * RB)];
+        if constexpr (NS > 1) {
+            constexpr uint32_t STEP = R / (NS * RR);
+            const uint32_t t = (j & (NS - 1)) * STEP;
+#pragma unroll
+            for (int r = 1; r < RR; ++r) {
+                const cplx<T> tw = wr[t * r];
+                w[b][r] = INV ? cconj(tw) : tw;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+        const uint32_t q = tid + b * NT;
+        const uint32_t j = q >> LC, c = q & (C - 1);
+        const uint32_t jm = j & (NS - 1);
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < RR; ++r) v[b][r] = cmul(v[b][r], w[b][r]);
+        }
+        dftR<T, RR, INV>(v[b]);
+        // first sub-pass: rows j RR + r from the even row j RR; later: rows d + r NS, NS even
+        const uint32_t base = L::row_off((j - jm) * RR + jm) + L::col_off(c);
+#pragma unroll
+        for (int r = 0; r < RR; ++r) buf[base + L::step(NS == 1 ? r : r * NS)] = v[b][r];
+    }
+    __syncthreads();
+}
+
+// Sub-radices in make_plan's order for a power of two: 8 while 8 divides what
+// is left, then 4 or 2.
+template <typename T, bool INV, int C, int R, int NS = 1>
+AGN_DEV void col_fft_fx(cplx<T>* buf, const cplx<T>* wr, uint32_t tid) {
+    if constexpr (NS < R) {
+        constexpr int LEFT = R / NS;
+        constexpr int RR = LEFT % 8 == 0 ? 8 : (LEFT % 4 == 0 ? 4 : 2);
+        col_pass_fx<T, RR, INV, C, R, NS>(buf, wr, tid);
+        col_fft_fx<T, INV, C, R, NS * RR>(buf, wr, tid);
+    }
+}
+
 template <typename T>
 AGN_DEV cplx<T> to_T(cplx<double> a) { return cmk((T)a.re, (T)a.im); }
 
@@ -199,14 +282,19 @@ AGN_DEV double eq4_term(double a, double b) {
 // grid: (M / R / C, curves), block: P.nthreads (E = R * C / nthreads, nthreads a
 // multiple of C and at most 1024, so each thread stays in one column
 // c = tid mod C).
-template <typename T, int E, bool INV, int C>
+template <typename T, int E, bool INV, int C, int LR>
 __global__ __launch_bounds__(1024) void k_fft_pass(const BigCurve* __restrict__ cv, FftPass P, TwTable tb) {
     typedef typename key_of<T>::type K;
+    typedef lds_lay<T, C> L;
+    // LR > 0: R = 2^LR and E = 8 fixed at compile time (col_fft_fx); 0: any R
+    constexpr bool FX = LR > 0;
+    static_assert(!FX || E == 8, "the compile-time transform takes 8 values per thread");
     extern __shared__ __align__(16) unsigned char smem[];
     const BigCurve& d = cv[blockIdx.y];
     if (d.state[1] == 0) return;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int R = P.R;
+    const int tid = threadIdx.x;
+    const int R = FX ? (1 << LR) : P.R;
+    const int nt = FX ? (1 << LR) * C / E : (int)blockDim.x;
     const int64_t M = P.M, N = 2 * M, MR = M / R, Ns = P.Ns;
     const int64_t j0 = (int64_t)blockIdx.x * C;
     // Ns is 1 or a multiple of C, so (j0 + c) mod Ns = j0m + c.
@@ -231,6 +319,8 @@ __global__ __launch_bounds__(1024) void k_fft_pass(const BigCurve* __restrict__ 
     double acc = 0.0;
     uint32_t chg = 0;
     const int c_t = tid % C, r_t = tid / C, dr = nt / C;
+    // (compile-time form: element e's padded LDS index from the thread's own)
+    const uint32_t e_lds = L::row_off((uint32_t)r_t) + L::col_off((uint32_t)c_t);
     const bool twid = Ns > 1;
     cplx<double> wk = cmk(1.0, 0.0), wstep = cmk(1.0, 0.0);
     if (twid) {
@@ -241,13 +331,13 @@ __global__ __launch_bounds__(1024) void k_fft_pass(const BigCurve* __restrict__ 
     // E elements per thread, loaded in two unrolled halves so that the data
     // loads of a half are all in flight together.
     static_assert(E % 2 == 0, "E must be even");
+    const int64_t m_t = j0 + c_t + (int64_t)r_t * MR;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         cplx<T> v[E / 2];
 #pragma unroll
         for (int u = 0; u < E / 2; ++u) {
-            const int r = r_t + (h * (E / 2) + u) * dr;
-            const int64_t m = j0 + c_t + (int64_t)r * MR;
+            const int64_t m = m_t + (int64_t)((h * (E / 2) + u) * dr) * MR;
             if (P.in_mode == 1) {
                 const cplx<double> a = gload(xc + m);  // x[2m], x[2m + 1]
                 if (P.with_delta) {
@@ -262,7 +352,7 @@ __global__ __launch_bounds__(1024) void k_fft_pass(const BigCurve* __restrict__ 
         }
 #pragma unroll
         for (int u = 0; u < E / 2; ++u) {
-            const int e = tid + (h * (E / 2) + u) * nt;
+            const int k = h * (E / 2) + u;
             cplx<T> x = v[u];
             if (twid) {
                 cplx<T> w = to_T<T>(wk);
@@ -270,7 +360,8 @@ __global__ __launch_bounds__(1024) void k_fft_pass(const BigCurve* __restrict__ 
                 x = cmul(x, w);
                 wk = cmul(wk, wstep);
             }
-            buf[tpad<T>(e)] = x;
+            if constexpr (FX) buf[e_lds + L::step(k * ((1 << LR) / 8))] = x;  // row r_t + k R / 8
+            else buf[tpad<T>(tid + k * nt)] = x;
         }
     }
     if (P.in_mode == 1 && P.with_delta) {
@@ -295,28 +386,47 @@ __global__ __launch_bounds__(1024) void k_fft_pass(const BigCurve* __restrict__ 
     // the first pass of an iteration, so every delta has one summation order
     if (P.out_mode == 2) return;
     __syncthreads();
-    col_fft<T, E, INV, C>(buf, wr, R, P.sub, tid, nt);
+    if constexpr (FX) col_fft_fx<T, INV, C, (1 << LR)>(buf, wr, (uint32_t)tid);
+    else col_fft<T, E, INV, C>(buf, wr, R, P.sub, tid, nt);
 
     // Write outputs: butterfly j = j0 + c, output q goes to (j - jm) R + jm + q Ns.
-    if (P.out_mode == 1) {
-        gmem<K>* keys = as_global((K*)(P.dst_sel ? d.sortB : d.sortA));
-        for (int e = tid; e < R * C; e += nt) {
-            int q, c;
-            if (Ns == 1) { c = e / R; q = e % R; } else { q = e / C; c = e % C; }
-            const int64_t jm = (Ns > 1) ? j0m + c : 0;
-            const int64_t m = (j0 + c - jm) * R + jm + (int64_t)q * Ns;
-            const cplx<T> v = buf[tpad<T>(q * C + c)];
-            keys[2 * m] = ord_key(v.re);
-            keys[2 * m + 1] = ord_key(v.im);
+    gmem<typename vec2_of<K>::type>* keys = as_global((typename vec2_of<K>::type*)(P.dst_sel ? d.sortB : d.sortA));
+    gmem<cplx<T>>* dst = as_global((cplx<T>*)(P.dst_sel ? d.sortB : d.sortA));
+    auto put = [&](int64_t m, const cplx<T>& v) {
+        if (P.out_mode == 1) {
+            typename vec2_of<K>::type kv;
+            kv.x = ord_key(v.re);
+            kv.y = ord_key(v.im);
+            keys[m] = kv;  // keys 2m, 2m + 1
+        } else {
+            gstore(dst + m, v);
+        }
+    };
+    if constexpr (FX) {
+        constexpr uint32_t RF = 1u << LR;
+        if (Ns == 1) {
+            // e = tid + k nt: column c = tid / R + k C / 8, row q = tid mod R;
+            // column c's outputs are z[(j0 + c) R + q]
+            const uint32_t q = (uint32_t)tid & (RF - 1), c1 = (uint32_t)tid >> LR;
+            const int64_t mb = (j0 + c1) * (int64_t)RF + q;
+            const uint32_t lq = L::row_off(q);
+#pragma unroll
+            for (int k = 0; k < E; ++k)
+                put(mb + (int64_t)k * (C / 8) * RF, buf[lq + L::col_off(c1 + k * (C / 8))]);
+        } else {
+            // e = tid + k nt: row q = r_t + k R / 8, column c_t
+            const int64_t mb = (j0 - j0m) * (int64_t)RF + j0m + c_t + (int64_t)r_t * Ns;
+#pragma unroll
+            for (int k = 0; k < E; ++k)
+                put(mb + (int64_t)k * (RF / 8) * Ns, buf[e_lds + L::step(k * (RF / 8))]);
         }
     } else {
-        gmem<cplx<T>>* dst = as_global((cplx<T>*)(P.dst_sel ? d.sortB : d.sortA));
         for (int e = tid; e < R * C; e += nt) {
             int q, c;
             if (Ns == 1) { c = e / R; q = e % R; } else { q = e / C; c = e % C; }
             const int64_t jm = (Ns > 1) ? j0m + c : 0;
             const int64_t m = (j0 + c - jm) * R + jm + (int64_t)q * Ns;
-            gstore(dst + m, buf[tpad<T>(q * C + c)]);
+            put(m, buf[tpad<T>(q * C + c)]);
         }
     }
 }
@@ -367,14 +477,19 @@ AGN_DEV int64_t xcd_order(int64_t x, int64_t rows) {
 // its 8 target moduli 32 bytes, so two and four neighbouring blocks share
 // each cache line; numbered this way, they run on one XCD at about the same
 // time and find the line in its L2 instead of each fetching it.
-template <typename T, int E, int C, int MODE>
+template <typename T, int E, int C, int MODE, int LR>
 __global__ __launch_bounds__(1024) void k_fft_mid(const BigCurve* __restrict__ cv, MidPass P, TwTable tb) {
     constexpr int C2 = 2 * C;
+    typedef lds_lay<T, C2> L;
+    // LR > 0: R = 2^LR and E = 8 fixed at compile time (col_fft_fx); 0: any R
+    constexpr bool FX = LR > 0;
+    static_assert(!FX || E == 8, "the compile-time transform takes 8 values per thread");
     extern __shared__ __align__(16) unsigned char smem[];
     const BigCurve& d = cv[blockIdx.y];
     if (d.state[1] == 0) return;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int R = P.R;
+    const int tid = threadIdx.x;
+    const int R = FX ? (1 << LR) : P.R;
+    const int nt = FX ? (1 << LR) * C2 / E : (int)blockDim.x;
     const int64_t M = P.M, N = 2 * M, MR = M / R;
     const int64_t j0 = xcd_order(blockIdx.x, gridDim.x) * C;
     cplx<T>* buf = (cplx<T>*)smem;
@@ -392,6 +507,7 @@ __global__ __launch_bounds__(1024) void k_fft_mid(const BigCurve* __restrict__ c
         // twiddle W_M^{j r} = W_N^{2 j r}, formed in FP64 as in k_fft_pass.
         const gmem<cplx<T>>* src = as_global((const cplx<T>*)(P.src_sel ? d.sortB : d.sortA));
         const int c_t = tid % C2, r_t = tid / C2, dr = nt / C2;
+        const uint32_t e_lds = L::row_off((uint32_t)r_t) + L::col_off((uint32_t)c_t);
         const int64_t jc = col_of(c_t);
         cplx<double> wk = tw64(tb, 2 * jc * r_t);
         const cplx<double> wstep = tw64(tb, 2 * jc * dr);
@@ -406,13 +522,16 @@ __global__ __launch_bounds__(1024) void k_fft_mid(const BigCurve* __restrict__ c
             }
 #pragma unroll
             for (int u = 0; u < E / 2; ++u) {
-                const int e = tid + (h * (E / 2) + u) * nt;
-                buf[tpad<T>(e)] = cmul(v[u], to_T<T>(wk));
+                const int k = h * (E / 2) + u;
+                const cplx<T> x = cmul(v[u], to_T<T>(wk));
+                if constexpr (FX) buf[e_lds + L::step(k * ((1 << LR) / 8))] = x;  // row r_t + k R / 8
+                else buf[tpad<T>(tid + k * nt)] = x;
                 wk = cmul(wk, wstep);
             }
         }
         __syncthreads();
-        col_fft<T, E, false, C2>(buf, wr, R, P.sub, tid, nt);
+        if constexpr (FX) col_fft_fx<T, false, C2, (1 << LR)>(buf, wr, (uint32_t)tid);
+        else col_fft<T, E, false, C2>(buf, wr, R, P.sub, tid, nt);
     }
 
     // Hermitian pairs.  Item e < R C: primary element (q, s); block 0 adds
@@ -425,7 +544,7 @@ __global__ __launch_bounds__(1024) void k_fft_mid(const BigCurve* __restrict__ c
         int64_t ka;
         bool dc = false, self = false;
         if (e < R * C) {
-            const int sl = e % C, q = e / C;
+            const int sl = (int)((uint32_t)e % C), q = (int)((uint32_t)e / C);
             const int64_t j = j0 + sl, k = j + (int64_t)q * MR;
             if (j == 0) {
                 if (2 * q > R) continue;  // taken as the partner of row R - q
@@ -485,11 +604,24 @@ __global__ __launch_bounds__(1024) void k_fft_mid(const BigCurve* __restrict__ c
     __syncthreads();
     // The inverse transform's first pass: length-R DFTs of the columns (no
     // twiddles), column j's outputs to z[j R + q].
-    col_fft<T, E, true, C2>(buf, wr, R, P.sub, tid, nt);
     gmem<cplx<T>>* dst = as_global((cplx<T>*)(P.dst_sel ? d.sortB : d.sortA));
-    for (int e = tid; e < R * C2; e += nt) {
-        const int sl = e / R, q = e % R;
-        gstore(dst + col_of(sl) * R + q, buf[tpad<T>(q * C2 + sl)]);
+    if constexpr (FX) {
+        col_fft_fx<T, true, C2, (1 << LR)>(buf, wr, (uint32_t)tid);
+        // e = tid + k nt: slot tid / R + 2 k (nt = 2 R), row q = tid mod R
+        constexpr uint32_t RF = 1u << LR;
+        const uint32_t q = (uint32_t)tid & (RF - 1), s1 = (uint32_t)tid >> LR;
+        const uint32_t lq = L::row_off(q);
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const int sl = (int)(s1 + k * (C2 / E));
+            gstore(dst + col_of(sl) * (int64_t)RF + q, buf[lq + L::col_off((uint32_t)sl)]);
+        }
+    } else {
+        col_fft<T, E, true, C2>(buf, wr, R, P.sub, tid, nt);
+        for (int e = tid; e < R * C2; e += nt) {
+            const int sl = e / R, q = e % R;
+            gstore(dst + col_of(sl) * R + q, buf[tpad<T>(q * C2 + sl)]);
+        }
     }
 }
 
