@@ -44,6 +44,9 @@ template <typename K>
 struct scat_ipt {
     static constexpr int value = sizeof(K) == 4 ? 16 : 8;
 };
+// Keys per wave whose digit peer masks are formed together in the scatter's
+// ranking (it divides both key counts per thread).
+constexpr int RANK_GROUP = 4;
 // Larger sort tile for 32-bit keys (curves whose length it divides): digit
 // runs twice as long, 146 KB of LDS, one 1024-thread workgroup per CU.  Its
 // staging does not fit for 64-bit keys.  Exact either way; the batch-plan
@@ -829,26 +832,46 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
             val[i] = P.first ? (uint32_t)p : svals[p];
         }
     }
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     // LDS-typed, so that the counter traffic compiles to ds_ instructions
     // (a volatile generic pointer becomes coherent flat loads and stores)
     volatile __attribute__((address_space(3))) uint16_t* vc =
         (volatile __attribute__((address_space(3))) uint16_t*)wcnt[wave];
+    // Keys are ranked RANK_GROUP at a time: their peer masks first (independent
+    // chains the compiler can interleave), then the counter updates in key order.
 #pragma unroll
-    for (int i = 0; i < SCAT_IPT; ++i) {
-        const uint32_t dg = (uint32_t)(key[i] >> P.shift) & 255u;
-        uint64_t peers = ~0ull;
+    for (int i0 = 0; i0 < SCAT_IPT; i0 += RANK_GROUP) {
+        uint32_t plo[RANK_GROUP], phi[RANK_GROUP];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const uint64_t bal = __ballot((dg >> b) & 1u);
-            peers &= ((dg >> b) & 1u) ? bal : ~bal;
+        for (int g = 0; g < RANK_GROUP; ++g) {
+            const uint32_t dg = (uint32_t)(key[i0 + g] >> P.shift) & 255u;
+            // lanes whose digit differs from this lane's in some bit b: the
+            // ballot of bit b, XOR this lane's bit b spread over a word, ORed
+            // over the bits; peers = the lanes that differ in none
+            uint32_t dlo = 0u, dhi = 0u;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                // (opaque: the ballot then tests m itself instead of re-deriving the bit)
+                const uint32_t m = (uint32_t)opaque(__builtin_amdgcn_sbfe((int)dg, (unsigned)b, 1u));  // 0 or ~0
+                const uint64_t bal = __ballot(m != 0u);
+                // d | (bal ^ m) in one three-input bitwise operation (truth table
+                // indexed by d * 4 + bal * 2 + m)
+                dlo = __builtin_amdgcn_bitop3_b32(dlo, (uint32_t)bal, m, 0xF6);
+                dhi = __builtin_amdgcn_bitop3_b32(dhi, (uint32_t)(bal >> 32), m, 0xF6);
+            }
+            plo[g] = ~dlo;
+            phi[g] = ~dhi;
         }
-        const uint32_t below = (uint32_t)__popcll(peers & lt);
-        const uint32_t cur = vc[dg];
-        __builtin_amdgcn_wave_barrier();
-        if (below == 0) vc[dg] = (uint16_t)(cur + (uint32_t)__popcll(peers));
-        __builtin_amdgcn_wave_barrier();
-        loc[i] = cur + below;
+#pragma unroll
+        for (int g = 0; g < RANK_GROUP; ++g) {
+            const uint32_t dg = (uint32_t)(key[i0 + g] >> P.shift) & 255u;
+            // peers in lower lanes
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi[g], __builtin_amdgcn_mbcnt_lo(plo[g], 0u));
+            const uint32_t cur = vc[dg];
+            __builtin_amdgcn_wave_barrier();
+            if (below == 0) vc[dg] = (uint16_t)(cur + (uint32_t)__popc(plo[g]) + (uint32_t)__popc(phi[g]));
+            __builtin_amdgcn_wave_barrier();
+            loc[i0 + g] = cur + below;
+        }
     }
     __syncthreads();
     // per digit (threads 0..255): prefix over waves, tile total, scan over digits
