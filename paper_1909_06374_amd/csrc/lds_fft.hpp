@@ -226,12 +226,22 @@ AGN_DEV void lds_fft(cplx<T>* buf, int M, const FftPlan& plan, int tid, int nt, 
     lds_fft_passes<T, E, INV>(buf, M, plan, 0, plan.npass, 1, tid, nt, tw);
 }
 
-// Modulus replacement keeping the phase; zero modulus takes phase 0.
+// Modulus replacement keeping the phase; zero modulus takes phase 0.  FP64:
+// correctly rounded square root and divisions.  FP32 form: the hardware
+// reciprocal square root of the squared modulus (about 1 ulp) and two
+// products, instead of a square root and two divisions.
 template <typename T>
 AGN_DEV cplx<T> replace_modulus(cplx<T> X, T a) {
-    T mod = sqrt(X.re * X.re + X.im * X.im);
-    if (mod == (T)0) return cmk(a, (T)0);
-    return cmk(a * (X.re / mod), a * (X.im / mod));
+    if constexpr (sizeof(T) == 4) {
+        const float m2 = X.re * X.re + X.im * X.im;
+        if (m2 == 0.0f) return cmk(a, 0.0f);
+        const float s = a * __builtin_amdgcn_rsqf(m2);
+        return cmk(s * X.re, s * X.im);
+    } else {
+        T mod = sqrt(X.re * X.re + X.im * X.im);
+        if (mod == (T)0) return cmk(a, (T)0);
+        return cmk(a * (X.re / mod), a * (X.im / mod));
+    }
 }
 
 // Z holds FFT_M(z), z[m] = x[2m] + i x[2m+1].  For every Hermitian pair
