@@ -35,7 +35,8 @@ torch = pytest.importorskip("torch")
 
 LDS_POW2 = [2**a for a in range(1, 15)]
 LDS_THREE = [3 * 2**a for a in range(1, 13)]
-HBM = [8192, 16384, 32768, 65536, 2**17, 24576, 49152, 98304, 196608]
+# (2^19: the FP32 plan is 512 x 512, the largest radix of the passes)
+HBM = [8192, 16384, 32768, 65536, 2**17, 2**19, 24576, 49152, 98304, 196608]
 EPS = {0: 2.0**-53, 1: 2.0**-24}
 C_BAR = {0: 4.0, 1: 2.0}
 
