@@ -636,11 +636,11 @@ __global__ __launch_bounds__(1024) void k_fft_mid(const BigCurve* __restrict__ c
 // wave ranks its items in position order).
 enum { SORT_MODE_MOVE = 0, SORT_MODE_RANK = 1, SORT_MODE_PREP = 2 };
 constexpr int SORT_MAX_PASSES = 8;
-// Between passes, 32-bit keys travel with their sample index as one 8-byte
-// record (key << 32 | index): one load and one store per key, and a digit
-// run is one contiguous run of records rather than one run in each of two
-// arrays.  64-bit keys keep separate key and index arrays (a 12-byte record
-// would straddle lines).  The first pass reads bare keys (index implicit).
+// Between passes, keys travel with their sample index as one record: 8 bytes
+// (key << 32 | index) for 32-bit keys, 12 bytes (key low word, key high word,
+// index; 4-byte aligned) for 64-bit keys, so that a digit run is one
+// contiguous run of records rather than one run in each of two arrays.  The
+// first pass reads bare keys (index implicit).
 template <typename K> constexpr bool SORT_AOS = sizeof(K) == 4;
 
 struct SortPass {
@@ -811,12 +811,18 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
     const int64_t base = tile * TILE + (int64_t)wave * 64 * SCAT_IPT;
     const unsigned char* srcb = P.src_sel ? d.sortB : d.sortA;
     const gmem<K>* skeys = as_global((const K*)srcb);
-    const gmem<uint32_t>* svals = as_global((const uint32_t*)(srcb + (size_t)n * sizeof(K)));
 
     K key[SCAT_IPT];
     uint32_t val[SCAT_IPT];
     uint32_t loc[SCAT_IPT];
-    if (SORT_AOS<K> && !P.first) {
+    if (P.first) {
+#pragma unroll
+        for (int i = 0; i < SCAT_IPT; ++i) {
+            const int64_t p = base + i * 64 + lane;
+            key[i] = skeys[p];
+            val[i] = (uint32_t)p;
+        }
+    } else if constexpr (SORT_AOS<K>) {
         const gmem<uint64_t>* srec = as_global((const uint64_t*)srcb);
 #pragma unroll
         for (int i = 0; i < SCAT_IPT; ++i) {
@@ -825,11 +831,13 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
             val[i] = (uint32_t)r;
         }
     } else {
+        // 12-byte records: key low word, key high word, index
+        const gmem<uint32_t>* sw = as_global((const uint32_t*)srcb);
 #pragma unroll
         for (int i = 0; i < SCAT_IPT; ++i) {
-            const int64_t p = base + i * 64 + lane;
-            key[i] = skeys[p];
-            val[i] = P.first ? (uint32_t)p : svals[p];
+            const int64_t p = 3 * (base + i * 64 + lane);
+            key[i] = ((uint64_t)sw[p + 1] << 32) | sw[p];
+            val[i] = sw[p + 2];
         }
     }
     // LDS-typed, so that the counter traffic compiles to ds_ instructions
@@ -938,9 +946,8 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
     }
     __syncthreads();
     unsigned char* dstb = P.src_sel ? d.sortA : d.sortB;
-    gmem<K>* dkeys = as_global((K*)dstb);
-    gmem<uint32_t>* dvals = as_global((uint32_t*)(dstb + (size_t)n * sizeof(K)));
     gmem<uint64_t>* drec = as_global((uint64_t*)dstb);
+    gmem<uint32_t>* dw = as_global((uint32_t*)dstb);
     gmem<uint32_t>* rnk = as_global(P.rank_sel ? d.rankB : d.rankA);
     gmem<double>* xn = as_global(P.rank_sel ? d.X1 : d.X0);
     gmem<double>* s64 = as_global(d.s64);
@@ -956,8 +963,9 @@ __global__ __launch_bounds__(TILE / scat_ipt<K>::value) void k_sort_scatter(cons
             if constexpr (SORT_AOS<K>) {
                 drec[dest] = ((uint64_t)k << 32) | v;
             } else {
-                dkeys[dest] = k;
-                dvals[dest] = v;
+                dw[3 * (size_t)dest] = (uint32_t)k;
+                dw[3 * (size_t)dest + 1] = (uint32_t)((uint64_t)k >> 32);
+                dw[3 * (size_t)dest + 2] = v;
             }
         } else if (v < (uint32_t)n) {  // (always, unless a look-back wait gave up in an earlier pass)
             if (P.mode == SORT_MODE_RANK) {
