@@ -221,7 +221,10 @@ int agn_lc_generate_batch(agn_ctx* ctx, int32_t n_curves, const int64_t* n,
  *              write x_out.  Neither choice changes any arithmetic: chains
  *              only reorder independent curves, and the sort is exact.
  *              AGN_PLAN_LARGE_SORT_TILE: use the 16384-key sort tile
- *              without tuning (not with AGN_PLAN_AUTOTUNE).
+ *              for every length it divides, without tuning (not with
+ *              AGN_PLAN_AUTOTUNE).  Without either flag the tile is chosen
+ *              by length: 16384 keys for FP32 multi-pass curves of at least
+ *              2^20 samples that it divides, 8192 otherwise.
  *              AGN_PLAN_NARROW_FFT: 16 butterflies per multi-pass FFT
  *              workgroup instead of up to 64, without tuning.  With
  *              AGN_PLAN_AUTOTUNE this width (64, 32 or 16) is also tuned,
@@ -254,8 +257,9 @@ int agn_batch_plan_launch(agn_batch_plan* plan, void* stream);
  * which counts once. */
 int agn_batch_plan_info(const agn_batch_plan* plan, int32_t* branches, int32_t* groups, int32_t* uses_graph);
 /* The tuned (or requested) choices: chain count, sort tile (8192 or 16384;
- * 16384 applies to FP32 multi-pass curves whose length it divides) and the
- * most butterflies per multi-pass FFT workgroup (64, 32 or 16).  Any output
+ * 16384 applies to FP32 multi-pass curves whose length it divides; 0: chosen
+ * by length, as described for AGN_PLAN_LARGE_SORT_TILE) and the most
+ * butterflies per multi-pass FFT workgroup (64, 32 or 16).  Any output
  * pointer may be NULL. */
 int agn_batch_plan_tuning(const agn_batch_plan* plan, int32_t* branches, int32_t* sort_tile,
                           int32_t* fft_cols);

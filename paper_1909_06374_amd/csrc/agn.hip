@@ -763,10 +763,18 @@ static void run_sort_t(agn_ctx* ctx, const BigCurve* d, int nc, int64_t n, int s
     }
 }
 
-// Sort tile actually used for keys K on a curve of length n (a multiple of BIG_TILE).
+// Sort tile actually used for keys K on a curve of length n (a multiple of
+// BIG_TILE).  want = SORT_TILE_AUTO chooses by length: the 16384-key tile for
+// 32-bit keys of curves of at least 2^20 samples that it divides (its digit
+// runs are twice as long; at 4 x 2^26 the scatter takes 1.94 ms per pass
+// against 2.00 ms), else 8192.
+constexpr int SORT_TILE_AUTO = 0;
+constexpr int64_t SORT_TILE_AUTO_MIN_N = int64_t(1) << 20;
 template <typename K>
 static int sort_tile_for(int64_t n, int want) {
-    return (sizeof(K) == 4 && want == SORT_TILE_BIG && n % SORT_TILE_BIG == 0) ? SORT_TILE_BIG : BIG_TILE;
+    if (sizeof(K) != 4 || n % SORT_TILE_BIG != 0) return BIG_TILE;
+    if (want == SORT_TILE_AUTO) return n >= SORT_TILE_AUTO_MIN_N ? SORT_TILE_BIG : BIG_TILE;
+    return want == SORT_TILE_BIG ? SORT_TILE_BIG : BIG_TILE;
 }
 
 template <typename K>
@@ -934,7 +942,8 @@ struct agn_batch_plan {
     std::vector<BigGroup> big;
     std::vector<double> lds_cost, big_cost;  // relative run time of each group
     int branches = 1;                         // concurrent launch chains
-    int sort_tile = BIG_TILE;                 // requested tile of 32-bit-key sorts (multi-pass curves)
+    int sort_tile = SORT_TILE_AUTO;           // requested tile of 32-bit-key sorts (multi-pass curves;
+                                              // SORT_TILE_AUTO: by length)
     int fft_cap = FFT_COLS_MAX;               // most butterflies per multi-pass FFT workgroup
     int look_polls = LOOK_SPIN_MAX;           // look-back wait limit (the context's, at plan build)
     int flags = 0;
@@ -1579,7 +1588,7 @@ extern "C" int agn_batch_plan_create(agn_ctx* ctx, int32_t n_curves, const int64
     pl->flags = flags;
     if ((rc = build_plan(ctx, rq, tol, prec, ws, ws_bytes, st, *pl))) { destroy_plan_resources(*pl); return rc; }
     int nb = branches > 0 ? branches : 1;
-    int tile = (flags & AGN_PLAN_LARGE_SORT_TILE) ? SORT_TILE_BIG : BIG_TILE;
+    int tile = (flags & AGN_PLAN_LARGE_SORT_TILE) ? SORT_TILE_BIG : SORT_TILE_AUTO;
     int cap = (flags & AGN_PLAN_NARROW_FFT) ? FFT_COLS_MIN : FFT_COLS_MAX;
     if ((flags & AGN_PLAN_AUTOTUNE) && !rq.empty()) {
         const std::string sig = plan_signature(*pl);
